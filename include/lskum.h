@@ -1,0 +1,178 @@
+/*
+ * lskum.h -- C ABI of the MI355X (gfx950) implicit LSKUM solver.
+ *
+ * The library computes, on one GPU, the implicit least squares kinetic
+ * upwind method (LSKUM) for the 2D Euler equations on a point cloud with the
+ * modified LU-SGS scheme of Verma, Mamidi and Nemili (2024):
+ *   - the second-order LSKUM residual R: least-squares derivatives of the
+ *     kinetic split fluxes Gx+-, Gy+- over each point's split stencils, built
+ *     from q-variables with defect-corrected q-derivatives
+ *     (Section 2, eq. 11 and eq. 13-16);
+ *   - the LU-SGS forward/backward sweeps (Section 3, eq. 25-27) with the
+ *     scalar diagonal of eq. (34)-(35), in point-colour order
+ *     (Section 4, Algorithms 4, 6 and 7); the split-flux Jacobian-vector
+ *     products are exact tangents (the paper's "+AD" solvers) or the flux
+ *     differences of eq. (28) (the paper's baseline).
+ *
+ * Conventions
+ *   - Every function returns int: 0 (LSKUM_OK) or a negative LSKUM_ERR_*
+ *     code; lskum_last_error() gives a message for the calling thread.
+ *   - Point fields are passed as structure-of-arrays [4][n] of double:
+ *     field v of point p at index v*n + p.  U = (rho, rho u1, rho u2, rho E)
+ *     with E the total specific energy.
+ *   - Point types: 0 wall, 1 interior, 2 outer (held at free stream).
+ *   - Wall frame: unit tangent (tx, ty); the normal n = (-ty, tx) must point
+ *     into the fluid.  Interior/outer points ignore the frame.
+ *   - Wall points, in storage order, must trace one closed body contour
+ *     (used only by lskum_forces).
+ *   - Connectivity is CSR (nbr_off[n+1], nbr_idx[nnz]) and must be symmetric
+ *     without self edges.
+ *   - Colours are 0-based; points of one colour share no edge.
+ *   - Flow condition: rho_inf = 1, p_inf = 1/gamma, velocity
+ *     M (cos aoa, sin aoa).
+ *   - "on_device" pointers are HIP device pointers (e.g. a torch tensor's
+ *     data_ptr()); otherwise host pointers.  The caller owns every pointer it
+ *     passes; create calls copy what they need.
+ *   - All GPU work of a state is ordered on the HIP stream given at
+ *     lskum_state_create (NULL = the default stream).  Calls that return
+ *     host data synchronise that stream.
+ */
+#ifndef LSKUM_H
+#define LSKUM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LSKUM_OK = 0,
+    LSKUM_ERR_ARG = -1,              /* invalid argument or size */
+    LSKUM_ERR_CONNECTIVITY = -2,     /* asymmetric CSR, self edge, bad index */
+    LSKUM_ERR_DEGENERATE = -3,       /* full stencil without a 2x2 LS solve */
+    LSKUM_ERR_COLOURING = -4,        /* given colours put an edge in a colour */
+    LSKUM_ERR_NONPHYSICAL = -5,      /* rho <= 0, p <= 0 or q~ with beta <= 0 */
+    LSKUM_ERR_NOT_CONVERGED = -6,    /* max_iters reached (report is filled) */
+    LSKUM_ERR_HIP = -7,              /* HIP runtime error */
+    LSKUM_ERR_OOM = -8               /* device allocation failed */
+};
+
+enum { LSKUM_JVP_EXACT = 0, LSKUM_JVP_FLUXDIFF = 1 };
+enum { LSKUM_FP64 = 0, LSKUM_MIXED = 1 };
+
+typedef struct lskum_cloud lskum_cloud; /* device geometry, CSR, colours */
+typedef struct lskum_state lskum_state; /* device flow state and work arrays */
+
+typedef struct {
+    double gamma;       /* ratio of specific heats (1.4) */
+    double cfl;         /* CFL number of the local time step
+                           dt0 = cfl * min_i |r_i - r_0| / (|u_0| + a_0) */
+    int32_t inner_iters;/* inner iterations of the q-derivative defect
+                           correction (eq. 16) after the first-order pass */
+    int32_t jvp_mode;   /* LSKUM_JVP_EXACT or LSKUM_JVP_FLUXDIFF */
+    int32_t precision;  /* LSKUM_FP64, or LSKUM_MIXED: fp32 sweeps and
+                           Jacobian products, fp64 residual and update */
+    int32_t check_every;/* lskum_solve reads the residual every k steps */
+    double tol_rel;     /* lskum_solve stops when res <= tol_rel * res_fs */
+    int32_t max_iters;  /* lskum_solve iteration cap */
+    int32_t reserved;
+} lskum_params;
+
+typedef struct {
+    int32_t iters;      /* iterations run */
+    int32_t status;     /* LSKUM_OK or the error that stopped the solve */
+    double res_fs;      /* residual norm of the free-stream state */
+    double res_first;   /* residual norm at the first iteration of the solve */
+    double res_final;   /* residual norm at the last iteration */
+    double seconds;     /* wall time of the iteration loop */
+    double cl, cd;      /* force coefficients of the final state */
+} lskum_report;
+
+/* Fills p with the defaults: gamma 1.4, cfl 100, inner_iters 1, exact JVP,
+ * fp64, check_every 10, tol_rel 1e-8, max_iters 20000. */
+void lskum_default_params(lskum_params* p);
+
+/* Creates a cloud on the current HIP device from host arrays of n points.
+ * colour == NULL runs the greedy colouring of Algorithm 4 on the host
+ * (point 0 first, then neighbours in storage/CSR order each take the smallest
+ * colour absent from their own neighbours); otherwise the given colours are
+ * validated.  tx/ty may be NULL when the cloud has no wall points.
+ * Errors: ARG, CONNECTIVITY, DEGENERATE (a point whose full-stencil
+ * least-squares matrix is singular), COLOURING, HIP, OOM. */
+int lskum_cloud_create(int64_t n, const double* x, const double* y, const int8_t* type,
+                       const double* tx, const double* ty, const int32_t* nbr_off,
+                       const int32_t* nbr_idx, const int32_t* colour, lskum_cloud** out);
+
+/* Point count, edge count, colour count and the number of degenerate split
+ * stencils (fewer than two members or a singular 2x2 system; such a half
+ * stencil contributes nothing). */
+int lskum_cloud_info(const lskum_cloud* c, int64_t* n, int64_t* nnz, int32_t* n_colours,
+                     int64_t* n_degenerate);
+
+/* Copies the 0-based colours (n int32) to host memory. */
+int lskum_cloud_colours(const lskum_cloud* c, int32_t* colour_out);
+
+void lskum_cloud_destroy(lskum_cloud* c);
+
+/* Creates a state on the cloud's device, initialised to the free stream
+ * (wall points keep only the tangential velocity), and evaluates res_fs, the
+ * residual norm of that free-stream state.  hip_stream is a hipStream_t or
+ * NULL.  The cloud must outlive the state. */
+int lskum_state_create(const lskum_cloud* c, double mach, double aoa_deg,
+                       const lskum_params* prm, void* hip_stream, lskum_state** out);
+
+void lskum_state_destroy(lskum_state* s);
+
+/* Replaces the parameters of a state (the free-stream residual is kept). */
+int lskum_state_set_params(lskum_state* s, const lskum_params* prm);
+
+/* Sets / gets the conserved state U ([4][n] doubles). set_U does not
+ * re-project wall velocities. */
+int lskum_state_set_U(lskum_state* s, const double* U, int on_device);
+int lskum_state_get_U(lskum_state* s, double* U, int on_device);
+
+/* Increment dU ([4][n]) of the last lskum_lusgs_step. */
+int lskum_state_get_dU(lskum_state* s, double* dU, int on_device);
+
+/* Residual of the current state (Algorithm 1 steps q_variables,
+ * q_derivatives, flux_residual).  R ([4][n], may be NULL) receives it;
+ * *res (may be NULL) the norm sqrt(sum_{non-outer} R_rho^2) / n_non_outer.
+ * Errors: NONPHYSICAL when a q~ has beta <= 0. */
+int lskum_residual(lskum_state* s, double* R, int on_device, double* res);
+
+/* q-derivatives of the current state after the first-order pass and
+ * inner_iters inner iterations (eq. 16): qx, qy ([4][n]). */
+int lskum_q_derivatives(lskum_state* s, double* qx, double* qy, int on_device);
+
+/* One implicit iteration: residual, local time step and diagonal, forward
+ * and backward colour sweeps (eq. 27), U += dU.  *res (may be NULL) receives
+ * the norm of the residual of the state the step started from; passing NULL
+ * keeps the step free of host synchronisation.
+ * Errors: NONPHYSICAL (state not advanced past the failing step). */
+int lskum_lusgs_step(lskum_state* s, double* res);
+
+/* One lskum_lusgs_step launched eagerly with HIP events between its
+ * phases on the state's stream; ms[6] receives the GPU milliseconds of
+ * (0) q-derivatives, (1) residual kernel, (2) residual norm, (3) forward
+ * sweep, (4) backward sweep, (5) state update.  Synchronises the stream. */
+int lskum_step_timed(lskum_state* s, double* ms);
+
+/* Iterates lusgs steps until res <= tol_rel * res_fs or max_iters; the
+ * iteration is captured once in a HIP graph and replayed.  rep may be NULL.
+ * Returns NOT_CONVERGED when max_iters is reached (report filled). */
+int lskum_solve(lskum_state* s, lskum_report* rep);
+
+/* Lift and drag coefficients of the current state from the wall pressure:
+ * trapezoidal pressure on each edge of the wall polygon, unit chord,
+ * dynamic pressure M^2/2. */
+int lskum_forces(lskum_state* s, double* cl, double* cd);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* lskum_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSKUM_H */

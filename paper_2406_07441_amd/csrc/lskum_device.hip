@@ -1,0 +1,919 @@
+// Device kernels of the MI355X implicit LSKUM solver (gfx950, wave64).
+//
+// One iteration (Section 4, Algorithm 3, with the colour sweeps of
+// Algorithms 6-7):
+//   k_qgrad_first / k_qgrad_inner   q-derivatives, eq. (16)
+//   k_residual                      LSKUM residual eq. (11), (15); local time
+//                                   step and scalar diagonal eq. (25), (34)-(35);
+//                                   per-point linearisation data for the sweeps
+//   k_sweep<...>   x C colours      forward sweep, eq. (27) first line
+//   k_sweep<...>   x C colours      backward sweep, eq. (27) second line
+//   k_update                        U += dU and the q-variables of eq. (14)
+//   k_norm_final                    density residual norm
+//
+// Mapping: one thread per point, points of a block contiguous in storage so
+// that the ring-structured neighbour gathers of a wavefront fall on a few
+// cache lines; block ids are remapped so that consecutive point ranges stay
+// on one XCD (each XCD has its own L2).  All per-point sums run over the CSR
+// neighbour order.  The per-point 4x4 algebra is not a dense contraction, so
+// no matrix cores are used.
+#include "lskum_internal.h"
+
+#include <cmath>
+
+namespace lskum {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr double kInvSqrtPi = 0.56418958354775628694807945156077;
+constexpr int8_t kWall = 0, kOuter = 2;
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Give XCD x the
+// contiguous range of logical blocks [x*per + min(x, rem), ...) so that
+// neighbouring point ranges share an L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b & 7, r = b >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    return x * per + (x < rem ? x : rem) + r;
+}
+
+__device__ __forceinline__ D4 ld4(const D4* p, int64_t i) { return p[i]; }
+
+// Projections onto a wall frame, evaluated without contraction so that split
+// membership (the sign of da) is decided exactly as a plain multiply-add would.
+__device__ __forceinline__ double dot_nc(double ax, double ay, double bx, double by) {
+#pragma clang fp contract(off)
+    double r = ax * bx;
+    double s = ay * by;
+    return r + s;
+}
+
+struct Prim {
+    double rho, u1, u2, p, beta, sb;
+};
+
+// Primitive state of a (reconstructed) q vector, eq. (14) inverted:
+// beta = -q4/2, u = (q2, q3)/(2 beta), rho = exp(q1 + beta |u|^2) beta^(-1/(gamma-1)),
+// p = rho/(2 beta).  For gamma = 1.4 the power is 1/(beta^2 sqrt(beta)).
+__device__ __forceinline__ Prim prim_from_q(const D4& q, double inv_gm1, bool g14) {
+    Prim w;
+    const double beta = -0.5 * q.w;
+    const double i2b = -1.0 / q.w;
+    w.u1 = q.y * i2b;
+    w.u2 = q.z * i2b;
+    const double sb = sqrt(beta);
+    const double e = exp(q.x + beta * (w.u1 * w.u1 + w.u2 * w.u2));
+    w.rho = g14 ? e / (beta * beta * sb) : e * exp(-inv_gm1 * log(beta));
+    w.p = w.rho * i2b;
+    w.beta = beta;
+    w.sb = sb;
+    return w;
+}
+
+// Kinetic split flux G_d^sg of a primitive state (half-range moments of the
+// Maxwellian, eq. 3-6): DIR 0 = x, 1 = y, 2 = unit direction (dx, dy).
+template <int DIR>
+__device__ __forceinline__ void split_flux(const Prim& w, double dx, double dy, double sg,
+                                           double inv_gm1, double G[4]) {
+    const double ud = DIR == 0 ? w.u1 : (DIR == 1 ? w.u2 : w.u1 * dx + w.u2 * dy);
+    const double S = ud * w.sb;
+    const double A = 0.5 * (1.0 + sg * erf(S));
+    const double B = exp(-(S * S)) * (0.5 * kInvSqrtPi) / w.sb;
+    const double rhoE = w.p * inv_gm1 + 0.5 * w.rho * (w.u1 * w.u1 + w.u2 * w.u2);
+    const double mass = w.rho * (ud * A + sg * B);
+    const double pA = w.p * A;
+    G[0] = mass;
+    if (DIR == 0) {
+        G[1] = pA + w.u1 * mass;
+        G[2] = w.u2 * mass;
+    } else if (DIR == 1) {
+        G[1] = w.u1 * mass;
+        G[2] = pA + w.u2 * mass;
+    } else {
+        G[1] = pA * dx + w.u1 * mass;
+        G[2] = pA * dy + w.u2 * mass;
+    }
+    G[3] = (rhoE + w.p) * ud * A + sg * (rhoE + 0.5 * w.p) * B;
+}
+
+template <int DIR>
+__device__ __forceinline__ void acc_split_diff(const Prim& wi, const Prim& w0, double dx, double dy,
+                                               double sg, double wgt, double inv_gm1, double R[4]) {
+    double Gi[4], G0[4];
+    split_flux<DIR>(wi, dx, dy, sg, inv_gm1, Gi);
+    split_flux<DIR>(w0, dx, dy, sg, inv_gm1, G0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) R[v] += wgt * (Gi[v] - G0[v]);
+}
+
+// ---------------------------------------------------------------------------
+// Geometry precompute (once per cloud).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_precompute(int64_t n, const D2* __restrict__ xy,
+                                                       const D2* __restrict__ frame,
+                                                       const int8_t* __restrict__ type,
+                                                       const int32_t* __restrict__ off,
+                                                       const int32_t* __restrict__ idx,
+                                                       PointGeom* __restrict__ geom,
+                                                       unsigned long long* __restrict__ counts) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const D2 r0 = xy[p];
+    const int8_t ty = type[p];
+    const D2 t = frame[p];
+    double sxx = 0, syy = 0, sxy = 0, rmin2 = INFINITY;
+    // split sums: a = split direction, b = transverse
+    double saa[4] = {0, 0, 0, 0}, sbb[4] = {0, 0, 0, 0}, sab[4] = {0, 0, 0, 0};
+    int cnt[4] = {0, 0, 0, 0};
+    const int32_t e0 = off[p], e1 = off[p + 1];
+    for (int32_t e = e0; e < e1; ++e) {
+        const D2 ri = xy[idx[e]];
+        const double dx = ri.x - r0.x, dy = ri.y - r0.y;
+        sxx += dx * dx;
+        syy += dy * dy;
+        sxy += dx * dy;
+        const double d2 = dx * dx + dy * dy;
+        rmin2 = d2 < rmin2 ? d2 : rmin2;
+        if (ty == kOuter) continue;
+        if (ty == kWall) {
+            const double ds = dot_nc(dx, dy, t.x, t.y);
+            const double dn = dot_nc(dx, dy, -t.y, t.x);
+            if (ds != 0.0) {
+                const int k = ds < 0.0 ? 0 : 1;
+                saa[k] += ds * ds; sbb[k] += dn * dn; sab[k] += ds * dn; ++cnt[k];
+            }
+            if (dn > 0.0) {
+                saa[2] += dn * dn; sbb[2] += ds * ds; sab[2] += ds * dn; ++cnt[2];
+            }
+        } else {
+            if (dx != 0.0) {
+                const int k = dx < 0.0 ? 0 : 1;
+                saa[k] += dx * dx; sbb[k] += dy * dy; sab[k] += dx * dy; ++cnt[k];
+            }
+            if (dy != 0.0) {
+                const int k = dy < 0.0 ? 2 : 3;
+                saa[k] += dy * dy; sbb[k] += dx * dx; sab[k] += dx * dy; ++cnt[k];
+            }
+        }
+    }
+    PointGeom g;
+    const double det = sxx * syy - sxy * sxy;
+    if (!(det > 1e-12 * sxx * syy)) {
+        atomicAdd(&counts[0], 1ull);  // singular full stencil
+        g.lsq = {0, 0, 0, sqrt(rmin2)};
+    } else {
+        g.lsq = {syy / det, -sxy / det, sxx / det, sqrt(rmin2)};
+    }
+    const int nsplit = ty == kOuter ? 0 : (ty == kWall ? 3 : 4);
+    double cb[4] = {0, 0, 0, 0}, cab[4] = {0, 0, 0, 0};
+    for (int k = 0; k < nsplit; ++k) {
+        const double dk = saa[k] * sbb[k] - sab[k] * sab[k];
+        if (cnt[k] < 2 || !(dk > 1e-12 * saa[k] * sbb[k])) {
+            atomicAdd(&counts[1], 1ull);  // degenerate half stencil: contributes 0
+            continue;
+        }
+        cb[k] = sbb[k] / dk;
+        cab[k] = -sab[k] / dk;
+    }
+    // LS_k(1): the weight sums, with the weights exactly as the kernels form them
+    double ls1[4] = {0, 0, 0, 0};
+    if (nsplit) {
+        for (int32_t e = e0; e < e1; ++e) {
+            const D2 ri = xy[idx[e]];
+            const double dx = ri.x - r0.x, dy = ri.y - r0.y;
+            if (ty == kWall) {
+                const double ds = dot_nc(dx, dy, t.x, t.y);
+                const double dn = dot_nc(dx, dy, -t.y, t.x);
+                if (ds != 0.0) {
+                    const int k = ds < 0.0 ? 0 : 1;
+                    ls1[k] += cb[k] * ds + cab[k] * dn;
+                }
+                if (dn > 0.0) ls1[2] += cb[2] * dn + cab[2] * ds;
+            } else {
+                if (dx != 0.0) {
+                    const int k = dx < 0.0 ? 0 : 1;
+                    ls1[k] += cb[k] * dx + cab[k] * dy;
+                }
+                if (dy != 0.0) {
+                    const int k = dy < 0.0 ? 2 : 3;
+                    ls1[k] += cb[k] * dy + cab[k] * dx;
+                }
+            }
+        }
+    }
+    for (int k = 0; k < 4; ++k) g.split[k] = {cb[k], cab[k]};
+    g.ls1 = {ls1[0], ls1[1], ls1[2], ls1[3]};
+    geom[p] = g;
+}
+
+// Free stream: rho 1, p 1/gamma, velocity M (cos a, sin a); wall points keep
+// the tangential velocity only.
+__global__ void __launch_bounds__(kBlock) k_free_stream(int64_t n, const int8_t* __restrict__ type,
+                                                        const D2* __restrict__ frame, double gamma,
+                                                        double u_inf, double v_inf, D4* __restrict__ U) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double u1 = u_inf, u2 = v_inf;
+    if (type[p] == kWall) {
+        const D2 t = frame[p];
+        const double ut = u1 * t.x + u2 * t.y;
+        u1 = ut * t.x;
+        u2 = ut * t.y;
+    }
+    const double rho = 1.0, pr = 1.0 / gamma;
+    U[p] = {rho, rho * u1, rho * u2, pr / (gamma - 1.0) + 0.5 * rho * (u1 * u1 + u2 * u2)};
+}
+
+// q-variables of eq. (14) from U.
+__device__ __forceinline__ D4 q_of_U(const D4& u, double gamma, double inv_gm1, bool& bad) {
+    const double rho = u.x;
+    const double irho = 1.0 / rho;
+    const double u1 = u.y * irho, u2 = u.z * irho;
+    const double usq = u1 * u1 + u2 * u2;
+    const double p = (gamma - 1.0) * (u.w - 0.5 * rho * usq);
+    bad = !(rho > 0.0) || !(p > 0.0);
+    const double beta = 0.5 * rho / p;
+    return {log(rho) + inv_gm1 * log(beta) - beta * usq, 2.0 * beta * u1, 2.0 * beta * u2,
+            -2.0 * beta};
+}
+
+__global__ void __launch_bounds__(kBlock) k_q_from_U(int64_t n, double gamma,
+                                                     const D4* __restrict__ U, D4* __restrict__ q,
+                                                     int32_t* __restrict__ flags) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    bool bad;
+    q[p] = q_of_U(U[p], gamma, 1.0 / (gamma - 1.0), bad);
+    if (bad) flags[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// q-derivatives (eq. 16): first-order pass and Jacobi inner passes.
+// ---------------------------------------------------------------------------
+template <bool INNER>
+__global__ void __launch_bounds__(kBlock) k_qgrad(int64_t n, const D2* __restrict__ xy,
+                                                  const int32_t* __restrict__ off,
+                                                  const int32_t* __restrict__ idx,
+                                                  const PointGeom* __restrict__ geom,
+                                                  const D4* __restrict__ q,
+                                                  const D4* __restrict__ qx_in,
+                                                  const D4* __restrict__ qy_in,
+                                                  D4* __restrict__ qx_out, D4* __restrict__ qy_out) {
+    const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const D2 r0 = xy[p];
+    const D4 q0 = q[p];
+    D4 gx0{}, gy0{};
+    if (INNER) {
+        gx0 = qx_in[p];
+        gy0 = qy_in[p];
+    }
+    double bx[4] = {0, 0, 0, 0}, by[4] = {0, 0, 0, 0};
+    const int32_t e0 = off[p], e1 = off[p + 1];
+    for (int32_t e = e0; e < e1; ++e) {
+        const int32_t i = idx[e];
+        const D2 ri = xy[i];
+        const double dx = ri.x - r0.x, dy = ri.y - r0.y;
+        const D4 qi = q[i];
+        double dq[4] = {qi.x - q0.x, qi.y - q0.y, qi.z - q0.z, qi.w - q0.w};
+        if (INNER) {
+            const D4 gxi = qx_in[i], gyi = qy_in[i];
+            dq[0] -= 0.5 * (dx * (gxi.x - gx0.x) + dy * (gyi.x - gy0.x));
+            dq[1] -= 0.5 * (dx * (gxi.y - gx0.y) + dy * (gyi.y - gy0.y));
+            dq[2] -= 0.5 * (dx * (gxi.z - gx0.z) + dy * (gyi.z - gy0.z));
+            dq[3] -= 0.5 * (dx * (gxi.w - gx0.w) + dy * (gyi.w - gy0.w));
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            bx[v] += dx * dq[v];
+            by[v] += dy * dq[v];
+        }
+    }
+    const D4 L = geom[p].lsq;
+    qx_out[p] = {L.x * bx[0] + L.y * by[0], L.x * bx[1] + L.y * by[1], L.x * bx[2] + L.y * by[2],
+                 L.x * bx[3] + L.y * by[3]};
+    qy_out[p] = {L.y * bx[0] + L.z * by[0], L.y * bx[1] + L.z * by[1], L.y * bx[2] + L.z * by[2],
+                 L.y * bx[3] + L.z * by[3]};
+}
+
+// ---------------------------------------------------------------------------
+// Residual (eq. 11 with the q~ reconstruction of eq. 15), local time step,
+// scalar diagonal (eq. 25, 34-35) and the sweep linearisation data.
+// ---------------------------------------------------------------------------
+template <bool MIXED>
+__global__ void __launch_bounds__(kBlock) k_residual(
+    int64_t n, double gamma, double cfl, const D2* __restrict__ xy, const D2* __restrict__ frame,
+    const int8_t* __restrict__ type, const int32_t* __restrict__ off,
+    const int32_t* __restrict__ idx, const PointGeom* __restrict__ geom,
+    const D4* __restrict__ U, const D4* __restrict__ q, const D4* __restrict__ qx,
+    const D4* __restrict__ qy, D4* __restrict__ R, double* __restrict__ Dg,
+    D4* __restrict__ jv0, D4* __restrict__ jv1, D4* __restrict__ jv2, F4* __restrict__ jv0f,
+    F4* __restrict__ jv1f, F4* __restrict__ jv2f, float* __restrict__ Df,
+    double* __restrict__ partial, int32_t* __restrict__ flags) {
+    __shared__ double red[kBlock / 64];
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t p = (int64_t)lb * blockDim.x + threadIdx.x;
+    const double inv_gm1 = 1.0 / (gamma - 1.0);
+    const bool g14 = gamma == 1.4;
+    double rr = 0.0;  // R_rho^2 of this point (non-outer)
+    if (p < n) {
+        const int8_t ty = type[p];
+        const D2 r0 = xy[p];
+        double Rp[4] = {0, 0, 0, 0};
+        bool bad = false;
+        if (ty != kOuter) {
+            const D4 q0 = q[p], gx0 = qx[p], gy0 = qy[p];
+            const PointGeom& G = geom[p];
+            const D2 c0 = G.split[0], c1 = G.split[1], c2 = G.split[2], c3 = G.split[3];
+            const D2 t = frame[p];
+            const int32_t e0 = off[p], e1 = off[p + 1];
+            for (int32_t e = e0; e < e1; ++e) {
+                const int32_t i = idx[e];
+                const D2 ri = xy[i];
+                const double dx = ri.x - r0.x, dy = ri.y - r0.y;
+                const D4 qi = q[i], gxi = qx[i], gyi = qy[i];
+                const D4 qti = {qi.x - 0.5 * (dx * gxi.x + dy * gyi.x),
+                                qi.y - 0.5 * (dx * gxi.y + dy * gyi.y),
+                                qi.z - 0.5 * (dx * gxi.z + dy * gyi.z),
+                                qi.w - 0.5 * (dx * gxi.w + dy * gyi.w)};
+                const D4 qt0 = {q0.x - 0.5 * (dx * gx0.x + dy * gy0.x),
+                                q0.y - 0.5 * (dx * gx0.y + dy * gy0.y),
+                                q0.z - 0.5 * (dx * gx0.z + dy * gy0.z),
+                                q0.w - 0.5 * (dx * gx0.w + dy * gy0.w)};
+                if (ty == kWall) {
+                    const double ds = dot_nc(dx, dy, t.x, t.y);
+                    const double dn = dot_nc(dx, dy, -t.y, t.x);
+                    const bool in_t = ds != 0.0, in_n = dn > 0.0;
+                    if (!in_t && !in_n) continue;
+                    bad |= !(qti.w < 0.0) || !(qt0.w < 0.0);
+                    const Prim wi = prim_from_q(qti, inv_gm1, g14);
+                    const Prim w0 = prim_from_q(qt0, inv_gm1, g14);
+                    if (in_t) {
+                        const D2 c = ds < 0.0 ? c0 : c1;
+                        const double sg = ds < 0.0 ? 1.0 : -1.0;
+                        acc_split_diff<2>(wi, w0, t.x, t.y, sg, c.x * ds + c.y * dn, inv_gm1, Rp);
+                    }
+                    if (in_n)
+                        acc_split_diff<2>(wi, w0, -t.y, t.x, -1.0, c2.x * dn + c2.y * ds, inv_gm1, Rp);
+                } else {
+                    const bool in_x = dx != 0.0, in_y = dy != 0.0;
+                    if (!in_x && !in_y) continue;
+                    bad |= !(qti.w < 0.0) || !(qt0.w < 0.0);
+                    const Prim wi = prim_from_q(qti, inv_gm1, g14);
+                    const Prim w0 = prim_from_q(qt0, inv_gm1, g14);
+                    if (in_x) {
+                        const D2 c = dx < 0.0 ? c0 : c1;
+                        const double sg = dx < 0.0 ? 1.0 : -1.0;
+                        acc_split_diff<0>(wi, w0, 1.0, 0.0, sg, c.x * dx + c.y * dy, inv_gm1, Rp);
+                    }
+                    if (in_y) {
+                        const D2 c = dy < 0.0 ? c2 : c3;
+                        const double sg = dy < 0.0 ? 1.0 : -1.0;
+                        acc_split_diff<1>(wi, w0, 0.0, 1.0, sg, c.x * dy + c.y * dx, inv_gm1, Rp);
+                    }
+                }
+            }
+            if (ty == kWall) {  // drop the normal-momentum component
+                const double nx = -t.y, ny = t.x;
+                const double mn = Rp[1] * nx + Rp[2] * ny;
+                Rp[1] -= mn * nx;
+                Rp[2] -= mn * ny;
+            }
+            rr = Rp[0] * Rp[0];
+        }
+        R[p] = {Rp[0], Rp[1], Rp[2], Rp[3]};
+
+        // linearisation data at the current state, local time step, diagonal
+        const D4 u = U[p];
+        const double rho = u.x, irho = 1.0 / rho;
+        const double u1 = u.y * irho, u2 = u.z * irho;
+        const double usq = u1 * u1 + u2 * u2;
+        const double pr = (gamma - 1.0) * (u.w - 0.5 * rho * usq);
+        const double beta = 0.5 * rho / pr;
+        const double sb = sqrt(beta);
+        const double sx = u1 * sb, sy = u2 * sb;
+        const D4 j0 = {rho, u1, u2, pr};
+        const D4 j1 = {sb, beta, irho, 1.0 / pr};
+        const D4 j2 = {erf(sx), exp(-(sx * sx)), erf(sy), exp(-(sy * sy))};
+        const double a = sqrt(gamma * pr / rho);
+        const PointGeom& G = geom[p];
+        const double dt = cfl * G.lsq.w / (sqrt(usq) + a);
+        double Dp = 1.0 / dt;
+        if (ty == kWall) {
+            const D2 t = frame[p];
+            const double ut = u1 * t.x + u2 * t.y, un = -u1 * t.y + u2 * t.x;
+            Dp -= G.ls1.x * fmax(ut + a, 0.0);
+            Dp += G.ls1.y * fmax(a - ut, 0.0);
+            Dp += G.ls1.z * fmax(a - un, 0.0);
+        } else if (ty != kOuter) {
+            Dp -= G.ls1.x * fmax(u1 + a, 0.0);
+            Dp += G.ls1.y * fmax(a - u1, 0.0);
+            Dp -= G.ls1.z * fmax(u2 + a, 0.0);
+            Dp += G.ls1.w * fmax(a - u2, 0.0);
+        }
+        if (MIXED) {
+            jv0f[p] = {(float)j0.x, (float)j0.y, (float)j0.z, (float)j0.w};
+            jv1f[p] = {(float)j1.x, (float)j1.y, (float)j1.z, (float)j1.w};
+            jv2f[p] = {(float)j2.x, (float)j2.y, (float)j2.z, (float)j2.w};
+            Df[p] = (float)Dp;
+        } else {
+            jv0[p] = j0;
+            jv1[p] = j1;
+            jv2[p] = j2;
+            Dg[p] = Dp;
+        }
+        if (bad || !(rho > 0.0) || !(pr > 0.0)) flags[0] = 1;
+    }
+    // deterministic block reduction of R_rho^2
+    for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+        partial[lb] = s;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_norm_final(const double* __restrict__ partial, int nb,
+                                                       double inv_active, double* __restrict__ out) {
+    __shared__ double red[kBlock / 64];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partial[b];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += red[w];
+        out[0] = sqrt(t) * inv_active;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Split-flux Jacobian-vector products for the sweeps.
+// ---------------------------------------------------------------------------
+template <class T>
+struct Lin {  // linearisation data of one neighbour
+    T rho, u1, u2, p, sb, beta, irho, ip;
+};
+
+// Tangent of the split flux along unit direction (dx, dy) with sign sg,
+// given erf(S) and exp(-S^2) at the linearisation state.  Hand-written
+// forward-mode derivative of the closed-form split flux (the paper's exact
+// Jacobian-vector product): with rho', u', p' from dU,
+//   beta' = (rho' - 2 beta p')/(2p),  S' = u_d' sqrt(beta) + u_d beta'/(2 sqrt(beta)),
+//   A' = sg exp(-S^2) S'/sqrt(pi),    B' = B (-2 S S' - beta'/(2 beta)),
+// and the product rule on each flux component.
+template <class T>
+__device__ __forceinline__ void jvp_exact(const Lin<T>& L, T er, T g, T dx, T dy, T sg,
+                                          const T dU[4], T gm1, T inv_gm1, T J[4]) {
+    const T rd = dU[0];
+    const T u1d = (dU[1] - L.u1 * rd) * L.irho;
+    const T u2d = (dU[2] - L.u2 * rd) * L.irho;
+    const T usq = L.u1 * L.u1 + L.u2 * L.u2;
+    const T pd = gm1 * (dU[3] - T(0.5) * rd * usq - L.rho * (L.u1 * u1d + L.u2 * u2d));
+    const T bd = (rd - T(2) * L.beta * pd) * (T(0.5) * L.ip);
+    const T ud = L.u1 * dx + L.u2 * dy;
+    const T udd = u1d * dx + u2d * dy;
+    const T isb = L.sb / L.beta;  // 1/sqrt(beta)
+    const T S = ud * L.sb;
+    const T Sd = udd * L.sb + T(0.5) * ud * bd * isb;
+    const T A = T(0.5) * (T(1) + sg * er);
+    const T Ad = sg * g * Sd * T(kInvSqrtPi);
+    const T B = g * T(0.5 * kInvSqrtPi) * isb;
+    const T Bd = B * (T(-2) * S * Sd - T(0.5) * bd / L.beta);
+    const T F = ud * A + sg * B;
+    const T Fd = udd * A + ud * Ad + sg * Bd;
+    const T rhoE = L.p * inv_gm1 + T(0.5) * L.rho * usq;
+    const T J0 = rd * F + L.rho * Fd;
+    const T mass = L.rho * F;
+    const T pAd = pd * A + L.p * Ad;
+    J[0] = J0;
+    J[1] = pAd * dx + u1d * mass + L.u1 * J0;
+    J[2] = pAd * dy + u2d * mass + L.u2 * J0;
+    J[3] = (dU[3] + pd) * ud * A + (rhoE + L.p) * (udd * A + ud * Ad) +
+           sg * ((dU[3] + T(0.5) * pd) * B + (rhoE + T(0.5) * L.p) * Bd);
+}
+
+// Split flux from the linearisation data (value only, used by the
+// flux-difference products).
+__device__ __forceinline__ void flux_lin(const Lin<double>& L, double er, double g, double dx,
+                                         double dy, double sg, double inv_gm1, double G[4]) {
+    const double ud = L.u1 * dx + L.u2 * dy;
+    const double A = 0.5 * (1.0 + sg * er);
+    const double B = g * (0.5 * kInvSqrtPi) / L.sb;
+    const double rhoE = L.p * inv_gm1 + 0.5 * L.rho * (L.u1 * L.u1 + L.u2 * L.u2);
+    const double mass = L.rho * (ud * A + sg * B);
+    G[0] = mass;
+    G[1] = L.p * A * dx + L.u1 * mass;
+    G[2] = L.p * A * dy + L.u2 * mass;
+    G[3] = (rhoE + L.p) * ud * A + sg * (rhoE + 0.5 * L.p) * B;
+}
+
+// Flux difference G(U + dU) - G(U) of eq. (28).
+__device__ __forceinline__ void jvp_fluxdiff(const Lin<double>& L, double er, double g, const D4& u,
+                                             double dx, double dy, double sg, const double dU[4],
+                                             double gamma, double inv_gm1, double J[4]) {
+    const double a0 = u.x + dU[0], a1 = u.y + dU[1], a2 = u.z + dU[2], a3 = u.w + dU[3];
+    Lin<double> W;
+    W.rho = a0;
+    W.irho = 1.0 / a0;
+    W.u1 = a1 * W.irho;
+    W.u2 = a2 * W.irho;
+    W.p = (gamma - 1.0) * (a3 - 0.5 * W.rho * (W.u1 * W.u1 + W.u2 * W.u2));
+    W.beta = 0.5 * W.rho / W.p;
+    W.sb = sqrt(W.beta);
+    const double S = (W.u1 * dx + W.u2 * dy) * W.sb;
+    double Ga[4], Gb[4];
+    flux_lin(W, erf(S), exp(-(S * S)), dx, dy, sg, inv_gm1, Ga);
+    flux_lin(L, er, g, dx, dy, sg, inv_gm1, Gb);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) J[v] = Ga[v] - Gb[v];
+}
+
+template <class T>
+__device__ __forceinline__ Lin<T> load_lin(const Vec4<T>* jv0, const Vec4<T>* jv1, int32_t i) {
+    const Vec4<T> a = jv0[i], b = jv1[i];
+    return Lin<T>{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+}
+
+// One colour phase of a sweep (eq. 27).  FWD: dU*_0 = -(R_0 + sum_lower w A dU*) / D_0;
+// backward: dU_0 = dU*_0 - (sum_upper w A dU) / D_0.  MODE 0 exact tangent,
+// 1 flux difference.  T is the arithmetic of the products and increments.
+template <class T, bool FWD, int MODE>
+__global__ void __launch_bounds__(kBlock) k_sweep(
+    int32_t start, int32_t count, int32_t c, const int32_t* __restrict__ col_perm,
+    const D2* __restrict__ xy, const D2* __restrict__ frame, const int8_t* __restrict__ type,
+    const int32_t* __restrict__ off, const int32_t* __restrict__ idx,
+    const int32_t* __restrict__ colour, const PointGeom* __restrict__ geom,
+    const Vec4<T>* __restrict__ jv0, const Vec4<T>* __restrict__ jv1,
+    const Vec4<T>* __restrict__ jv2, const D4* __restrict__ U, const D4* __restrict__ R,
+    const T* __restrict__ Dg, Vec4<T>* __restrict__ dU, double gamma) {
+    const int t_ = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (t_ >= count) return;
+    const int32_t p = col_perm[start + t_];
+    const int8_t ty = type[p];
+    if (ty == kOuter) {
+        if (FWD) dU[p] = {T(0), T(0), T(0), T(0)};
+        return;
+    }
+    const T gm1 = T(gamma - 1.0), inv_gm1 = T(1.0 / (gamma - 1.0));
+    T acc[4] = {T(0), T(0), T(0), T(0)};
+    if (FWD) {
+        const D4 r = R[p];
+        acc[0] = T(r.x); acc[1] = T(r.y); acc[2] = T(r.z); acc[3] = T(r.w);
+    }
+    const D2 r0 = xy[p];
+    const PointGeom& G = geom[p];
+    const D2 c0 = G.split[0], c1 = G.split[1], c2 = G.split[2], c3 = G.split[3];
+    const D2 t = frame[p];
+    const int32_t e0 = off[p], e1 = off[p + 1];
+    for (int32_t e = e0; e < e1; ++e) {
+        const int32_t i = idx[e];
+        const int32_t ci = colour[i];
+        if (FWD ? !(ci < c) : !(ci > c)) continue;
+        const D2 ri = xy[i];
+        const double dx = ri.x - r0.x, dy = ri.y - r0.y;
+        const Vec4<T> di = dU[i];
+        const T dv[4] = {di.x, di.y, di.z, di.w};
+        const Lin<T> L = load_lin(jv0, jv1, i);
+        T J[4];
+        if (ty == kWall) {
+            const double ds = dot_nc(dx, dy, t.x, t.y);
+            const double dn = dot_nc(dx, dy, -t.y, t.x);
+            // directions of the wall frame: erf/exp at the neighbour state are formed here
+            if (ds != 0.0) {
+                const D2 cc = ds < 0.0 ? c0 : c1;
+                const double sg = ds < 0.0 ? 1.0 : -1.0;
+                const T w = T(cc.x * ds + cc.y * dn);
+                if constexpr (MODE == 1) {
+                    const Lin<double>& Ld = reinterpret_cast<const Lin<double>&>(L);
+                    const double S = (Ld.u1 * t.x + Ld.u2 * t.y) * Ld.sb;
+                    jvp_fluxdiff(Ld, erf(S), exp(-(S * S)), U[i], t.x, t.y, sg,
+                                 reinterpret_cast<const double*>(dv), gamma, 1.0 / (gamma - 1.0),
+                                 reinterpret_cast<double*>(J));
+                } else {
+                    const T S = (L.u1 * T(t.x) + L.u2 * T(t.y)) * L.sb;
+                    jvp_exact<T>(L, erf(S), exp(-(S * S)), T(t.x), T(t.y), T(sg), dv, gm1,
+                                 inv_gm1, J);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
+            }
+            if (dn > 0.0) {
+                const T w = T(c2.x * dn + c2.y * ds);
+                if constexpr (MODE == 1) {
+                    const Lin<double>& Ld = reinterpret_cast<const Lin<double>&>(L);
+                    const double S = (-Ld.u1 * t.y + Ld.u2 * t.x) * Ld.sb;
+                    jvp_fluxdiff(Ld, erf(S), exp(-(S * S)), U[i], -t.y, t.x, -1.0,
+                                 reinterpret_cast<const double*>(dv), gamma, 1.0 / (gamma - 1.0),
+                                 reinterpret_cast<double*>(J));
+                } else {
+                    const T S = (-L.u1 * T(t.y) + L.u2 * T(t.x)) * L.sb;
+                    jvp_exact<T>(L, erf(S), exp(-(S * S)), T(-t.y), T(t.x), T(-1), dv, gm1,
+                                 inv_gm1, J);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
+            }
+        } else {
+            const Vec4<T> k2 = jv2[i];
+            if (dx != 0.0) {
+                const D2 cc = dx < 0.0 ? c0 : c1;
+                const T sg = dx < 0.0 ? T(1) : T(-1);
+                const T w = T(cc.x * dx + cc.y * dy);
+                if constexpr (MODE == 1) {
+                    jvp_fluxdiff(reinterpret_cast<const Lin<double>&>(L), (double)k2.x,
+                                 (double)k2.y, U[i], 1.0, 0.0, (double)sg,
+                                 reinterpret_cast<const double*>(dv), gamma, 1.0 / (gamma - 1.0),
+                                 reinterpret_cast<double*>(J));
+                } else {
+                    jvp_exact<T>(L, k2.x, k2.y, T(1), T(0), sg, dv, gm1, inv_gm1, J);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
+            }
+            if (dy != 0.0) {
+                const D2 cc = dy < 0.0 ? c2 : c3;
+                const T sg = dy < 0.0 ? T(1) : T(-1);
+                const T w = T(cc.x * dy + cc.y * dx);
+                if constexpr (MODE == 1) {
+                    jvp_fluxdiff(reinterpret_cast<const Lin<double>&>(L), (double)k2.z,
+                                 (double)k2.w, U[i], 0.0, 1.0, (double)sg,
+                                 reinterpret_cast<const double*>(dv), gamma, 1.0 / (gamma - 1.0),
+                                 reinterpret_cast<double*>(J));
+                } else {
+                    jvp_exact<T>(L, k2.z, k2.w, T(0), T(1), sg, dv, gm1, inv_gm1, J);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
+            }
+        }
+    }
+    const T iD = T(1) / Dg[p];
+    T out[4];
+    if (FWD) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[v] = -acc[v] * iD;
+    } else {
+        const Vec4<T> d0 = dU[p];
+        out[0] = d0.x - acc[0] * iD;
+        out[1] = d0.y - acc[1] * iD;
+        out[2] = d0.z - acc[2] * iD;
+        out[3] = d0.w - acc[3] * iD;
+    }
+    if (ty == kWall) {
+        const T nx = T(-t.y), ny = T(t.x);
+        const T mn = out[1] * nx + out[2] * ny;
+        out[1] -= mn * nx;
+        out[2] -= mn * ny;
+    }
+    dU[p] = {out[0], out[1], out[2], out[3]};
+}
+
+// U += dU (Section 3) and the q-variables of the new state (eq. 14).
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_update(int64_t n, double gamma, D4* __restrict__ U,
+                                                   const Vec4<T>* __restrict__ dU,
+                                                   D4* __restrict__ q, int32_t* __restrict__ flags) {
+    const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    D4 u = U[p];
+    const Vec4<T> d = dU[p];
+    u.x += (double)d.x;
+    u.y += (double)d.y;
+    u.z += (double)d.z;
+    u.w += (double)d.w;
+    U[p] = u;
+    bool bad;
+    q[p] = q_of_U(u, gamma, 1.0 / (gamma - 1.0), bad);
+    if (bad) flags[0] = 1;
+}
+
+// Pressure force on the closed wall polygon: sum over edges (a, b) of
+// -(p_mid - p_inf) * (edge normal pointing out of the body) * |e|.
+__global__ void __launch_bounds__(kBlock) k_forces(int64_t m, const int32_t* __restrict__ wall,
+                                                   const D2* __restrict__ xy, const D4* __restrict__ U,
+                                                   double gamma, double orient,
+                                                   double* __restrict__ out) {
+    __shared__ double rx[kBlock / 64], ry[kBlock / 64];
+    double fx = 0.0, fy = 0.0;
+    const double pinf = 1.0 / gamma;
+    for (int64_t j = threadIdx.x; j < m; j += blockDim.x) {
+        const int32_t a = wall[j], b = wall[j + 1 == m ? 0 : j + 1];
+        const D4 ua = U[a], ub = U[b];
+        const double pa = (gamma - 1.0) * (ua.w - 0.5 * (ua.y * ua.y + ua.z * ua.z) / ua.x);
+        const double pb = (gamma - 1.0) * (ub.w - 0.5 * (ub.y * ub.y + ub.z * ub.z) / ub.x);
+        const double pm = 0.5 * (pa + pb) - pinf;
+        const D2 ra = xy[a], rb = xy[b];
+        const double ex = rb.x - ra.x, ey = rb.y - ra.y;
+        fx -= pm * (orient * ey);
+        fy -= pm * (-orient * ex);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        fx += __shfl_xor(fx, o, 64);
+        fy += __shfl_xor(fy, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        rx[threadIdx.x >> 6] = fx;
+        ry[threadIdx.x >> 6] = fy;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sx = 0, sy = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            sx += rx[w];
+            sy += ry[w];
+        }
+        out[0] = sx;
+        out[1] = sy;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_soa_to_aos(const double* __restrict__ soa,
+                                                       D4* __restrict__ aos, int64_t n) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    aos[p] = {soa[p], soa[n + p], soa[2 * n + p], soa[3 * n + p]};
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_aos_to_soa(const Vec4<T>* __restrict__ aos,
+                                                       double* __restrict__ soa, int64_t n) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const Vec4<T> v = aos[p];
+    soa[p] = (double)v.x;
+    soa[n + p] = (double)v.y;
+    soa[2 * n + p] = (double)v.z;
+    soa[3 * n + p] = (double)v.w;
+}
+
+__global__ void k_clear_flags(int32_t* flags) {
+    if (threadIdx.x < 4) flags[threadIdx.x] = 0;
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_precompute(Cloud& c, hipStream_t st) {
+    unsigned long long* d_cnt = nullptr;
+    hipError_t e = hipMalloc((void**)&d_cnt, 2 * sizeof(unsigned long long));
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(d_cnt, 0, 2 * sizeof(unsigned long long), st);
+    if (e != hipSuccess) return e;
+    if (c.n > 0)
+        hipLaunchKernelGGL(k_precompute, dim3(grid_for(c.n)), dim3(kBlock), 0, st, c.n, c.xy,
+                           c.frame, c.type, c.off, c.idx, c.geom, d_cnt);
+    unsigned long long h[2] = {0, 0};
+    e = hipMemcpyAsync(h, d_cnt, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    (void)hipFree(d_cnt);
+    c.n_degenerate = (int64_t)h[1];
+    if (h[0]) return hipErrorInvalidValue;  // singular full stencil, reported by the caller
+    return hipGetLastError();
+}
+
+hipError_t launch_free_stream(State& s) {
+    const Cloud& c = *s.cloud;
+    const double a = s.aoa_deg * 3.14159265358979323846 / 180.0;
+    hipLaunchKernelGGL(k_free_stream, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream, c.n, c.type,
+                       c.frame, s.prm.gamma, s.mach * cos(a), s.mach * sin(a), s.U);
+    return hipGetLastError();
+}
+
+hipError_t launch_q_from_U(State& s) {
+    const Cloud& c = *s.cloud;
+    hipLaunchKernelGGL(k_q_from_U, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream, c.n,
+                       s.prm.gamma, s.U, s.q, s.flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_q_derivatives(State& s) {
+    const Cloud& c = *s.cloud;
+    const dim3 g(grid_for(c.n)), b(kBlock);
+    hipLaunchKernelGGL(k_qgrad<false>, g, b, 0, s.stream, c.n, c.xy, c.off, c.idx, c.geom, s.q,
+                       nullptr, nullptr, s.qx[0], s.qy[0]);
+    int cur = 0;
+    for (int it = 0; it < s.prm.inner_iters; ++it) {
+        hipLaunchKernelGGL(k_qgrad<true>, g, b, 0, s.stream, c.n, c.xy, c.off, c.idx, c.geom, s.q,
+                           s.qx[cur], s.qy[cur], s.qx[1 - cur], s.qy[1 - cur]);
+        cur = 1 - cur;
+    }
+    s.qsel = cur;
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(State& s, int slot) {
+    const Cloud& c = *s.cloud;
+    const unsigned nb = grid_for(c.n);
+    const D4* qx = s.qx[s.qsel];
+    const D4* qy = s.qy[s.qsel];
+    if (s.prm.precision == 1)
+        hipLaunchKernelGGL(k_residual<true>, dim3(nb), dim3(kBlock), 0, s.stream, c.n, s.prm.gamma,
+                           s.prm.cfl, c.xy, c.frame, c.type, c.off, c.idx, c.geom, s.U, s.q, qx, qy,
+                           s.R, s.D, s.jv0, s.jv1, s.jv2, s.jv0f, s.jv1f, s.jv2f, s.Df, s.partial,
+                           s.flags);
+    else
+        hipLaunchKernelGGL(k_residual<false>, dim3(nb), dim3(kBlock), 0, s.stream, c.n, s.prm.gamma,
+                           s.prm.cfl, c.xy, c.frame, c.type, c.off, c.idx, c.geom, s.U, s.q, qx, qy,
+                           s.R, s.D, s.jv0, s.jv1, s.jv2, s.jv0f, s.jv1f, s.jv2f, s.Df, s.partial,
+                           s.flags);
+    (void)slot;
+    return hipGetLastError();
+}
+
+hipError_t launch_norm(State& s, int slot) {
+    const Cloud& c = *s.cloud;
+    const double inv_active = c.n_active ? 1.0 / (double)c.n_active : 0.0;
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, s.stream, s.partial,
+                       (int)grid_for(c.n), inv_active, s.res_hist + slot);
+    return hipGetLastError();
+}
+
+template <class T, int MODE>
+static void sweep_t(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv1,
+                    const Vec4<T>* jv2, const T* Dg, Vec4<T>* dU) {
+    const Cloud& c = *s.cloud;
+    for (int k = 0; k < c.ncolour; ++k) {
+        const int col = forward ? k : c.ncolour - 1 - k;
+        const int32_t start = c.h_col_off[col], cnt = c.h_col_off[col + 1] - start;
+        if (!cnt) continue;
+        if (forward)
+            hipLaunchKernelGGL((k_sweep<T, true, MODE>), dim3(grid_for(cnt)), dim3(kBlock), 0,
+                               s.stream, start, cnt, col, c.col_perm, c.xy, c.frame, c.type, c.off,
+                               c.idx, c.colour, c.geom, jv0, jv1, jv2, s.U, s.R, Dg, dU,
+                               s.prm.gamma);
+        else
+            hipLaunchKernelGGL((k_sweep<T, false, MODE>), dim3(grid_for(cnt)), dim3(kBlock), 0,
+                               s.stream, start, cnt, col, c.col_perm, c.xy, c.frame, c.type, c.off,
+                               c.idx, c.colour, c.geom, jv0, jv1, jv2, s.U, s.R, Dg, dU,
+                               s.prm.gamma);
+    }
+}
+
+hipError_t launch_sweep_dir(State& s, bool forward) {
+    if (s.prm.precision == 1)
+        sweep_t<float, 0>(s, forward, s.jv0f, s.jv1f, s.jv2f, s.Df, s.dUf);
+    else if (s.prm.jvp_mode == 1)
+        sweep_t<double, 1>(s, forward, s.jv0, s.jv1, s.jv2, s.D, s.dU);
+    else
+        sweep_t<double, 0>(s, forward, s.jv0, s.jv1, s.jv2, s.D, s.dU);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweeps(State& s) {
+    hipError_t e = launch_sweep_dir(s, true);
+    if (e != hipSuccess) return e;
+    return launch_sweep_dir(s, false);
+}
+
+hipError_t launch_update(State& s) {
+    const Cloud& c = *s.cloud;
+    if (s.prm.precision == 1)
+        hipLaunchKernelGGL(k_update<float>, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream, c.n,
+                           s.prm.gamma, s.U, s.dUf, s.q, s.flags);
+    else
+        hipLaunchKernelGGL(k_update<double>, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream, c.n,
+                           s.prm.gamma, s.U, s.dU, s.q, s.flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_forces(State& s, double* d_out2) {
+    const Cloud& c = *s.cloud;
+    hipLaunchKernelGGL(k_forces, dim3(1), dim3(kBlock), 0, s.stream, c.n_wall, c.wall_list, c.xy,
+                       s.U, s.prm.gamma, c.wall_orient, d_out2);
+    return hipGetLastError();
+}
+
+hipError_t launch_soa_to_aos(const double* soa, D4* aos, int64_t n, hipStream_t st) {
+    if (n) hipLaunchKernelGGL(k_soa_to_aos, dim3(grid_for(n)), dim3(kBlock), 0, st, soa, aos, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_aos_to_soa(const D4* aos, double* soa, int64_t n, hipStream_t st) {
+    if (n)
+        hipLaunchKernelGGL(k_aos_to_soa<double>, dim3(grid_for(n)), dim3(kBlock), 0, st, aos, soa, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_aosf_to_soa(const F4* aos, double* soa, int64_t n, hipStream_t st) {
+    if (n)
+        hipLaunchKernelGGL(k_aos_to_soa<float>, dim3(grid_for(n)), dim3(kBlock), 0, st, aos, soa, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_flags(int32_t* flags, hipStream_t st) {
+    hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, st, flags);
+    return hipGetLastError();
+}
+
+}  // namespace lskum

@@ -1,0 +1,249 @@
+"""Python binding of the MI355X LSKUM library (argument marshalling only).
+
+Every computation runs in ``liblskum.so`` (hand-written HIP for gfx950);
+this module converts arguments, owns nothing but handles, and raises
+``LskumError`` with the library's message on a non-zero status.  Device
+memory and streams may come from PyTorch (tensors' ``data_ptr()``, streams'
+``cuda_stream``); host arrays are numpy.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import cloudgen
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblskum.so")
+
+OK, ERR_ARG, ERR_CONNECTIVITY, ERR_DEGENERATE, ERR_COLOURING = 0, -1, -2, -3, -4
+ERR_NONPHYSICAL, ERR_NOT_CONVERGED, ERR_HIP, ERR_OOM = -5, -6, -7, -8
+JVP_EXACT, JVP_FLUXDIFF = 0, 1
+FP64, MIXED = 0, 1
+
+
+class LskumError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lskum error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("inner_iters", C.c_int32),
+                ("jvp_mode", C.c_int32), ("precision", C.c_int32), ("check_every", C.c_int32),
+                ("tol_rel", C.c_double), ("max_iters", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Report(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("res_fs", C.c_double),
+                ("res_first", C.c_double), ("res_final", C.c_double), ("seconds", C.c_double),
+                ("cl", C.c_double), ("cd", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+# name -> (restype, argtypes); mirrors include/lskum.h
+_SIGS = {
+    "lskum_default_params": (None, [C.c_void_p]),
+    "lskum_cloud_create": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lskum_cloud_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lskum_cloud_colours": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lskum_cloud_destroy": (None, [C.c_void_p]),
+    "lskum_state_create": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]),
+    "lskum_state_destroy": (None, [C.c_void_p]),
+    "lskum_state_set_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lskum_state_set_U": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "lskum_state_get_U": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "lskum_state_get_dU": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "lskum_residual": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
+    "lskum_q_derivatives": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "lskum_lusgs_step": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lskum_step_timed": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lskum_solve": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lskum_forces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lskum_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Loads the in-tree HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2406_07441_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != OK:
+        raise LskumError(code, lib().lskum_last_error().decode())
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().lskum_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data
+
+
+class Cloud:
+    """Device copy of a point cloud (geometry, CSR, colours)."""
+
+    def __init__(self, cloud: cloudgen.Cloud, colours: np.ndarray | None = None):
+        self.src = cloud
+        arrs = [np.ascontiguousarray(cloud.x, np.float64), np.ascontiguousarray(cloud.y, np.float64),
+                np.ascontiguousarray(cloud.type, np.int8), np.ascontiguousarray(cloud.tx, np.float64),
+                np.ascontiguousarray(cloud.ty, np.float64),
+                np.ascontiguousarray(cloud.nbr_off, np.int32),
+                np.ascontiguousarray(cloud.nbr_idx, np.int32)]
+        col = None if colours is None else np.ascontiguousarray(colours, np.int32)
+        h = C.c_void_p()
+        _check(lib().lskum_cloud_create(cloud.n, *[_ptr(a) for a in arrs],
+                                        None if col is None else _ptr(col), C.byref(h)))
+        self.h = h
+        n, nnz, nc, nd = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int64()
+        _check(lib().lskum_cloud_info(h, C.byref(n), C.byref(nnz), C.byref(nc), C.byref(nd)))
+        self.n, self.nnz, self.n_colours, self.n_degenerate = n.value, nnz.value, nc.value, nd.value
+
+    def colours(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.int32)
+        _check(lib().lskum_cloud_colours(self.h, _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lskum_cloud_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class State:
+    """One flow condition on a cloud: U and the iteration's work arrays.
+
+    ``stream`` is a torch.cuda.Stream (or a raw hipStream_t int); by default
+    the library uses a private stream of default priority.
+    """
+
+    def __init__(self, cloud: Cloud, mach: float, aoa_deg: float, params: Params | None = None,
+                 stream=None):
+        self.cloud = cloud
+        self.params = params if params is not None else default_params()
+        handle = None
+        if stream is not None:
+            handle = stream if isinstance(stream, int) else stream.cuda_stream
+        h = C.c_void_p()
+        _check(lib().lskum_state_create(cloud.h, float(mach), float(aoa_deg),
+                                        C.byref(self.params), handle, C.byref(h)))
+        self.h = h
+        self.n = cloud.n
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lskum_state_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: Params):
+        _check(lib().lskum_state_set_params(self.h, C.byref(params)))
+        self.params = params
+
+    # -- fields ----------------------------------------------------------------
+    def set_U(self, U):
+        if isinstance(U, np.ndarray):
+            U = np.ascontiguousarray(U, np.float64)
+            assert U.shape == (4, self.n)
+            _check(lib().lskum_state_set_U(self.h, _ptr(U), 0))
+        else:  # torch tensor on the device
+            import torch
+            assert U.is_cuda and U.dtype == torch.float64 and U.shape == (4, self.n)
+            U = U.contiguous()
+            torch.cuda.current_stream().synchronize()
+            _check(lib().lskum_state_set_U(self.h, U.data_ptr(), 1))
+
+    def _get(self, fn, device: bool):
+        if device:
+            import torch
+            out = torch.empty((4, self.n), dtype=torch.float64, device="cuda")
+            torch.cuda.current_stream().synchronize()
+            _check(fn(self.h, out.data_ptr(), 1))
+            return out
+        out = np.empty((4, self.n))
+        _check(fn(self.h, _ptr(out), 0))
+        return out
+
+    def get_U(self, device: bool = False):
+        return self._get(lib().lskum_state_get_U, device)
+
+    def get_dU(self, device: bool = False):
+        return self._get(lib().lskum_state_get_dU, device)
+
+    # -- hot path ----------------------------------------------------------------
+    def residual(self, want_R: bool = True):
+        res = C.c_double()
+        R = np.empty((4, self.n)) if want_R else None
+        _check(lib().lskum_residual(self.h, None if R is None else _ptr(R), 0, C.byref(res)))
+        return R, res.value
+
+    def q_derivatives(self):
+        qx, qy = np.empty((4, self.n)), np.empty((4, self.n))
+        _check(lib().lskum_q_derivatives(self.h, _ptr(qx), _ptr(qy), 0))
+        return qx, qy
+
+    def step(self, want_res: bool = True):
+        if not want_res:
+            _check(lib().lskum_lusgs_step(self.h, None))
+            return None
+        res = C.c_double()
+        _check(lib().lskum_lusgs_step(self.h, C.byref(res)))
+        return res.value
+
+    PHASES = ("q_derivatives", "residual", "norm", "forward_sweep", "backward_sweep", "update")
+
+    def step_timed(self) -> dict:
+        """One step with per-phase GPU times (ms) from HIP events."""
+        ms = np.zeros(6)
+        _check(lib().lskum_step_timed(self.h, _ptr(ms)))
+        return dict(zip(self.PHASES, ms.tolist()))
+
+    def solve(self, raise_on_error: bool = False) -> Report:
+        rep = Report()
+        code = lib().lskum_solve(self.h, C.byref(rep))
+        if code != OK and (raise_on_error or code not in (ERR_NOT_CONVERGED, ERR_NONPHYSICAL)):
+            _check(code)
+        return rep
+
+    def forces(self):
+        cl, cd = C.c_double(), C.c_double()
+        _check(lib().lskum_forces(self.h, C.byref(cl), C.byref(cd)))
+        return cl.value, cd.value

@@ -1,0 +1,175 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+Bar (FP64): max |X_gpu - X_oracle| / max |X_oracle| <= 1e-11 for the
+residual R, the q-derivatives and the increment dU of one iteration, on the
+same input state; colours bit-exact.  Inputs: the free-stream start and
+oracle states after 1 and 10 iterations of the 160 x 40 O-grid
+(M 0.63, 2 deg) -- several colours, wall/interior/outer points and ragged
+neighbour counts (14/19/24) -- plus a jittered 320 x 96 cloud at M 0.85.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2406_07441_amd import cloudgen as cg
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.fixture(scope="module")
+def lk():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2406_07441_amd import lskum
+    lskum.lib()
+    return lskum
+
+
+class Case:
+    def __init__(self, lk, cloud, mach, aoa, cfl=100.0, inner=1, jvp_mode=0, states=(0, 1, 10)):
+        self.cloud = cloud
+        self.gc = lk.Cloud(cloud)
+        self.colours = self.gc.colours()
+        self.o = O.Oracle(cloud, mach=mach, aoa_deg=aoa, cfl=cfl, inner_iters=inner,
+                          jvp_mode=jvp_mode)
+        self.prm = lk.default_params(cfl=cfl, inner_iters=inner, jvp_mode=jvp_mode)
+        self.st = lk.State(self.gc, mach, aoa, self.prm)
+        U = self.o.free_stream()
+        self.states = {}
+        for it in range(max(states) + 1):
+            if it in states:
+                self.states[it] = U.copy()
+            U, _, _, _ = self.o.iteration(U)
+
+
+@pytest.fixture(scope="module")
+def cfg1(lk):
+    return Case(lk, cg.cloud_6400(), 0.63, 2.0)
+
+
+@pytest.fixture(scope="module")
+def jit(lk):
+    return Case(lk, cg.ogrid(320, 96, r=None, jitter_p=0.04, seed=77), 0.85, 1.0, states=(0, 3))
+
+
+def test_colours_match_algorithm4(cfg1):
+    col, nc = O.colour(cfg1.cloud)
+    assert np.array_equal(cfg1.colours, col)
+    assert cfg1.gc.n_colours == nc
+
+
+def test_free_stream_state_and_anchor(cfg1):
+    U = cfg1.st.get_U()
+    assert rel(U, cfg1.states[0]) < 1e-14
+    _, res = cfg1.o.residual(cfg1.states[0])
+    R, res_gpu = cfg1.st.residual()
+    assert abs(res_gpu - res) <= TOL * res
+
+
+@pytest.mark.parametrize("it", [0, 1, 10])
+def test_q_derivatives_parity(cfg1, it):
+    U = cfg1.states[it]
+    cfg1.st.set_U(U)
+    qx, qy = cfg1.st.q_derivatives()
+    q = O.q_from_U(U)
+    ox, oy = cfg1.o.q_derivatives(q)
+    assert rel(qx, ox) < TOL and rel(qy, oy) < TOL
+
+
+@pytest.mark.parametrize("it", [0, 1, 10])
+def test_residual_parity(cfg1, it):
+    U = cfg1.states[it]
+    cfg1.st.set_U(U)
+    R, res = cfg1.st.residual()
+    Ro, reso = cfg1.o.residual(U)
+    e = rel(R, Ro)
+    print(f"residual it={it} rel err {e:.3e}")
+    assert e < TOL
+    assert abs(res - reso) <= TOL * reso
+
+
+@pytest.mark.parametrize("it", [0, 1, 10])
+def test_iteration_parity_exact_jvp(cfg1, it):
+    U = cfg1.states[it]
+    cfg1.st.set_U(U)
+    res = cfg1.st.step()
+    dU = cfg1.st.get_dU()
+    Un, _, dUo, reso = cfg1.o.iteration(U)
+    e = rel(dU, dUo)
+    print(f"dU it={it} rel err {e:.3e}")
+    assert e < TOL
+    assert abs(res - reso) <= TOL * reso
+    assert rel(cfg1.st.get_U(), Un) < 1e-14
+
+
+def test_iteration_parity_flux_difference(lk, cfg1):
+    prm = lk.default_params(cfl=100.0, inner_iters=1, jvp_mode=lk.JVP_FLUXDIFF)
+    st = lk.State(cfg1.gc, 0.63, 2.0, prm)
+    o = O.Oracle(cfg1.cloud, mach=0.63, aoa_deg=2.0, cfl=100.0, inner_iters=1, jvp_mode=1)
+    for it in (0, 1):
+        U = cfg1.states[it]
+        st.set_U(U)
+        st.step()
+        _, _, dUo, _ = o.iteration(U)
+        e = rel(st.get_dU(), dUo)
+        print(f"FD dU it={it} rel err {e:.3e}")
+        assert e < 1e-10
+
+
+def test_jittered_transonic_parity(jit):
+    for it in (0, 3):
+        U = jit.states[it]
+        jit.st.set_U(U)
+        R, _ = jit.st.residual()
+        Ro, _ = jit.o.residual(U)
+        assert rel(R, Ro) < TOL
+        jit.st.set_U(U)
+        jit.st.step()
+        _, _, dUo, _ = jit.o.iteration(U)
+        e = rel(jit.st.get_dU(), dUo)
+        print(f"jittered dU it={it} rel err {e:.3e}")
+        assert e < TOL
+
+
+def test_multi_step_matches_oracle_iterations(cfg1):
+    cfg1.st.set_U(cfg1.states[0])
+    for _ in range(10):
+        cfg1.st.step(want_res=False)
+    assert rel(cfg1.st.get_U(), cfg1.states[10]) < 1e-12
+
+
+def test_solve_graph_replay_matches_eager_steps(lk, cfg1):
+    prm = lk.default_params(cfl=100.0, inner_iters=1, check_every=5, max_iters=20, tol_rel=0.0)
+    a = lk.State(cfg1.gc, 0.63, 2.0, prm)
+    rep = a.solve()
+    assert rep.iters == 20 and rep.status == lk.ERR_NOT_CONVERGED
+    b = lk.State(cfg1.gc, 0.63, 2.0, prm)
+    for _ in range(20):
+        b.step(want_res=False)
+    assert np.array_equal(a.get_U(), b.get_U())
+    # replaying the graph again continues deterministically
+    a2 = lk.State(cfg1.gc, 0.63, 2.0, prm)
+    a2.solve()
+    assert np.array_equal(a.get_U(), a2.get_U())
+
+
+def test_device_pointer_round_trip(lk, cfg1):
+    import torch
+    U = torch.tensor(cfg1.states[1], device="cuda")
+    cfg1.st.set_U(U)
+    back = cfg1.st.get_U(device=True)
+    assert torch.equal(back, U)
+
+
+def test_nonphysical_state_is_reported(lk, cfg1):
+    U = cfg1.states[0].copy()
+    U[0, 100] = -1.0
+    with pytest.raises(lk.LskumError) as ei:
+        cfg1.st.set_U(U)
+    assert ei.value.code == lk.ERR_NONPHYSICAL
