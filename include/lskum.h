@@ -76,7 +76,11 @@ typedef struct {
     int32_t check_every;/* lskum_solve reads the residual every k steps */
     double tol_rel;     /* lskum_solve stops when res <= tol_rel * res_fs */
     int32_t max_iters;  /* lskum_solve iteration cap */
-    int32_t reserved;
+    int32_t sweep_lanes;    /* lanes per point in the sweep kernels: 1, 2, 4, 8;
+                               0 = library choice */
+    int32_t residual_lanes; /* lanes per point in the residual kernel: 1, 2, 4,
+                               8; 0 = library choice */
+    int32_t reserved;       /* must be 0 */
 } lskum_params;
 
 typedef struct {
@@ -90,7 +94,8 @@ typedef struct {
 } lskum_report;
 
 /* Fills p with the defaults: gamma 1.4, cfl 100, inner_iters 1, exact JVP,
- * fp64, check_every 10, tol_rel 1e-8, max_iters 20000. */
+ * fp64, check_every 10, tol_rel 1e-8, max_iters 20000, lanes 0 (library
+ * choice). */
 void lskum_default_params(lskum_params* p);
 
 /* Creates a cloud on the current HIP device from host arrays of n points.

@@ -60,6 +60,10 @@ void free_cloud(lskum::Cloud& c) {
     (void)hipFree(c.col_perm);
     (void)hipFree(c.wall_list);
     (void)hipFree(c.geom);
+    (void)hipFree(c.lo_off);
+    (void)hipFree(c.lo_idx);
+    (void)hipFree(c.up_off);
+    (void)hipFree(c.up_idx);
     c = lskum::Cloud{};
 }
 
@@ -153,14 +157,26 @@ int check_params(const lskum_params* p) {
         (p->jvp_mode != 0 && p->jvp_mode != 1) || (p->precision != 0 && p->precision != 1) ||
         p->check_every < 1 || p->check_every > 4096 || p->max_iters < 0 || !(p->tol_rel >= 0.0))
         return fail(LSKUM_ERR_ARG, "invalid lskum_params");
+    auto lanes_ok = [](int l) { return l == 0 || l == 1 || l == 2 || l == 4 || l == 8; };
+    if (!lanes_ok(p->sweep_lanes) || !lanes_ok(p->residual_lanes) || p->reserved != 0)
+        return fail(LSKUM_ERR_ARG, "lanes must be 0, 1, 2, 4 or 8 and reserved 0");
     if (p->precision == 1 && p->jvp_mode == 1)
         return fail(LSKUM_ERR_ARG, "mixed precision supports the exact Jacobian products only");
     return LSKUM_OK;
 }
 
 lskum::Params to_params(const lskum_params* p) {
-    return lskum::Params{p->gamma,     p->cfl,         p->inner_iters, p->jvp_mode,
-                         p->precision, p->check_every, p->tol_rel,     p->max_iters};
+    return lskum::Params{p->gamma,       p->cfl,         p->inner_iters, p->jvp_mode,
+                         p->precision,   p->check_every, p->tol_rel,     p->max_iters,
+                         p->sweep_lanes, p->residual_lanes};
+}
+
+// Lanes per point: the caller's choice, else 8 for the latency-bound sweeps
+// and 2 for the compute-bound residual (measured best on the 163,840-point
+// transonic cloud, FP64 and mixed).
+void apply_lanes(lskum::State& s) {
+    s.sweep_lanes = s.prm.sweep_lanes ? s.prm.sweep_lanes : 8;
+    s.residual_lanes = s.prm.residual_lanes ? s.prm.residual_lanes : 2;
 }
 
 int read_flags(lskum::State& s, int32_t* h) {
@@ -287,6 +303,20 @@ int lskum_cloud_create(int64_t n, const double* x, const double* y, const int8_t
     }
     c.wall_orient = area2 >= 0.0 ? 1.0 : -1.0;
 
+    // lower/upper colour neighbour lists (CSR order kept)
+    std::vector<int32_t> lo_off(n + 1, 0), up_off(n + 1, 0), lo_idx, up_idx;
+    lo_idx.reserve(nnz / 2 + 1);
+    up_idx.reserve(nnz / 2 + 1);
+    for (int64_t p = 0; p < n; ++p) {
+        for (int32_t e = nbr_off[p]; e < nbr_off[p + 1]; ++e) {
+            const int32_t i = nbr_idx[e];
+            if (c.h_colour[i] < c.h_colour[p]) lo_idx.push_back(i);
+            else up_idx.push_back(i);
+        }
+        lo_off[p + 1] = (int32_t)lo_idx.size();
+        up_off[p + 1] = (int32_t)up_idx.size();
+    }
+
     std::vector<lskum::D2> hxy(n), hfr(n);
     for (int64_t p = 0; p < n; ++p) {
         hxy[p] = {x[p], y[p]};
@@ -315,6 +345,10 @@ int lskum_cloud_create(int64_t n, const double* x, const double* y, const int8_t
     chk(dalloc(&c.col_perm, n));
     chk(dalloc(&c.wall_list, wall.size()));
     chk(dalloc(&c.geom, n));
+    chk(dalloc(&c.lo_off, n + 1));
+    chk(dalloc(&c.up_off, n + 1));
+    chk(dalloc(&c.lo_idx, lo_idx.size()));
+    chk(dalloc(&c.up_idx, up_idx.size()));
     if (e == hipSuccess) {
         chk(hipMemcpy(c.xy, hxy.data(), n * sizeof(lskum::D2), hipMemcpyHostToDevice));
         chk(hipMemcpy(c.frame, hfr.data(), n * sizeof(lskum::D2), hipMemcpyHostToDevice));
@@ -323,6 +357,14 @@ int lskum_cloud_create(int64_t n, const double* x, const double* y, const int8_t
         chk(hipMemcpy(c.idx, nbr_idx, nnz * sizeof(int32_t), hipMemcpyHostToDevice));
         chk(hipMemcpy(c.colour, c.h_colour.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
         chk(hipMemcpy(c.col_perm, perm.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
+        chk(hipMemcpy(c.lo_off, lo_off.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+        chk(hipMemcpy(c.up_off, up_off.data(), (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+        if (!lo_idx.empty())
+            chk(hipMemcpy(c.lo_idx, lo_idx.data(), lo_idx.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+        if (!up_idx.empty())
+            chk(hipMemcpy(c.up_idx, up_idx.data(), up_idx.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
         if (!wall.empty())
             chk(hipMemcpy(c.wall_list, wall.data(), wall.size() * sizeof(int32_t),
                           hipMemcpyHostToDevice));
@@ -381,6 +423,7 @@ int lskum_state_create(const lskum_cloud* cl, double mach, double aoa_deg,
     lskum::State& s = so->s;
     s.cloud = &cl->c;
     s.prm = to_params(prm);
+    apply_lanes(s);
     s.mach = mach;
     s.aoa_deg = aoa_deg;
     s.stream = (hipStream_t)hip_stream;
@@ -394,7 +437,7 @@ int lskum_state_create(const lskum_cloud* cl, double mach, double aoa_deg,
         s.own_stream = true;
     }
     const int64_t n = cl->c.n;
-    s.nblk_partial = (int)((n + 255) / 256);
+    s.partial_cap = (int)((n + 255) / 256) * 8 + 2;  // residual blocks at 8 lanes per point
     s.res_cap = 4096;
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t r) {
@@ -417,7 +460,7 @@ int lskum_state_create(const lskum_cloud* cl, double mach, double aoa_deg,
     chk(dalloc(&s.jv2f, n));
     chk(dalloc(&s.dUf, n));
     chk(dalloc(&s.Df, n));
-    chk(dalloc(&s.partial, std::max(s.nblk_partial, 2)));
+    chk(dalloc(&s.partial, s.partial_cap));
     chk(dalloc(&s.res_hist, s.res_cap));
     chk(dalloc(&s.flags, 4));
     if (e == hipSuccess) chk(lskum::launch_clear_flags(s.flags, s.stream));
@@ -460,8 +503,15 @@ int lskum_state_set_params(lskum_state* so, const lskum_params* prm) {
         (void)hipGraphExecDestroy(s.graph);
         s.graph = nullptr;
     }
+    const bool same_lanes = np.sweep_lanes == s.prm.sweep_lanes &&
+                            np.residual_lanes == s.prm.residual_lanes;
+    if (s.graph && !same_lanes) {
+        (void)hipGraphExecDestroy(s.graph);
+        s.graph = nullptr;
+    }
     if (np.precision != s.prm.precision) s.have_dU = false;
     s.prm = np;
+    apply_lanes(s);
     return LSKUM_OK;
 }
 

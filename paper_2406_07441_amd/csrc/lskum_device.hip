@@ -50,24 +50,28 @@ __device__ __forceinline__ double dot_nc(double ax, double ay, double bx, double
 }
 
 struct Prim {
-    double rho, u1, u2, p, beta, sb;
+    double rho, u1, u2, p, sb, isb, rhoE;  // sb = sqrt(beta), isb = 1/sqrt(beta)
 };
 
 // Primitive state of a (reconstructed) q vector, eq. (14) inverted:
 // beta = -q4/2, u = (q2, q3)/(2 beta), rho = exp(q1 + beta |u|^2) beta^(-1/(gamma-1)),
-// p = rho/(2 beta).  For gamma = 1.4 the power is 1/(beta^2 sqrt(beta)).
+// p = rho/(2 beta).  Division free: with r = 1/sqrt(beta), 1/(2 beta) = r^2/2 and,
+// for gamma = 1.4, beta^(-5/2) = r^5.
 __device__ __forceinline__ Prim prim_from_q(const D4& q, double inv_gm1, bool g14) {
     Prim w;
     const double beta = -0.5 * q.w;
-    const double i2b = -1.0 / q.w;
+    const double r = rsqrt(beta);
+    const double i2b = 0.5 * r * r;
     w.u1 = q.y * i2b;
     w.u2 = q.z * i2b;
-    const double sb = sqrt(beta);
-    const double e = exp(q.x + beta * (w.u1 * w.u1 + w.u2 * w.u2));
-    w.rho = g14 ? e / (beta * beta * sb) : e * exp(-inv_gm1 * log(beta));
+    const double usq = w.u1 * w.u1 + w.u2 * w.u2;
+    const double e = exp(q.x + beta * usq);
+    const double r2 = r * r;
+    w.rho = g14 ? e * (r2 * r2 * r) : e * exp(-inv_gm1 * log(beta));
     w.p = w.rho * i2b;
-    w.beta = beta;
-    w.sb = sb;
+    w.sb = beta * r;
+    w.isb = r;
+    w.rhoE = w.p * inv_gm1 + 0.5 * w.rho * usq;
     return w;
 }
 
@@ -76,11 +80,11 @@ __device__ __forceinline__ Prim prim_from_q(const D4& q, double inv_gm1, bool g1
 template <int DIR>
 __device__ __forceinline__ void split_flux(const Prim& w, double dx, double dy, double sg,
                                            double inv_gm1, double G[4]) {
+    (void)inv_gm1;
     const double ud = DIR == 0 ? w.u1 : (DIR == 1 ? w.u2 : w.u1 * dx + w.u2 * dy);
     const double S = ud * w.sb;
     const double A = 0.5 * (1.0 + sg * erf(S));
-    const double B = exp(-(S * S)) * (0.5 * kInvSqrtPi) / w.sb;
-    const double rhoE = w.p * inv_gm1 + 0.5 * w.rho * (w.u1 * w.u1 + w.u2 * w.u2);
+    const double B = exp(-(S * S)) * (0.5 * kInvSqrtPi) * w.isb;
     const double mass = w.rho * (ud * A + sg * B);
     const double pA = w.p * A;
     G[0] = mass;
@@ -94,7 +98,7 @@ __device__ __forceinline__ void split_flux(const Prim& w, double dx, double dy, 
         G[1] = pA * dx + w.u1 * mass;
         G[2] = pA * dy + w.u2 * mass;
     }
-    G[3] = (rhoE + w.p) * ud * A + sg * (rhoE + 0.5 * w.p) * B;
+    G[3] = (w.rhoE + w.p) * ud * A + sg * (w.rhoE + 0.5 * w.p) * B;
 }
 
 template <int DIR>
@@ -301,7 +305,10 @@ __global__ void __launch_bounds__(kBlock) k_qgrad(int64_t n, const D2* __restric
 // Residual (eq. 11 with the q~ reconstruction of eq. 15), local time step,
 // scalar diagonal (eq. 25, 34-35) and the sweep linearisation data.
 // ---------------------------------------------------------------------------
-template <bool MIXED>
+// LANES consecutive lanes share one point: each takes every LANES-th
+// neighbour, the four residual sums are combined with cross-lane shuffles and
+// the first lane finishes the point.
+template <bool MIXED, int LANES>
 __global__ void __launch_bounds__(kBlock) k_residual(
     int64_t n, double gamma, double cfl, const D2* __restrict__ xy, const D2* __restrict__ frame,
     const int8_t* __restrict__ type, const int32_t* __restrict__ off,
@@ -313,22 +320,24 @@ __global__ void __launch_bounds__(kBlock) k_residual(
     double* __restrict__ partial, int32_t* __restrict__ flags) {
     __shared__ double red[kBlock / 64];
     const int lb = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t p = (int64_t)lb * blockDim.x + threadIdx.x;
+    const int64_t gt = (int64_t)lb * blockDim.x + threadIdx.x;
+    const int64_t p = gt / LANES;
+    const int lane = (int)(gt % LANES);
     const double inv_gm1 = 1.0 / (gamma - 1.0);
     const bool g14 = gamma == 1.4;
-    double rr = 0.0;  // R_rho^2 of this point (non-outer)
+    double rr = 0.0;  // R_rho^2 of this point (non-outer), first lane only
     if (p < n) {
         const int8_t ty = type[p];
         const D2 r0 = xy[p];
+        const D2 t = frame[p];
         double Rp[4] = {0, 0, 0, 0};
-        bool bad = false;
+        int bad = 0;
         if (ty != kOuter) {
             const D4 q0 = q[p], gx0 = qx[p], gy0 = qy[p];
             const PointGeom& G = geom[p];
             const D2 c0 = G.split[0], c1 = G.split[1], c2 = G.split[2], c3 = G.split[3];
-            const D2 t = frame[p];
-            const int32_t e0 = off[p], e1 = off[p + 1];
-            for (int32_t e = e0; e < e1; ++e) {
+            const int32_t e1 = off[p + 1];
+            for (int32_t e = off[p] + lane; e < e1; e += LANES) {
                 const int32_t i = idx[e];
                 const D2 ri = xy[i];
                 const double dx = ri.x - r0.x, dy = ri.y - r0.y;
@@ -374,56 +383,63 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                     }
                 }
             }
+        }
+#pragma unroll
+        for (int o = LANES / 2; o > 0; o >>= 1) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Rp[v] += __shfl_xor(Rp[v], o, 64);
+            bad |= __shfl_xor(bad, o, 64);
+        }
+        if (lane == 0) {
             if (ty == kWall) {  // drop the normal-momentum component
                 const double nx = -t.y, ny = t.x;
                 const double mn = Rp[1] * nx + Rp[2] * ny;
                 Rp[1] -= mn * nx;
                 Rp[2] -= mn * ny;
             }
-            rr = Rp[0] * Rp[0];
-        }
-        R[p] = {Rp[0], Rp[1], Rp[2], Rp[3]};
+            if (ty != kOuter) rr = Rp[0] * Rp[0];
+            R[p] = {Rp[0], Rp[1], Rp[2], Rp[3]};
 
-        // linearisation data at the current state, local time step, diagonal
-        const D4 u = U[p];
-        const double rho = u.x, irho = 1.0 / rho;
-        const double u1 = u.y * irho, u2 = u.z * irho;
-        const double usq = u1 * u1 + u2 * u2;
-        const double pr = (gamma - 1.0) * (u.w - 0.5 * rho * usq);
-        const double beta = 0.5 * rho / pr;
-        const double sb = sqrt(beta);
-        const double sx = u1 * sb, sy = u2 * sb;
-        const D4 j0 = {rho, u1, u2, pr};
-        const D4 j1 = {sb, beta, irho, 1.0 / pr};
-        const D4 j2 = {erf(sx), exp(-(sx * sx)), erf(sy), exp(-(sy * sy))};
-        const double a = sqrt(gamma * pr / rho);
-        const PointGeom& G = geom[p];
-        const double dt = cfl * G.lsq.w / (sqrt(usq) + a);
-        double Dp = 1.0 / dt;
-        if (ty == kWall) {
-            const D2 t = frame[p];
-            const double ut = u1 * t.x + u2 * t.y, un = -u1 * t.y + u2 * t.x;
-            Dp -= G.ls1.x * fmax(ut + a, 0.0);
-            Dp += G.ls1.y * fmax(a - ut, 0.0);
-            Dp += G.ls1.z * fmax(a - un, 0.0);
-        } else if (ty != kOuter) {
-            Dp -= G.ls1.x * fmax(u1 + a, 0.0);
-            Dp += G.ls1.y * fmax(a - u1, 0.0);
-            Dp -= G.ls1.z * fmax(u2 + a, 0.0);
-            Dp += G.ls1.w * fmax(a - u2, 0.0);
+            // linearisation data at the current state, local time step, diagonal
+            const D4 u = U[p];
+            const double rho = u.x, irho = 1.0 / rho;
+            const double u1 = u.y * irho, u2 = u.z * irho;
+            const double usq = u1 * u1 + u2 * u2;
+            const double pr = (gamma - 1.0) * (u.w - 0.5 * rho * usq);
+            const double beta = 0.5 * rho / pr;
+            const double sb = sqrt(beta);
+            const double sx = u1 * sb, sy = u2 * sb;
+            const D4 j0 = {rho, u1, u2, pr};
+            const D4 j1 = {sb, beta, irho, 1.0 / pr};
+            const D4 j2 = {erf(sx), exp(-(sx * sx)), erf(sy), exp(-(sy * sy))};
+            const double a = sqrt(gamma * pr / rho);
+            const PointGeom& G = geom[p];
+            const double dt = cfl * G.lsq.w / (sqrt(usq) + a);
+            double Dp = 1.0 / dt;
+            if (ty == kWall) {
+                const double ut = u1 * t.x + u2 * t.y, un = -u1 * t.y + u2 * t.x;
+                Dp -= G.ls1.x * fmax(ut + a, 0.0);
+                Dp += G.ls1.y * fmax(a - ut, 0.0);
+                Dp += G.ls1.z * fmax(a - un, 0.0);
+            } else if (ty != kOuter) {
+                Dp -= G.ls1.x * fmax(u1 + a, 0.0);
+                Dp += G.ls1.y * fmax(a - u1, 0.0);
+                Dp -= G.ls1.z * fmax(u2 + a, 0.0);
+                Dp += G.ls1.w * fmax(a - u2, 0.0);
+            }
+            if (MIXED) {
+                jv0f[p] = {(float)j0.x, (float)j0.y, (float)j0.z, (float)j0.w};
+                jv1f[p] = {(float)j1.x, (float)j1.y, (float)j1.z, (float)j1.w};
+                jv2f[p] = {(float)j2.x, (float)j2.y, (float)j2.z, (float)j2.w};
+                Df[p] = (float)Dp;
+            } else {
+                jv0[p] = j0;
+                jv1[p] = j1;
+                jv2[p] = j2;
+                Dg[p] = Dp;
+            }
+            if (bad || !(rho > 0.0) || !(pr > 0.0)) flags[0] = 1;
         }
-        if (MIXED) {
-            jv0f[p] = {(float)j0.x, (float)j0.y, (float)j0.z, (float)j0.w};
-            jv1f[p] = {(float)j1.x, (float)j1.y, (float)j1.z, (float)j1.w};
-            jv2f[p] = {(float)j2.x, (float)j2.y, (float)j2.z, (float)j2.w};
-            Df[p] = (float)Dp;
-        } else {
-            jv0[p] = j0;
-            jv1[p] = j1;
-            jv2[p] = j2;
-            Dg[p] = Dp;
-        }
-        if (bad || !(rho > 0.0) || !(pr > 0.0)) flags[0] = 1;
     }
     // deterministic block reduction of R_rho^2
     for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o, 64);
@@ -539,124 +555,131 @@ __device__ __forceinline__ Lin<T> load_lin(const Vec4<T>* jv0, const Vec4<T>* jv
     return Lin<T>{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 }
 
+// Contribution sum_k w_i^k A_k(U_i) dU_i of neighbour i to point p's sweep
+// sum (eq. 22-27): interior points use the x and y split the neighbour
+// falls in, wall points the t split and, on the fluid side, the n- split.
+template <class T, int MODE>
+__device__ __forceinline__ void sweep_contrib(int8_t ty, const D2& t, const D2& c0, const D2& c1,
+                                              const D2& c2, const D2& c3, double dx, double dy,
+                                              int32_t i, const Vec4<T>* __restrict__ jv0,
+                                              const Vec4<T>* __restrict__ jv1,
+                                              const Vec4<T>* __restrict__ jv2,
+                                              const D4* __restrict__ U,
+                                              const Vec4<T>* __restrict__ dU, double gamma,
+                                              T acc[4]) {
+    const T gm1 = T(gamma - 1.0), inv_gm1 = T(1.0 / (gamma - 1.0));
+    const Vec4<T> di = dU[i];
+    const T dv[4] = {di.x, di.y, di.z, di.w};
+    const Lin<T> L = load_lin(jv0, jv1, i);
+    T J[4];
+    if (ty == kWall) {
+        const double ds = dot_nc(dx, dy, t.x, t.y);
+        const double dn = dot_nc(dx, dy, -t.y, t.x);
+        // wall-frame directions: erf/exp at the neighbour state are formed here
+        if (ds != 0.0) {
+            const D2 cc = ds < 0.0 ? c0 : c1;
+            const double sg = ds < 0.0 ? 1.0 : -1.0;
+            const T w = T(cc.x * ds + cc.y * dn);
+            if constexpr (MODE == 1) {
+                const double S = (L.u1 * t.x + L.u2 * t.y) * L.sb;
+                jvp_fluxdiff(L, erf(S), exp(-(S * S)), U[i], t.x, t.y, sg, dv, gamma,
+                             1.0 / (gamma - 1.0), J);
+            } else {
+                const T S = (L.u1 * T(t.x) + L.u2 * T(t.y)) * L.sb;
+                jvp_exact<T>(L, erf(S), exp(-(S * S)), T(t.x), T(t.y), T(sg), dv, gm1, inv_gm1, J);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
+        }
+        if (dn > 0.0) {
+            const T w = T(c2.x * dn + c2.y * ds);
+            if constexpr (MODE == 1) {
+                const double S = (-L.u1 * t.y + L.u2 * t.x) * L.sb;
+                jvp_fluxdiff(L, erf(S), exp(-(S * S)), U[i], -t.y, t.x, -1.0, dv, gamma,
+                             1.0 / (gamma - 1.0), J);
+            } else {
+                const T S = (-L.u1 * T(t.y) + L.u2 * T(t.x)) * L.sb;
+                jvp_exact<T>(L, erf(S), exp(-(S * S)), T(-t.y), T(t.x), T(-1), dv, gm1, inv_gm1, J);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
+        }
+        return;
+    }
+    const Vec4<T> k2 = jv2[i];
+    if (dx != 0.0) {
+        const D2 cc = dx < 0.0 ? c0 : c1;
+        const T sg = dx < 0.0 ? T(1) : T(-1);
+        const T w = T(cc.x * dx + cc.y * dy);
+        if constexpr (MODE == 1)
+            jvp_fluxdiff(L, k2.x, k2.y, U[i], 1.0, 0.0, sg, dv, gamma, 1.0 / (gamma - 1.0), J);
+        else
+            jvp_exact<T>(L, k2.x, k2.y, T(1), T(0), sg, dv, gm1, inv_gm1, J);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
+    }
+    if (dy != 0.0) {
+        const D2 cc = dy < 0.0 ? c2 : c3;
+        const T sg = dy < 0.0 ? T(1) : T(-1);
+        const T w = T(cc.x * dy + cc.y * dx);
+        if constexpr (MODE == 1)
+            jvp_fluxdiff(L, k2.z, k2.w, U[i], 0.0, 1.0, sg, dv, gamma, 1.0 / (gamma - 1.0), J);
+        else
+            jvp_exact<T>(L, k2.z, k2.w, T(0), T(1), sg, dv, gm1, inv_gm1, J);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
+    }
+}
+
 // One colour phase of a sweep (eq. 27).  FWD: dU*_0 = -(R_0 + sum_lower w A dU*) / D_0;
 // backward: dU_0 = dU*_0 - (sum_upper w A dU) / D_0.  MODE 0 exact tangent,
 // 1 flux difference.  T is the arithmetic of the products and increments.
-template <class T, bool FWD, int MODE>
+// LANES consecutive lanes share one point: each walks every LANES-th entry of
+// the point's lower (forward) or upper (backward) neighbour list, and the
+// partial sums are combined with cross-lane shuffles.
+template <class T, bool FWD, int MODE, int LANES>
 __global__ void __launch_bounds__(kBlock) k_sweep(
-    int32_t start, int32_t count, int32_t c, const int32_t* __restrict__ col_perm,
+    int32_t start, int32_t count, const int32_t* __restrict__ col_perm,
     const D2* __restrict__ xy, const D2* __restrict__ frame, const int8_t* __restrict__ type,
-    const int32_t* __restrict__ off, const int32_t* __restrict__ idx,
-    const int32_t* __restrict__ colour, const PointGeom* __restrict__ geom,
-    const Vec4<T>* __restrict__ jv0, const Vec4<T>* __restrict__ jv1,
-    const Vec4<T>* __restrict__ jv2, const D4* __restrict__ U, const D4* __restrict__ R,
-    const T* __restrict__ Dg, Vec4<T>* __restrict__ dU, double gamma) {
-    const int t_ = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (t_ >= count) return;
-    const int32_t p = col_perm[start + t_];
+    const int32_t* __restrict__ loff, const int32_t* __restrict__ lidx,
+    const PointGeom* __restrict__ geom, const Vec4<T>* __restrict__ jv0,
+    const Vec4<T>* __restrict__ jv1, const Vec4<T>* __restrict__ jv2,
+    const D4* __restrict__ U, const D4* __restrict__ R, const T* __restrict__ Dg,
+    Vec4<T>* __restrict__ dU, double gamma) {
+    const int gt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int pt = gt / LANES, lane = gt % LANES;
+    if (pt >= count) return;  // uniform over the lanes of a point
+    const int32_t p = col_perm[start + pt];
     const int8_t ty = type[p];
     if (ty == kOuter) {
-        if (FWD) dU[p] = {T(0), T(0), T(0), T(0)};
+        if (FWD && lane == 0) dU[p] = {T(0), T(0), T(0), T(0)};
         return;
     }
-    const T gm1 = T(gamma - 1.0), inv_gm1 = T(1.0 / (gamma - 1.0));
     T acc[4] = {T(0), T(0), T(0), T(0)};
-    if (FWD) {
-        const D4 r = R[p];
-        acc[0] = T(r.x); acc[1] = T(r.y); acc[2] = T(r.z); acc[3] = T(r.w);
-    }
     const D2 r0 = xy[p];
     const PointGeom& G = geom[p];
     const D2 c0 = G.split[0], c1 = G.split[1], c2 = G.split[2], c3 = G.split[3];
     const D2 t = frame[p];
-    const int32_t e0 = off[p], e1 = off[p + 1];
-    for (int32_t e = e0; e < e1; ++e) {
-        const int32_t i = idx[e];
-        const int32_t ci = colour[i];
-        if (FWD ? !(ci < c) : !(ci > c)) continue;
+    const int32_t e1 = loff[p + 1];
+    for (int32_t e = loff[p] + lane; e < e1; e += LANES) {
+        const int32_t i = lidx[e];
         const D2 ri = xy[i];
-        const double dx = ri.x - r0.x, dy = ri.y - r0.y;
-        const Vec4<T> di = dU[i];
-        const T dv[4] = {di.x, di.y, di.z, di.w};
-        const Lin<T> L = load_lin(jv0, jv1, i);
-        T J[4];
-        if (ty == kWall) {
-            const double ds = dot_nc(dx, dy, t.x, t.y);
-            const double dn = dot_nc(dx, dy, -t.y, t.x);
-            // directions of the wall frame: erf/exp at the neighbour state are formed here
-            if (ds != 0.0) {
-                const D2 cc = ds < 0.0 ? c0 : c1;
-                const double sg = ds < 0.0 ? 1.0 : -1.0;
-                const T w = T(cc.x * ds + cc.y * dn);
-                if constexpr (MODE == 1) {
-                    const Lin<double>& Ld = reinterpret_cast<const Lin<double>&>(L);
-                    const double S = (Ld.u1 * t.x + Ld.u2 * t.y) * Ld.sb;
-                    jvp_fluxdiff(Ld, erf(S), exp(-(S * S)), U[i], t.x, t.y, sg,
-                                 reinterpret_cast<const double*>(dv), gamma, 1.0 / (gamma - 1.0),
-                                 reinterpret_cast<double*>(J));
-                } else {
-                    const T S = (L.u1 * T(t.x) + L.u2 * T(t.y)) * L.sb;
-                    jvp_exact<T>(L, erf(S), exp(-(S * S)), T(t.x), T(t.y), T(sg), dv, gm1,
-                                 inv_gm1, J);
-                }
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
-            }
-            if (dn > 0.0) {
-                const T w = T(c2.x * dn + c2.y * ds);
-                if constexpr (MODE == 1) {
-                    const Lin<double>& Ld = reinterpret_cast<const Lin<double>&>(L);
-                    const double S = (-Ld.u1 * t.y + Ld.u2 * t.x) * Ld.sb;
-                    jvp_fluxdiff(Ld, erf(S), exp(-(S * S)), U[i], -t.y, t.x, -1.0,
-                                 reinterpret_cast<const double*>(dv), gamma, 1.0 / (gamma - 1.0),
-                                 reinterpret_cast<double*>(J));
-                } else {
-                    const T S = (-L.u1 * T(t.y) + L.u2 * T(t.x)) * L.sb;
-                    jvp_exact<T>(L, erf(S), exp(-(S * S)), T(-t.y), T(t.x), T(-1), dv, gm1,
-                                 inv_gm1, J);
-                }
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
-            }
-        } else {
-            const Vec4<T> k2 = jv2[i];
-            if (dx != 0.0) {
-                const D2 cc = dx < 0.0 ? c0 : c1;
-                const T sg = dx < 0.0 ? T(1) : T(-1);
-                const T w = T(cc.x * dx + cc.y * dy);
-                if constexpr (MODE == 1) {
-                    jvp_fluxdiff(reinterpret_cast<const Lin<double>&>(L), (double)k2.x,
-                                 (double)k2.y, U[i], 1.0, 0.0, (double)sg,
-                                 reinterpret_cast<const double*>(dv), gamma, 1.0 / (gamma - 1.0),
-                                 reinterpret_cast<double*>(J));
-                } else {
-                    jvp_exact<T>(L, k2.x, k2.y, T(1), T(0), sg, dv, gm1, inv_gm1, J);
-                }
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
-            }
-            if (dy != 0.0) {
-                const D2 cc = dy < 0.0 ? c2 : c3;
-                const T sg = dy < 0.0 ? T(1) : T(-1);
-                const T w = T(cc.x * dy + cc.y * dx);
-                if constexpr (MODE == 1) {
-                    jvp_fluxdiff(reinterpret_cast<const Lin<double>&>(L), (double)k2.z,
-                                 (double)k2.w, U[i], 0.0, 1.0, (double)sg,
-                                 reinterpret_cast<const double*>(dv), gamma, 1.0 / (gamma - 1.0),
-                                 reinterpret_cast<double*>(J));
-                } else {
-                    jvp_exact<T>(L, k2.z, k2.w, T(0), T(1), sg, dv, gm1, inv_gm1, J);
-                }
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
-            }
-        }
+        sweep_contrib<T, MODE>(ty, t, c0, c1, c2, c3, ri.x - r0.x, ri.y - r0.y, i, jv0, jv1, jv2,
+                               U, dU, gamma, acc);
     }
+#pragma unroll
+    for (int o = LANES / 2; o > 0; o >>= 1)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] += __shfl_xor(acc[v], o, 64);
+    if (lane != 0) return;
     const T iD = T(1) / Dg[p];
     T out[4];
     if (FWD) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) out[v] = -acc[v] * iD;
+        const D4 r = R[p];
+        out[0] = -(T(r.x) + acc[0]) * iD;
+        out[1] = -(T(r.y) + acc[1]) * iD;
+        out[2] = -(T(r.z) + acc[2]) * iD;
+        out[3] = -(T(r.w) + acc[3]) * iD;
     } else {
         const Vec4<T> d0 = dU[p];
         out[0] = d0.x - acc[0] * iD;
@@ -812,22 +835,33 @@ hipError_t launch_q_derivatives(State& s) {
     return hipGetLastError();
 }
 
-hipError_t launch_residual(State& s, int slot) {
+template <bool MIXED, int LANES>
+static void residual_lanes(State& s) {
     const Cloud& c = *s.cloud;
-    const unsigned nb = grid_for(c.n);
-    const D4* qx = s.qx[s.qsel];
-    const D4* qy = s.qy[s.qsel];
-    if (s.prm.precision == 1)
-        hipLaunchKernelGGL(k_residual<true>, dim3(nb), dim3(kBlock), 0, s.stream, c.n, s.prm.gamma,
-                           s.prm.cfl, c.xy, c.frame, c.type, c.off, c.idx, c.geom, s.U, s.q, qx, qy,
-                           s.R, s.D, s.jv0, s.jv1, s.jv2, s.jv0f, s.jv1f, s.jv2f, s.Df, s.partial,
-                           s.flags);
-    else
-        hipLaunchKernelGGL(k_residual<false>, dim3(nb), dim3(kBlock), 0, s.stream, c.n, s.prm.gamma,
-                           s.prm.cfl, c.xy, c.frame, c.type, c.off, c.idx, c.geom, s.U, s.q, qx, qy,
-                           s.R, s.D, s.jv0, s.jv1, s.jv2, s.jv0f, s.jv1f, s.jv2f, s.Df, s.partial,
-                           s.flags);
+    const unsigned nb = grid_for(c.n * LANES);
+    hipLaunchKernelGGL((k_residual<MIXED, LANES>), dim3(nb), dim3(kBlock), 0, s.stream, c.n,
+                       s.prm.gamma, s.prm.cfl, c.xy, c.frame, c.type, c.off, c.idx, c.geom, s.U,
+                       s.q, s.qx[s.qsel], s.qy[s.qsel], s.R, s.D, s.jv0, s.jv1, s.jv2, s.jv0f,
+                       s.jv1f, s.jv2f, s.Df, s.partial, s.flags);
+    s.nblk_partial = (int)nb;
+}
+
+template <bool MIXED>
+static void residual_t(State& s) {
+    switch (s.residual_lanes) {
+        case 1: residual_lanes<MIXED, 1>(s); break;
+        case 2: residual_lanes<MIXED, 2>(s); break;
+        case 8: residual_lanes<MIXED, 8>(s); break;
+        default: residual_lanes<MIXED, 4>(s); break;
+    }
+}
+
+hipError_t launch_residual(State& s, int slot) {
     (void)slot;
+    if (s.prm.precision == 1)
+        residual_t<true>(s);
+    else
+        residual_t<false>(s);
     return hipGetLastError();
 }
 
@@ -835,28 +869,38 @@ hipError_t launch_norm(State& s, int slot) {
     const Cloud& c = *s.cloud;
     const double inv_active = c.n_active ? 1.0 / (double)c.n_active : 0.0;
     hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, s.stream, s.partial,
-                       (int)grid_for(c.n), inv_active, s.res_hist + slot);
+                       s.nblk_partial, inv_active, s.res_hist + slot);
     return hipGetLastError();
 }
 
-template <class T, int MODE>
-static void sweep_t(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv1,
-                    const Vec4<T>* jv2, const T* Dg, Vec4<T>* dU) {
+template <class T, int MODE, int LANES>
+static void sweep_lanes(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv1,
+                        const Vec4<T>* jv2, const T* Dg, Vec4<T>* dU) {
     const Cloud& c = *s.cloud;
     for (int k = 0; k < c.ncolour; ++k) {
         const int col = forward ? k : c.ncolour - 1 - k;
         const int32_t start = c.h_col_off[col], cnt = c.h_col_off[col + 1] - start;
         if (!cnt) continue;
+        const dim3 g(grid_for((int64_t)cnt * LANES)), b(kBlock);
         if (forward)
-            hipLaunchKernelGGL((k_sweep<T, true, MODE>), dim3(grid_for(cnt)), dim3(kBlock), 0,
-                               s.stream, start, cnt, col, c.col_perm, c.xy, c.frame, c.type, c.off,
-                               c.idx, c.colour, c.geom, jv0, jv1, jv2, s.U, s.R, Dg, dU,
-                               s.prm.gamma);
+            hipLaunchKernelGGL((k_sweep<T, true, MODE, LANES>), g, b, 0, s.stream, start, cnt,
+                               c.col_perm, c.xy, c.frame, c.type, c.lo_off, c.lo_idx, c.geom, jv0,
+                               jv1, jv2, s.U, s.R, Dg, dU, s.prm.gamma);
         else
-            hipLaunchKernelGGL((k_sweep<T, false, MODE>), dim3(grid_for(cnt)), dim3(kBlock), 0,
-                               s.stream, start, cnt, col, c.col_perm, c.xy, c.frame, c.type, c.off,
-                               c.idx, c.colour, c.geom, jv0, jv1, jv2, s.U, s.R, Dg, dU,
-                               s.prm.gamma);
+            hipLaunchKernelGGL((k_sweep<T, false, MODE, LANES>), g, b, 0, s.stream, start, cnt,
+                               c.col_perm, c.xy, c.frame, c.type, c.up_off, c.up_idx, c.geom, jv0,
+                               jv1, jv2, s.U, s.R, Dg, dU, s.prm.gamma);
+    }
+}
+
+template <class T, int MODE>
+static void sweep_t(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv1,
+                    const Vec4<T>* jv2, const T* Dg, Vec4<T>* dU) {
+    switch (s.sweep_lanes) {
+        case 1: sweep_lanes<T, MODE, 1>(s, forward, jv0, jv1, jv2, Dg, dU); break;
+        case 2: sweep_lanes<T, MODE, 2>(s, forward, jv0, jv1, jv2, Dg, dU); break;
+        case 8: sweep_lanes<T, MODE, 8>(s, forward, jv0, jv1, jv2, Dg, dU); break;
+        default: sweep_lanes<T, MODE, 4>(s, forward, jv0, jv1, jv2, Dg, dU); break;
     }
 }
 

@@ -52,6 +52,12 @@ struct Cloud {
     int32_t* colour = nullptr;
     int32_t* col_perm = nullptr;   // points sorted by colour, then index
     int32_t* wall_list = nullptr;  // wall points in storage order
+    // neighbours of each point split by colour, CSR order kept within each list:
+    // lower colours (read by the forward sweep) and higher colours (backward)
+    int32_t* lo_off = nullptr;
+    int32_t* lo_idx = nullptr;
+    int32_t* up_off = nullptr;
+    int32_t* up_idx = nullptr;
     PointGeom* geom = nullptr;
     // host
     std::vector<int32_t> h_colour;
@@ -63,6 +69,7 @@ struct Params {
     int inner_iters, jvp_mode, precision, check_every;
     double tol_rel;
     int max_iters;
+    int sweep_lanes, residual_lanes;
 };
 
 // Device work arrays of one flow state.
@@ -72,6 +79,8 @@ struct State {
     double mach = 0, aoa_deg = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int sweep_lanes = 4;         // lanes per point in the sweep kernels (1, 2, 4 or 8)
+    int residual_lanes = 4;      // lanes per point in the residual kernel (1, 2, 4 or 8)
     double res_fs = 0.0;
     // fp64
     D4* U = nullptr;
@@ -92,7 +101,8 @@ struct State {
     float* Df = nullptr;
     // reductions
     double* partial = nullptr;   // per-block partial sums of R_rho^2
-    int nblk_partial = 0;
+    int nblk_partial = 0;        // blocks of the last residual launch
+    int partial_cap = 0;
     double* res_hist = nullptr;  // residual norms written by the iteration
     int res_cap = 0;
     int32_t* flags = nullptr;    // [0] non-physical

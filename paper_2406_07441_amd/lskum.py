@@ -33,7 +33,8 @@ class LskumError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("inner_iters", C.c_int32),
                 ("jvp_mode", C.c_int32), ("precision", C.c_int32), ("check_every", C.c_int32),
-                ("tol_rel", C.c_double), ("max_iters", C.c_int32), ("reserved", C.c_int32)]
+                ("tol_rel", C.c_double), ("max_iters", C.c_int32), ("sweep_lanes", C.c_int32),
+                ("residual_lanes", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Report(C.Structure):
