@@ -63,6 +63,7 @@ enum { LSKUM_FP64 = 0, LSKUM_MIXED = 1 };
 
 typedef struct lskum_cloud lskum_cloud; /* device geometry, CSR, colours */
 typedef struct lskum_state lskum_state; /* device flow state and work arrays */
+typedef struct lskum_batch lskum_batch; /* many flow conditions iterated together */
 
 typedef struct {
     double gamma;       /* ratio of specific heats (1.4) */
@@ -80,7 +81,11 @@ typedef struct {
                                0 = library choice */
     int32_t residual_lanes; /* lanes per point in the residual kernel: 1, 2, 4,
                                8; 0 = library choice */
-    int32_t reserved;       /* must be 0 */
+    int32_t limiter;        /* 0: none (the paper's scheme); 1: Venkatakrishnan
+                               limiter on the q~ reconstruction (an addition
+                               for flows with shocks) */
+    double limiter_k;       /* limiter constant K: eps^2 = (K h)^3, h the
+                               nearest-neighbour distance */
 } lskum_params;
 
 typedef struct {
@@ -95,7 +100,7 @@ typedef struct {
 
 /* Fills p with the defaults: gamma 1.4, cfl 100, inner_iters 1, exact JVP,
  * fp64, check_every 10, tol_rel 1e-8, max_iters 20000, lanes 0 (library
- * choice). */
+ * choice), no limiter (limiter_k 5). */
 void lskum_default_params(lskum_params* p);
 
 /* Creates a cloud on the current HIP device from host arrays of n points.
@@ -154,7 +159,7 @@ int lskum_q_derivatives(lskum_state* s, double* qx, double* qy, int on_device);
  * and backward colour sweeps (eq. 27), U += dU.  *res (may be NULL) receives
  * the norm of the residual of the state the step started from; passing NULL
  * keeps the step free of host synchronisation.
- * Errors: NONPHYSICAL (state not advanced past the failing step). */
+ * Errors: NONPHYSICAL (the state then holds the non-physical result). */
 int lskum_lusgs_step(lskum_state* s, double* res);
 
 /* One lskum_lusgs_step launched eagerly with HIP events between its
@@ -164,7 +169,9 @@ int lskum_lusgs_step(lskum_state* s, double* res);
 int lskum_step_timed(lskum_state* s, double* ms);
 
 /* Iterates lusgs steps until res <= tol_rel * res_fs or max_iters; the
- * iteration is captured once in a HIP graph and replayed.  rep may be NULL.
+ * iteration is captured once in a HIP graph (check_every iterations) and
+ * replayed; convergence is tested on the device, so the state stops at the
+ * first iteration whose residual meets the tolerance.  rep may be NULL.
  * Returns NOT_CONVERGED when max_iters is reached (report filled). */
 int lskum_solve(lskum_state* s, lskum_report* rep);
 
@@ -172,6 +179,50 @@ int lskum_solve(lskum_state* s, lskum_report* rep);
  * trapezoidal pressure on each edge of the wall polygon, unit chord,
  * dynamic pressure M^2/2. */
 int lskum_forces(lskum_state* s, double* cl, double* cd);
+
+/* ---- Batches: many flow conditions (Mach, AoA) on one or more clouds,
+ * iterated together.  The batch holds one copy of its cloud per condition;
+ * every kernel of an iteration (each colour phase of both sweeps included)
+ * is one launch over all conditions, colour c of every cloud in phase c.
+ * Conditions that reach their tolerance (tol_rel times their own free-stream
+ * residual) or fail (non-finite residual) retire on the device and skip
+ * further work.  The clouds must outlive the batch creation only. */
+
+/* Creates a batch of n_cond conditions; condition k uses
+ * clouds[cond_cloud[k]] and (mach[k], aoa_deg[k]).  All conditions start at
+ * their free stream.  Errors: ARG, HIP, OOM. */
+int lskum_batch_create(int32_t n_clouds, const lskum_cloud* const* clouds, int32_t n_cond,
+                       const int32_t* cond_cloud, const double* mach, const double* aoa_deg,
+                       const lskum_params* prm, void* hip_stream, lskum_batch** out);
+
+/* Total points and edges over all conditions, and colour phases. */
+int lskum_batch_info(const lskum_batch* b, int64_t* n_points, int64_t* nnz, int32_t* n_colours);
+
+int lskum_batch_set_params(lskum_batch* b, const lskum_params* prm);
+
+/* Solves all conditions (graph-replayed iterations, device-side retirement)
+ * until all retire or max_iters.  reps (n_cond entries, may be NULL): per
+ * condition iterations, status (OK, NOT_CONVERGED or NONPHYSICAL), residual
+ * norms, the wall time at which it retired, CL and CD.  *seconds_total (may be
+ * NULL): wall time of the whole solve.  Returns the first non-OK status. */
+int lskum_batch_solve(lskum_batch* b, lskum_report* reps, double* seconds_total);
+
+/* One iteration of all conditions with per-phase GPU times (as
+ * lskum_step_timed). */
+int lskum_batch_step_timed(lskum_batch* b, double* ms);
+
+/* Gets / sets the state ([4][n_k] doubles) of condition k. */
+int lskum_batch_get_U(lskum_batch* b, int32_t cond, double* U, int on_device);
+int lskum_batch_set_U(lskum_batch* b, int32_t cond, const double* U, int on_device);
+
+/* Autotuner: times `iters` iterations with 1, 2, 4 and 8 lanes per point
+ * and keeps the fastest lane count for the sweep and for the residual
+ * kernels (written to *sweep_lanes, *residual_lanes).  The batch's state is
+ * restored afterwards. */
+int lskum_batch_autotune(lskum_batch* b, int32_t iters, int32_t* sweep_lanes,
+                         int32_t* residual_lanes);
+
+void lskum_batch_destroy(lskum_batch* b);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char* lskum_last_error(void);

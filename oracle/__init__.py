@@ -40,7 +40,8 @@ class _Cloud(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("mach", C.c_double),
-                ("aoa_deg", C.c_double), ("inner_iters", C.c_int32), ("jvp_mode", C.c_int32)]
+                ("aoa_deg", C.c_double), ("inner_iters", C.c_int32), ("jvp_mode", C.c_int32),
+                ("limiter", C.c_int32), ("pad", C.c_int32), ("limiter_k", C.c_double)]
 
 
 _lib = None
@@ -66,6 +67,7 @@ def lib():
             "ora_q_derivatives": (I32, [P, P, P, P, P]),
             "ora_residual": (I32, [P, P, P, P, P, P]),
             "ora_flux_residual": (I32, [P, P, P, P, P, P]),
+            "ora_limit_gradients": (None, [P, P, P, P, P]),
             "ora_timestep_diag": (None, [P, P, P, P, P]),
             "ora_lusgs": (None, [P, P, P, P, P, P]),
             "ora_residual_norm": (D, [P, P]),
@@ -103,8 +105,9 @@ def split_flux(U, d, s, gamma=GAMMA):
     return G
 
 
-def params(mach=0.63, aoa_deg=2.0, cfl=100.0, inner_iters=3, jvp_mode=0, gamma=GAMMA):
-    return _Params(gamma, cfl, mach, aoa_deg, inner_iters, jvp_mode)
+def params(mach=0.63, aoa_deg=2.0, cfl=100.0, inner_iters=1, jvp_mode=0, gamma=GAMMA, limiter=0,
+           limiter_k=5.0):
+    return _Params(gamma, cfl, mach, aoa_deg, inner_iters, jvp_mode, limiter, 0, limiter_k)
 
 
 def flux_jvp(U, dU, d, s, jvp_mode=0, gamma=GAMMA):
@@ -134,8 +137,8 @@ def U_from_q(q, gamma=GAMMA):
 class Oracle:
     """Oracle bound to one cloud and one flow condition."""
 
-    def __init__(self, cloud, mach=0.63, aoa_deg=2.0, cfl=100.0, inner_iters=3, jvp_mode=0,
-                 gamma=GAMMA, colours=None):
+    def __init__(self, cloud, mach=0.63, aoa_deg=2.0, cfl=100.0, inner_iters=1, jvp_mode=0,
+                 gamma=GAMMA, colours=None, limiter=0, limiter_k=5.0):
         self.cloud = cloud
         self._keep = [_f64(cloud.x), _f64(cloud.y), _f64(cloud.tx), _f64(cloud.ty),
                       np.ascontiguousarray(cloud.type, dtype=np.int8),
@@ -150,7 +153,7 @@ class Oracle:
         k = self._keep
         self.c = _Cloud(cloud.n, _p(k[0]), _p(k[1]), _p(k[2]), _p(k[3]), _p(k[4]), _p(k[5]),
                         _p(k[6]), _p(col), nc)
-        self.prm = params(mach, aoa_deg, cfl, inner_iters, jvp_mode, gamma)
+        self.prm = params(mach, aoa_deg, cfl, inner_iters, jvp_mode, gamma, limiter, limiter_k)
         self.n = cloud.n
 
     # -- state -------------------------------------------------------------
@@ -188,6 +191,11 @@ class Oracle:
             raise RuntimeError(f"residual status {st}")
         self.degenerate = int(ndeg.value)
         return R, float(res.value)
+
+    def limit_gradients(self, q, qx, qy):
+        qx, qy = _f64(qx).copy(), _f64(qy).copy()
+        lib().ora_limit_gradients(C.byref(self.c), C.byref(self.prm), _p(_f64(q)), _p(qx), _p(qy))
+        return qx, qy
 
     def flux_residual(self, q, qx, qy):
         R = np.empty((4, self.n))

@@ -169,6 +169,8 @@ struct Cloud {
 struct Params {
     double gamma, cfl, mach, aoa_deg;
     int32_t inner_iters, jvp_mode;  // jvp_mode 0 exact tangent, 1 flux difference
+    int32_t limiter;                // 0 none (the paper), 1 Venkatakrishnan on q~
+    double limiter_k;
 };
 
 enum { OK = 0, ERR_ARG = -1, ERR_CONN = -2, ERR_DEGEN = -3, ERR_COLOUR = -4, ERR_NONPHYS = -5 };
@@ -331,6 +333,56 @@ int q_derivatives(const Cloud& c, const Params& P, const double* q, double* qx, 
         std::memcpy(qy, ty.data(), sizeof(double) * 4 * c.n);
     }
     return OK;
+}
+
+// Optional limiter on the q~ reconstruction (not part of the paper, which
+// describes none; an addition for transonic robustness).  Venkatakrishnan's
+// limiter (AIAA 93-0880 / J. Comput. Phys. 1995): for point p and component v,
+// with dmax = max_i q_i - q_p, dmin = min_i q_i - q_p over the full stencil,
+// each reconstruction increment d2 = -1/2 (dx_i qx_p + dy_i qy_p) toward a
+// neighbour direction gets
+//   phi_i = [(d1^2 + eps^2) d2 + 2 d2^2 d1] / [d2 (d1^2 + 2 d2^2 + d1 d2 + eps^2)]
+// with d1 = dmax (d2 > 0) or dmin (d2 < 0), phi_i = 1 for d2 = 0, and
+// phi_p = min(1, min_i phi_i); eps^2 = (K h)^3 with h the nearest-neighbour
+// distance.  The residual then uses phi_p * (qx_p, qy_p).
+void limit_gradients(const Cloud& c, const Params& P, const double* q, double* qx, double* qy) {
+    std::vector<double> phi(4 * c.n, 1.0);
+    for (int64_t p = 0; p < c.n; ++p) {
+        double rmin = INFINITY;
+        double dmax[4] = {0, 0, 0, 0}, dmin[4] = {0, 0, 0, 0};
+        for (int32_t e = c.off[p]; e < c.off[p + 1]; ++e) {
+            int32_t i = c.idx[e];
+            double dx = c.x[i] - c.x[p], dy = c.y[i] - c.y[p];
+            double r = std::sqrt(dx * dx + dy * dy);
+            if (r < rmin) rmin = r;
+            for (int v = 0; v < 4; ++v) {
+                double d = q[v * c.n + i] - q[v * c.n + p];
+                if (d > dmax[v]) dmax[v] = d;
+                if (d < dmin[v]) dmin[v] = d;
+            }
+        }
+        double kh = P.limiter_k * rmin;
+        double eps2 = kh * kh * kh;
+        for (int v = 0; v < 4; ++v) {
+            double ph = 1.0;
+            for (int32_t e = c.off[p]; e < c.off[p + 1]; ++e) {
+                int32_t i = c.idx[e];
+                double dx = c.x[i] - c.x[p], dy = c.y[i] - c.y[p];
+                double d2 = -0.5 * (dx * qx[v * c.n + p] + dy * qy[v * c.n + p]);
+                if (d2 == 0.0) continue;
+                double d1 = d2 > 0.0 ? dmax[v] : dmin[v];
+                double num = (d1 * d1 + eps2) * d2 + 2.0 * d2 * d2 * d1;
+                double den = d2 * (d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2);
+                double f = num / den;
+                if (f < ph) ph = f;
+            }
+            phi[v * c.n + p] = ph < 0.0 ? 0.0 : ph;
+        }
+    }
+    for (int64_t k = 0; k < 4 * c.n; ++k) {
+        qx[k] *= phi[k];
+        qy[k] *= phi[k];
+    }
 }
 
 // flux_residual(): R_0 = sum over the point's split stencils k of
@@ -533,13 +585,16 @@ typedef struct {
 typedef struct {
     double gamma, cfl, mach, aoa_deg;
     int32_t inner_iters, jvp_mode;
+    int32_t limiter, pad;
+    double limiter_k;
 } ora_params;
 
 static Cloud to_cloud(const ora_cloud* c) {
     return Cloud{c->n, c->x, c->y, c->tx, c->ty, c->type, c->off, c->idx, c->colour, c->ncolour};
 }
 static Params to_params(const ora_params* p) {
-    return Params{p->gamma, p->cfl, p->mach, p->aoa_deg, p->inner_iters, p->jvp_mode};
+    return Params{p->gamma,       p->cfl,      p->mach,    p->aoa_deg,
+                  p->inner_iters, p->jvp_mode, p->limiter, p->limiter_k};
 }
 
 // Point colouring, Algorithm 4: colour(first point) = first colour; then for
@@ -662,9 +717,16 @@ int32_t ora_residual(const ora_cloud* oc, const ora_params* prm, const double* U
     if (st) return st;
     st = q_derivatives(c, P, q.data(), qx.data(), qy.data());
     if (st) return st;
+    if (P.limiter) limit_gradients(c, P, q.data(), qx.data(), qy.data());
     st = flux_residual(c, P, q.data(), qx.data(), qy.data(), R, degenerate);
     if (res) *res = residual_norm(c, R);
     return st;
+}
+
+// Limited gradients (Venkatakrishnan) of given q, q_x, q_y, in place.
+void ora_limit_gradients(const ora_cloud* oc, const ora_params* prm, const double* q, double* qx,
+                         double* qy) {
+    limit_gradients(to_cloud(oc), to_params(prm), q, qx, qy);
 }
 
 // Residual from given q, q_x, q_y (flux_residual alone).

@@ -38,7 +38,11 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * per + (x < rem ? x : rem) + r;
 }
 
-__device__ __forceinline__ D4 ld4(const D4* p, int64_t i) { return p[i]; }
+// A point takes part in an iteration while its component is active.
+__device__ __forceinline__ bool live(const int32_t* __restrict__ comp,
+                                     const int32_t* __restrict__ active, int64_t p) {
+    return active[comp ? comp[p] : 0] != 0;
+}
 
 // Projections onto a wall frame, evaluated without contraction so that split
 // membership (the sign of da) is decided exactly as a plain multiply-add would.
@@ -215,10 +219,13 @@ __global__ void __launch_bounds__(kBlock) k_precompute(int64_t n, const D2* __re
 // the tangential velocity only.
 __global__ void __launch_bounds__(kBlock) k_free_stream(int64_t n, const int8_t* __restrict__ type,
                                                         const D2* __restrict__ frame, double gamma,
-                                                        double u_inf, double v_inf, D4* __restrict__ U) {
+                                                        const int32_t* __restrict__ comp,
+                                                        const double* __restrict__ vinf,
+                                                        D4* __restrict__ U) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    double u1 = u_inf, u2 = v_inf;
+    const int k = comp ? comp[p] : 0;
+    double u1 = vinf[2 * k], u2 = vinf[2 * k + 1];
     if (type[p] == kWall) {
         const D2 t = frame[p];
         const double ut = u1 * t.x + u2 * t.y;
@@ -260,12 +267,14 @@ __global__ void __launch_bounds__(kBlock) k_qgrad(int64_t n, const D2* __restric
                                                   const int32_t* __restrict__ off,
                                                   const int32_t* __restrict__ idx,
                                                   const PointGeom* __restrict__ geom,
+                                                  const int32_t* __restrict__ comp,
+                                                  const int32_t* __restrict__ active,
                                                   const D4* __restrict__ q,
                                                   const D4* __restrict__ qx_in,
                                                   const D4* __restrict__ qy_in,
                                                   D4* __restrict__ qx_out, D4* __restrict__ qy_out) {
     const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    if (p >= n || !live(comp, active, p)) return;
     const D2 r0 = xy[p];
     const D4 q0 = q[p];
     D4 gx0{}, gy0{};
@@ -301,6 +310,63 @@ __global__ void __launch_bounds__(kBlock) k_qgrad(int64_t n, const D2* __restric
                  L.y * bx[3] + L.z * by[3]};
 }
 
+// Venkatakrishnan's limiter on the q~ reconstruction (an addition: the paper
+// names no limiter).  Per point and component, phi = min over neighbours of
+//   (d1^2 + eps^2 + 2 d1 d2) / (d1^2 + 2 d2^2 + d1 d2 + eps^2),
+// d2 = -(dx qx + dy qy)/2 the reconstruction increment toward the neighbour,
+// d1 the largest (d2 > 0) or smallest (d2 < 0) neighbour difference,
+// eps^2 = (K h)^3 with h the nearest-neighbour distance; phi clamped to >= 0.
+// Writes phi * (qx, qy).
+__global__ void __launch_bounds__(kBlock) k_limiter(int64_t n, double K, const D2* __restrict__ xy,
+                                                    const int32_t* __restrict__ off,
+                                                    const int32_t* __restrict__ idx,
+                                                    const PointGeom* __restrict__ geom,
+                                                    const int32_t* __restrict__ comp,
+                                                    const int32_t* __restrict__ active,
+                                                    const D4* __restrict__ q,
+                                                    const D4* __restrict__ qx,
+                                                    const D4* __restrict__ qy,
+                                                    D4* __restrict__ qxl, D4* __restrict__ qyl) {
+    const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (p >= n || !live(comp, active, p)) return;
+    const D2 r0 = xy[p];
+    const D4 q0 = q[p];
+    const D4 gx = qx[p], gy = qy[p];
+    const double g_x[4] = {gx.x, gx.y, gx.z, gx.w}, g_y[4] = {gy.x, gy.y, gy.z, gy.w};
+    const double qv[4] = {q0.x, q0.y, q0.z, q0.w};
+    double dmax[4] = {0, 0, 0, 0}, dmin[4] = {0, 0, 0, 0};
+    const int32_t e0 = off[p], e1 = off[p + 1];
+    for (int32_t e = e0; e < e1; ++e) {
+        const D4 qi = q[idx[e]];
+        const double d[4] = {qi.x - qv[0], qi.y - qv[1], qi.z - qv[2], qi.w - qv[3]};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            dmax[v] = fmax(dmax[v], d[v]);
+            dmin[v] = fmin(dmin[v], d[v]);
+        }
+    }
+    const double kh = K * geom[p].lsq.w;
+    const double eps2 = kh * kh * kh;
+    double phi[4] = {1.0, 1.0, 1.0, 1.0};
+    for (int32_t e = e0; e < e1; ++e) {
+        const D2 ri = xy[idx[e]];
+        const double dx = ri.x - r0.x, dy = ri.y - r0.y;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double d2 = -0.5 * (dx * g_x[v] + dy * g_y[v]);
+            if (d2 == 0.0) continue;
+            const double d1 = d2 > 0.0 ? dmax[v] : dmin[v];
+            const double f = (d1 * d1 + eps2 + 2.0 * d1 * d2) /
+                             (d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2);
+            phi[v] = fmin(phi[v], f);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) phi[v] = fmax(phi[v], 0.0);
+    qxl[p] = {phi[0] * gx.x, phi[1] * gx.y, phi[2] * gx.z, phi[3] * gx.w};
+    qyl[p] = {phi[0] * gy.x, phi[1] * gy.y, phi[2] * gy.z, phi[3] * gy.w};
+}
+
 // ---------------------------------------------------------------------------
 // Residual (eq. 11 with the q~ reconstruction of eq. 15), local time step,
 // scalar diagonal (eq. 25, 34-35) and the sweep linearisation data.
@@ -313,20 +379,19 @@ __global__ void __launch_bounds__(kBlock) k_residual(
     int64_t n, double gamma, double cfl, const D2* __restrict__ xy, const D2* __restrict__ frame,
     const int8_t* __restrict__ type, const int32_t* __restrict__ off,
     const int32_t* __restrict__ idx, const PointGeom* __restrict__ geom,
+    const int32_t* __restrict__ comp, const int32_t* __restrict__ active,
     const D4* __restrict__ U, const D4* __restrict__ q, const D4* __restrict__ qx,
     const D4* __restrict__ qy, D4* __restrict__ R, double* __restrict__ Dg,
     D4* __restrict__ jv0, D4* __restrict__ jv1, D4* __restrict__ jv2, F4* __restrict__ jv0f,
     F4* __restrict__ jv1f, F4* __restrict__ jv2f, float* __restrict__ Df,
-    double* __restrict__ partial, int32_t* __restrict__ flags) {
-    __shared__ double red[kBlock / 64];
+    double* __restrict__ rr_out, int32_t* __restrict__ flags) {
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t gt = (int64_t)lb * blockDim.x + threadIdx.x;
     const int64_t p = gt / LANES;
     const int lane = (int)(gt % LANES);
     const double inv_gm1 = 1.0 / (gamma - 1.0);
     const bool g14 = gamma == 1.4;
-    double rr = 0.0;  // R_rho^2 of this point (non-outer), first lane only
-    if (p < n) {
+    if (p < n && live(comp, active, p)) {
         const int8_t ty = type[p];
         const D2 r0 = xy[p];
         const D2 t = frame[p];
@@ -397,7 +462,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                 Rp[1] -= mn * nx;
                 Rp[2] -= mn * ny;
             }
-            if (ty != kOuter) rr = Rp[0] * Rp[0];
+            rr_out[p] = ty != kOuter ? Rp[0] * Rp[0] : 0.0;
             R[p] = {Rp[0], Rp[1], Rp[2], Rp[3]};
 
             // linearisation data at the current state, local time step, diagonal
@@ -441,30 +506,53 @@ __global__ void __launch_bounds__(kBlock) k_residual(
             if (bad || !(rho > 0.0) || !(pr > 0.0)) flags[0] = 1;
         }
     }
-    // deterministic block reduction of R_rho^2
-    for (int o = 32; o > 0; o >>= 1) rr += __shfl_xor(rr, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rr;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) s += red[w];
-        partial[lb] = s;
-    }
 }
 
-__global__ void __launch_bounds__(kBlock) k_norm_final(const double* __restrict__ partial, int nb,
-                                                       double inv_active, double* __restrict__ out) {
+// Residual norm of each component (one block per component, fixed reduction
+// order): res = sqrt(sum of R_rho^2 over its non-outer points) / their count.
+// A component whose norm is not finite is retired as failed; one that
+// reaches tol_abs (> 0) is retired as converged.
+__global__ void __launch_bounds__(kBlock) k_norm_comp(const double* __restrict__ rr,
+                                                      const int32_t* __restrict__ comp_off,
+                                                      const double* __restrict__ inv_active,
+                                                      const double* __restrict__ tol_abs,
+                                                      int32_t* __restrict__ active,
+                                                      int32_t* __restrict__ status,
+                                                      int32_t* __restrict__ iters,
+                                                      double* __restrict__ res_last,
+                                                      double* __restrict__ out) {
     __shared__ double red[kBlock / 64];
+    const int k = blockIdx.x;
+    if (!active[k]) return;  // uniform over the block
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partial[b];
+    for (int64_t p = comp_off[k] + threadIdx.x; p < comp_off[k + 1]; p += blockDim.x) s += rr[p];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) t += red[w];
-        out[0] = sqrt(t) * inv_active;
+        const double res = sqrt(t) * inv_active[k];
+        out[k] = res;
+        res_last[k] = res;
+        iters[k] += 1;
+        if (!(res <= 1e300)) {
+            status[k] = -1;
+            active[k] = 0;
+        } else if (tol_abs[k] > 0.0 && res <= tol_abs[k]) {
+            status[k] = 1;
+            active[k] = 0;
+        }
     }
+}
+
+__global__ void k_reset_components(int ncomp, int32_t* __restrict__ active,
+                                   int32_t* __restrict__ status, int32_t* __restrict__ iters) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ncomp) return;
+    active[k] = 1;
+    status[k] = 0;
+    iters[k] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -642,7 +730,8 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
     int32_t start, int32_t count, const int32_t* __restrict__ col_perm,
     const D2* __restrict__ xy, const D2* __restrict__ frame, const int8_t* __restrict__ type,
     const int32_t* __restrict__ loff, const int32_t* __restrict__ lidx,
-    const PointGeom* __restrict__ geom, const Vec4<T>* __restrict__ jv0,
+    const PointGeom* __restrict__ geom, const int32_t* __restrict__ comp,
+    const int32_t* __restrict__ active, const Vec4<T>* __restrict__ jv0,
     const Vec4<T>* __restrict__ jv1, const Vec4<T>* __restrict__ jv2,
     const D4* __restrict__ U, const D4* __restrict__ R, const T* __restrict__ Dg,
     Vec4<T>* __restrict__ dU, double gamma) {
@@ -650,6 +739,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
     const int pt = gt / LANES, lane = gt % LANES;
     if (pt >= count) return;  // uniform over the lanes of a point
     const int32_t p = col_perm[start + pt];
+    if (!live(comp, active, p)) return;
     const int8_t ty = type[p];
     if (ty == kOuter) {
         if (FWD && lane == 0) dU[p] = {T(0), T(0), T(0), T(0)};
@@ -700,9 +790,11 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_update(int64_t n, double gamma, D4* __restrict__ U,
                                                    const Vec4<T>* __restrict__ dU,
+                                                   const int32_t* __restrict__ comp,
+                                                   const int32_t* __restrict__ active,
                                                    D4* __restrict__ q, int32_t* __restrict__ flags) {
     const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    if (p >= n || !live(comp, active, p)) return;
     D4 u = U[p];
     const Vec4<T> d = dU[p];
     u.x += (double)d.x;
@@ -715,17 +807,22 @@ __global__ void __launch_bounds__(kBlock) k_update(int64_t n, double gamma, D4* 
     if (bad) flags[0] = 1;
 }
 
-// Pressure force on the closed wall polygon: sum over edges (a, b) of
-// -(p_mid - p_inf) * (edge normal pointing out of the body) * |e|.
-__global__ void __launch_bounds__(kBlock) k_forces(int64_t m, const int32_t* __restrict__ wall,
+// Pressure force on the closed wall polygon of each component (one block per
+// component): sum over edges (a, b) of -(p_mid - p_inf) * |e| * (edge normal
+// pointing out of the body), orient = +1 for a counter-clockwise polygon.
+__global__ void __launch_bounds__(kBlock) k_forces(const int32_t* __restrict__ wall,
+                                                   const int32_t* __restrict__ wall_off,
+                                                   const double* __restrict__ orient_k,
                                                    const D2* __restrict__ xy, const D4* __restrict__ U,
-                                                   double gamma, double orient,
-                                                   double* __restrict__ out) {
+                                                   double gamma, double* __restrict__ out) {
     __shared__ double rx[kBlock / 64], ry[kBlock / 64];
+    const int k = blockIdx.x;
+    const int64_t w0 = wall_off[k], m = wall_off[k + 1] - w0;
+    const double orient = orient_k[k];
     double fx = 0.0, fy = 0.0;
     const double pinf = 1.0 / gamma;
     for (int64_t j = threadIdx.x; j < m; j += blockDim.x) {
-        const int32_t a = wall[j], b = wall[j + 1 == m ? 0 : j + 1];
+        const int32_t a = wall[w0 + j], b = wall[w0 + (j + 1 == m ? 0 : j + 1)];
         const D4 ua = U[a], ub = U[b];
         const double pa = (gamma - 1.0) * (ua.w - 0.5 * (ua.y * ua.y + ua.z * ua.z) / ua.x);
         const double pb = (gamma - 1.0) * (ub.w - 0.5 * (ub.y * ub.y + ub.z * ub.z) / ub.x);
@@ -750,8 +847,8 @@ __global__ void __launch_bounds__(kBlock) k_forces(int64_t m, const int32_t* __r
             sx += rx[w];
             sy += ry[w];
         }
-        out[0] = sx;
-        out[1] = sy;
+        out[2 * k] = sx;
+        out[2 * k + 1] = sy;
     }
 }
 
@@ -807,9 +904,8 @@ hipError_t launch_precompute(Cloud& c, hipStream_t st) {
 
 hipError_t launch_free_stream(State& s) {
     const Cloud& c = *s.cloud;
-    const double a = s.aoa_deg * 3.14159265358979323846 / 180.0;
     hipLaunchKernelGGL(k_free_stream, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream, c.n, c.type,
-                       c.frame, s.prm.gamma, s.mach * cos(a), s.mach * sin(a), s.U);
+                       c.frame, s.prm.gamma, c.comp, s.vinf, s.U);
     return hipGetLastError();
 }
 
@@ -823,15 +919,19 @@ hipError_t launch_q_from_U(State& s) {
 hipError_t launch_q_derivatives(State& s) {
     const Cloud& c = *s.cloud;
     const dim3 g(grid_for(c.n)), b(kBlock);
-    hipLaunchKernelGGL(k_qgrad<false>, g, b, 0, s.stream, c.n, c.xy, c.off, c.idx, c.geom, s.q,
-                       nullptr, nullptr, s.qx[0], s.qy[0]);
+    hipLaunchKernelGGL(k_qgrad<false>, g, b, 0, s.stream, c.n, c.xy, c.off, c.idx, c.geom, c.comp,
+                       s.active, s.q, nullptr, nullptr, s.qx[0], s.qy[0]);
     int cur = 0;
     for (int it = 0; it < s.prm.inner_iters; ++it) {
-        hipLaunchKernelGGL(k_qgrad<true>, g, b, 0, s.stream, c.n, c.xy, c.off, c.idx, c.geom, s.q,
-                           s.qx[cur], s.qy[cur], s.qx[1 - cur], s.qy[1 - cur]);
+        hipLaunchKernelGGL(k_qgrad<true>, g, b, 0, s.stream, c.n, c.xy, c.off, c.idx, c.geom,
+                           c.comp, s.active, s.q, s.qx[cur], s.qy[cur], s.qx[1 - cur],
+                           s.qy[1 - cur]);
         cur = 1 - cur;
     }
     s.qsel = cur;
+    if (s.prm.limiter)
+        hipLaunchKernelGGL(k_limiter, g, b, 0, s.stream, c.n, s.prm.limiter_k, c.xy, c.off, c.idx,
+                           c.geom, c.comp, s.active, s.q, s.qx[cur], s.qy[cur], s.qxl, s.qyl);
     return hipGetLastError();
 }
 
@@ -840,10 +940,10 @@ static void residual_lanes(State& s) {
     const Cloud& c = *s.cloud;
     const unsigned nb = grid_for(c.n * LANES);
     hipLaunchKernelGGL((k_residual<MIXED, LANES>), dim3(nb), dim3(kBlock), 0, s.stream, c.n,
-                       s.prm.gamma, s.prm.cfl, c.xy, c.frame, c.type, c.off, c.idx, c.geom, s.U,
-                       s.q, s.qx[s.qsel], s.qy[s.qsel], s.R, s.D, s.jv0, s.jv1, s.jv2, s.jv0f,
-                       s.jv1f, s.jv2f, s.Df, s.partial, s.flags);
-    s.nblk_partial = (int)nb;
+                       s.prm.gamma, s.prm.cfl, c.xy, c.frame, c.type, c.off, c.idx, c.geom, c.comp,
+                       s.active, s.U, s.q, s.prm.limiter ? s.qxl : s.qx[s.qsel],
+                       s.prm.limiter ? s.qyl : s.qy[s.qsel], s.R, s.D, s.jv0, s.jv1, s.jv2,
+                       s.jv0f, s.jv1f, s.jv2f, s.Df, s.rr, s.flags);
 }
 
 template <bool MIXED>
@@ -867,9 +967,16 @@ hipError_t launch_residual(State& s, int slot) {
 
 hipError_t launch_norm(State& s, int slot) {
     const Cloud& c = *s.cloud;
-    const double inv_active = c.n_active ? 1.0 / (double)c.n_active : 0.0;
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, s.stream, s.partial,
-                       s.nblk_partial, inv_active, s.res_hist + slot);
+    hipLaunchKernelGGL(k_norm_comp, dim3(c.ncomp), dim3(kBlock), 0, s.stream, s.rr, c.comp_off,
+                       c.comp_inv_active, s.tol_abs, s.active, s.status, s.iters, s.res_last,
+                       s.res_hist + (size_t)slot * c.ncomp);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_components(State& s) {
+    const Cloud& c = *s.cloud;
+    hipLaunchKernelGGL(k_reset_components, dim3((c.ncomp + 63) / 64), dim3(64), 0, s.stream,
+                       c.ncomp, s.active, s.status, s.iters);
     return hipGetLastError();
 }
 
@@ -884,12 +991,12 @@ static void sweep_lanes(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T
         const dim3 g(grid_for((int64_t)cnt * LANES)), b(kBlock);
         if (forward)
             hipLaunchKernelGGL((k_sweep<T, true, MODE, LANES>), g, b, 0, s.stream, start, cnt,
-                               c.col_perm, c.xy, c.frame, c.type, c.lo_off, c.lo_idx, c.geom, jv0,
-                               jv1, jv2, s.U, s.R, Dg, dU, s.prm.gamma);
+                               c.col_perm, c.xy, c.frame, c.type, c.lo_off, c.lo_idx, c.geom,
+                               c.comp, s.active, jv0, jv1, jv2, s.U, s.R, Dg, dU, s.prm.gamma);
         else
             hipLaunchKernelGGL((k_sweep<T, false, MODE, LANES>), g, b, 0, s.stream, start, cnt,
-                               c.col_perm, c.xy, c.frame, c.type, c.up_off, c.up_idx, c.geom, jv0,
-                               jv1, jv2, s.U, s.R, Dg, dU, s.prm.gamma);
+                               c.col_perm, c.xy, c.frame, c.type, c.up_off, c.up_idx, c.geom,
+                               c.comp, s.active, jv0, jv1, jv2, s.U, s.R, Dg, dU, s.prm.gamma);
     }
 }
 
@@ -924,17 +1031,17 @@ hipError_t launch_update(State& s) {
     const Cloud& c = *s.cloud;
     if (s.prm.precision == 1)
         hipLaunchKernelGGL(k_update<float>, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream, c.n,
-                           s.prm.gamma, s.U, s.dUf, s.q, s.flags);
+                           s.prm.gamma, s.U, s.dUf, c.comp, s.active, s.q, s.flags);
     else
         hipLaunchKernelGGL(k_update<double>, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream, c.n,
-                           s.prm.gamma, s.U, s.dU, s.q, s.flags);
+                           s.prm.gamma, s.U, s.dU, c.comp, s.active, s.q, s.flags);
     return hipGetLastError();
 }
 
-hipError_t launch_forces(State& s, double* d_out2) {
+hipError_t launch_forces(State& s) {
     const Cloud& c = *s.cloud;
-    hipLaunchKernelGGL(k_forces, dim3(1), dim3(kBlock), 0, s.stream, c.n_wall, c.wall_list, c.xy,
-                       s.U, s.prm.gamma, c.wall_orient, d_out2);
+    hipLaunchKernelGGL(k_forces, dim3(c.ncomp), dim3(kBlock), 0, s.stream, c.wall_list,
+                       c.wall_off, c.comp_orient, c.xy, s.U, s.prm.gamma, s.fsum);
     return hipGetLastError();
 }
 

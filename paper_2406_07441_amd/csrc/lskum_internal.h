@@ -58,6 +58,23 @@ struct Cloud {
     int32_t* lo_idx = nullptr;
     int32_t* up_off = nullptr;
     int32_t* up_idx = nullptr;
+    // Components: a batch cloud is the disjoint union of one copy of a cloud
+    // per flow condition.  Component k owns points [comp_off[k], comp_off[k+1])
+    // and wall-list entries [wall_off[k], wall_off[k+1]).  A plain cloud has
+    // one component and comp == nullptr.
+    int32_t ncomp = 1;
+    int32_t* comp = nullptr;        // component of each point (batch clouds only)
+    int32_t* comp_off = nullptr;    // device, ncomp + 1
+    int32_t* wall_off = nullptr;    // device, ncomp + 1
+    std::vector<int64_t> h_comp_off, h_wall_off, h_comp_active;
+    std::vector<double> h_comp_orient;
+    std::vector<double> h_comp_inv_active;
+    double* comp_inv_active = nullptr;  // device, 1 / non-outer points per component
+    double* comp_orient = nullptr;      // device, wall polygon orientation per component
+    // host copies kept for building batch clouds
+    std::vector<double> h_x, h_y, h_tx, h_ty;
+    std::vector<int8_t> h_type;
+    std::vector<int32_t> h_off, h_idx;
     PointGeom* geom = nullptr;
     // host
     std::vector<int32_t> h_colour;
@@ -70,13 +87,28 @@ struct Params {
     double tol_rel;
     int max_iters;
     int sweep_lanes, residual_lanes;
+    int limiter;
+    double limiter_k;
 };
 
 // Device work arrays of one flow state.
 struct State {
     const Cloud* cloud = nullptr;
     Params prm{};
-    double mach = 0, aoa_deg = 0;
+    double mach = 0, aoa_deg = 0;          // component 0 (plain states)
+    std::vector<double> h_mach, h_aoa;     // per component
+    std::vector<double> h_res_fs;          // per component free-stream residual
+    // per-component device bookkeeping, written by the norm kernel:
+    //   active: 1 while the component iterates; status: 0 running,
+    //   1 converged (res <= tol_abs), -1 non-finite residual;
+    //   iters: iterations taken; res_last: last residual norm.
+    int32_t* active = nullptr;
+    int32_t* status = nullptr;
+    int32_t* iters = nullptr;
+    double* res_last = nullptr;
+    double* tol_abs = nullptr;             // 0 disables device-side retirement
+    double* vinf = nullptr;                // 2 per component: free-stream velocity
+    double* rr = nullptr;                  // per point R_rho^2 (0 at outer points)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int sweep_lanes = 4;         // lanes per point in the sweep kernels (1, 2, 4 or 8)
@@ -87,6 +119,8 @@ struct State {
     D4* q = nullptr;
     D4* qx[2] = {nullptr, nullptr};
     D4* qy[2] = {nullptr, nullptr};
+    D4* qxl = nullptr;   // limited q-derivatives (limiter on)
+    D4* qyl = nullptr;
     D4* R = nullptr;
     D4* dU = nullptr;
     D4* jv0 = nullptr;   // (rho, u1, u2, p) at the state the sweeps linearise about
@@ -100,11 +134,9 @@ struct State {
     F4* dUf = nullptr;
     float* Df = nullptr;
     // reductions
-    double* partial = nullptr;   // per-block partial sums of R_rho^2
-    int nblk_partial = 0;        // blocks of the last residual launch
-    int partial_cap = 0;
-    double* res_hist = nullptr;  // residual norms written by the iteration
-    int res_cap = 0;
+    double* fsum = nullptr;      // 2 doubles per component: pressure force
+    double* res_hist = nullptr;  // residual norms, [slot][component]
+    int res_cap = 0;             // slots
     int32_t* flags = nullptr;    // [0] non-physical
     int qsel = 0;                // which qx/qy buffer holds the final pass
     bool have_dU = false;
@@ -119,15 +151,16 @@ struct State {
 hipError_t launch_precompute(Cloud& c, hipStream_t st);
 hipError_t launch_free_stream(State& s);
 hipError_t launch_q_from_U(State& s);
-hipError_t launch_q_derivatives(State& s);
-// residual + time step/diagonal + sweep intermediates (block partial norms)
+hipError_t launch_q_derivatives(State& s);  // includes the limiter when on
+// residual + time step/diagonal + sweep intermediates (per-point R_rho^2)
 hipError_t launch_residual(State& s, int slot);
-// residual norm from the block partials into res_hist[slot]
+// per-component residual norms into res_hist[slot][k]; retires components
 hipError_t launch_norm(State& s, int slot);
+hipError_t launch_reset_components(State& s);
 hipError_t launch_sweeps(State& s);
 hipError_t launch_sweep_dir(State& s, bool forward);
 hipError_t launch_update(State& s);
-hipError_t launch_forces(State& s, double* d_out2);
+hipError_t launch_forces(State& s);  // fsum[2k..2k+1] = force of component k
 hipError_t launch_soa_to_aos(const double* soa, D4* aos, int64_t n, hipStream_t st);
 hipError_t launch_aos_to_soa(const D4* aos, double* soa, int64_t n, hipStream_t st);
 hipError_t launch_aosf_to_soa(const F4* aos, double* soa, int64_t n, hipStream_t st);

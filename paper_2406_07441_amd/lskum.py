@@ -34,7 +34,7 @@ class Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("inner_iters", C.c_int32),
                 ("jvp_mode", C.c_int32), ("precision", C.c_int32), ("check_every", C.c_int32),
                 ("tol_rel", C.c_double), ("max_iters", C.c_int32), ("sweep_lanes", C.c_int32),
-                ("residual_lanes", C.c_int32), ("reserved", C.c_int32)]
+                ("residual_lanes", C.c_int32), ("limiter", C.c_int32), ("limiter_k", C.c_double)]
 
 
 class Report(C.Structure):
@@ -69,6 +69,16 @@ _SIGS = {
     "lskum_step_timed": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lskum_solve": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lskum_forces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lskum_batch_create": (C.c_int, [C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lskum_batch_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lskum_batch_set_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lskum_batch_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lskum_batch_step_timed": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lskum_batch_get_U": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int]),
+    "lskum_batch_set_U": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int]),
+    "lskum_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "lskum_batch_destroy": (None, [C.c_void_p]),
     "lskum_last_error": (C.c_char_p, []),
 }
 
@@ -248,3 +258,77 @@ class State:
         cl, cd = C.c_double(), C.c_double()
         _check(lib().lskum_forces(self.h, C.byref(cl), C.byref(cd)))
         return cl.value, cd.value
+
+
+class Batch:
+    """Many flow conditions iterated together (one launch per kernel/phase).
+
+    ``clouds``: list of ``Cloud``; condition k uses ``clouds[cond_cloud[k]]``
+    at (``mach[k]``, ``aoa[k]``).
+    """
+
+    def __init__(self, clouds, cond_cloud, mach, aoa, params: Params | None = None, stream=None):
+        self.clouds = list(clouds)
+        self.params = params if params is not None else default_params()
+        cc = np.ascontiguousarray(cond_cloud, np.int32)
+        m = np.ascontiguousarray(mach, np.float64)
+        a = np.ascontiguousarray(aoa, np.float64)
+        assert cc.shape == m.shape == a.shape
+        arr = (C.c_void_p * len(self.clouds))(*[c.h.value for c in self.clouds])
+        handle = None
+        if stream is not None:
+            handle = stream if isinstance(stream, int) else stream.cuda_stream
+        h = C.c_void_p()
+        _check(lib().lskum_batch_create(len(self.clouds), arr, len(cc), _ptr(cc), _ptr(m), _ptr(a),
+                                        C.byref(self.params), handle, C.byref(h)))
+        self.h = h
+        self.n_cond = len(cc)
+        self.sizes = [self.clouds[k].n for k in cc]
+        npt, nnz, nc = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib().lskum_batch_info(h, C.byref(npt), C.byref(nnz), C.byref(nc)))
+        self.n_points, self.nnz, self.n_colours = npt.value, nnz.value, nc.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lskum_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: Params):
+        _check(lib().lskum_batch_set_params(self.h, C.byref(params)))
+        self.params = params
+
+    def solve(self):
+        """Returns (list of Report dicts, total seconds)."""
+        reps = (Report * self.n_cond)()
+        tot = C.c_double()
+        code = lib().lskum_batch_solve(self.h, reps, C.byref(tot))
+        if code not in (OK, ERR_NOT_CONVERGED, ERR_NONPHYSICAL):
+            _check(code)
+        return [r.as_dict() for r in reps], tot.value
+
+    def step_timed(self) -> dict:
+        ms = np.zeros(6)
+        _check(lib().lskum_batch_step_timed(self.h, _ptr(ms)))
+        return dict(zip(State.PHASES, ms.tolist()))
+
+    def get_U(self, k: int) -> np.ndarray:
+        out = np.empty((4, self.sizes[k]))
+        _check(lib().lskum_batch_get_U(self.h, int(k), _ptr(out), 0))
+        return out
+
+    def set_U(self, k: int, U: np.ndarray):
+        U = np.ascontiguousarray(U, np.float64)
+        assert U.shape == (4, self.sizes[k])
+        _check(lib().lskum_batch_set_U(self.h, int(k), _ptr(U), 0))
+
+    def autotune(self, iters: int = 3):
+        sl, rl = C.c_int32(), C.c_int32()
+        _check(lib().lskum_batch_autotune(self.h, int(iters), C.byref(sl), C.byref(rl)))
+        self.params.sweep_lanes, self.params.residual_lanes = sl.value, rl.value
+        return sl.value, rl.value

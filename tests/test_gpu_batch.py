@@ -1,0 +1,86 @@
+"""Batched multi-condition solves through the C ABI.
+
+A batch iterates many (cloud, Mach, AoA) conditions together, one launch per
+kernel and colour phase.  Each condition's arithmetic is that of a single
+state, so a batched condition must reproduce the single-condition result
+bitwise; retirement, autotuning and reports are checked here as well.
+"""
+import numpy as np
+import pytest
+
+from paper_2406_07441_amd import cloudgen as cg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lk():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2406_07441_amd import lskum
+    lskum.lib()
+    return lskum
+
+
+@pytest.fixture(scope="module")
+def setup(lk):
+    a = cg.ogrid(96, 24, r=1.12, t=0.12)
+    b = cg.ogrid(128, 30, r=1.1, t=0.10, jitter_p=0.05, seed=3)
+    ga, gb = lk.Cloud(a), lk.Cloud(b)
+    conds = [(0, 0.5, 2.0), (1, 0.63, -1.0), (0, 0.6, 3.0)]
+    return a, b, ga, gb, conds
+
+
+def test_batch_step_equals_single_states_bitwise(lk, setup):
+    a, b, ga, gb, conds = setup
+    prm = lk.default_params(cfl=50.0, inner_iters=1)
+    bat = lk.Batch([ga, gb], [c[0] for c in conds], [c[1] for c in conds], [c[2] for c in conds], prm)
+    assert bat.n_points == 2 * a.n + b.n
+    for _ in range(3):
+        bat.step_timed()
+    for k, (ci, m, al) in enumerate(conds):
+        st = lk.State([ga, gb][ci], m, al, lk.default_params(cfl=50.0, inner_iters=1))
+        for _ in range(3):
+            st.step(want_res=False)
+        assert np.array_equal(bat.get_U(k), st.get_U()), k
+
+
+def test_batch_solve_matches_single_solves(lk, setup):
+    a, b, ga, gb, conds = setup
+    prm = lk.default_params(cfl=100.0, inner_iters=1, check_every=10, tol_rel=1e-4, max_iters=3000)
+    bat = lk.Batch([ga, gb], [c[0] for c in conds], [c[1] for c in conds], [c[2] for c in conds], prm)
+    reps, total = bat.solve()
+    assert total > 0
+    for k, (ci, m, al) in enumerate(conds):
+        st = lk.State([ga, gb][ci], m, al, lk.default_params(cfl=100.0, inner_iters=1, check_every=10,
+                                                            tol_rel=1e-4, max_iters=3000))
+        r = st.solve()
+        print(k, reps[k]["iters"], r.iters, reps[k]["status"], r.status)
+        assert reps[k]["iters"] == r.iters
+        assert reps[k]["status"] == r.status == lk.OK
+        assert reps[k]["res_final"] <= 1e-4 * reps[k]["res_fs"]
+        assert np.array_equal(bat.get_U(k), st.get_U())
+        assert reps[k]["cl"] == pytest.approx(r.cl, rel=1e-12, abs=1e-14)
+
+
+def test_batch_autotune_keeps_state(lk, setup):
+    a, b, ga, gb, conds = setup
+    prm = lk.default_params(cfl=50.0)
+    bat = lk.Batch([ga, gb], [0, 1], [0.5, 0.6], [1.0, 2.0], prm)
+    U0 = [bat.get_U(0), bat.get_U(1)]
+    sl, rl = bat.autotune(iters=2)
+    assert sl in (1, 2, 4, 8) and rl in (1, 2, 4, 8)
+    assert np.array_equal(bat.get_U(0), U0[0]) and np.array_equal(bat.get_U(1), U0[1])
+
+
+def test_batch_set_U_and_failed_condition_retires(lk, setup):
+    a, b, ga, gb, conds = setup
+    prm = lk.default_params(cfl=50.0, check_every=5, max_iters=20, tol_rel=0.0)
+    bat = lk.Batch([ga, gb], [0, 1], [0.5, 0.6], [1.0, 2.0], prm)
+    U = bat.get_U(1)
+    U[3, 500] *= 1e-9   # almost zero energy: negative pressure -> non-finite residual
+    with pytest.raises(lk.LskumError):
+        bat.set_U(1, U)
+    reps, _ = bat.solve()
+    assert reps[0]["status"] == lk.ERR_NOT_CONVERGED and reps[0]["iters"] == 20
+    assert reps[1]["status"] == lk.ERR_NONPHYSICAL and reps[1]["iters"] < 20

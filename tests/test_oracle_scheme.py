@@ -241,3 +241,40 @@ def test_zero_lift_at_zero_incidence():
     assert hist[-1] < 1e-3 * hist[0]
     cl, cd = o.forces(U)
     assert abs(cl) < 1e-5
+
+
+def test_limiter_keeps_linear_fields_and_clips_extrema():
+    # Venkatakrishnan's limiter (an addition: the paper names no limiter).
+    c = cg.box(11, 11, h=0.1)
+    o = O.Oracle(c, limiter=1, limiter_k=0.5)
+    x, y = c.x, c.y
+    lin = np.stack([0.3 + x - 2 * y, -2 + 0.4 * x, 0.1 * y, -1.4 + 0.01 * x + 0.02 * y])
+    qx, qy = o.q_grad_pass(lin)
+    lx, ly = o.limit_gradients(lin, qx, qy)
+    j, k = np.arange(c.n) % 11, np.arange(c.n) // 11
+    inner = (j >= 2) & (j <= 8) & (k >= 2) & (k <= 8)    # symmetric stencils
+    # symmetric stencils: the extreme neighbour difference is twice the
+    # reconstruction increment, where the limiter function is exactly 1
+    assert np.allclose(lx[:, inner], qx[:, inner], rtol=1e-12, atol=1e-14)
+    assert np.allclose(ly[:, inner], qy[:, inner], rtol=1e-12, atol=1e-14)
+    # a strict local maximum: no neighbour above it, so phi -> eps^2/(2 d2^2 + eps^2)
+    bump = np.exp(-((x - 0.5) ** 2 + (y - 0.5) ** 2) / 0.01)
+    q = np.stack([bump, bump, bump, bump - 3.0])
+    qx, qy = o.q_grad_pass(q)
+    lx, ly = o.limit_gradients(q, qx, qy)
+    pk = int(np.argmax(bump))
+    phi = np.hypot(lx[0, pk], ly[0, pk]) / max(np.hypot(qx[0, pk], qy[0, pk]), 1e-300)
+    assert phi <= 1.0
+    ratio = np.hypot(lx, ly) / np.maximum(np.hypot(qx, qy), 1e-300)
+    assert np.all(ratio <= 1.0 + 1e-12) and np.all(ratio >= 0.0)
+    # the limited reconstruction toward any neighbour stays within the
+    # neighbourhood's range up to the eps^2 relaxation
+    o2 = O.Oracle(c, limiter=1, limiter_k=1e-6)
+    lx, ly = o2.limit_gradients(q, qx, qy)
+    for p in np.where(inner)[0]:
+        nb = c.nbr_idx[c.nbr_off[p]:c.nbr_off[p + 1]]
+        dx, dy = c.x[nb] - c.x[p], c.y[nb] - c.y[p]
+        rec = q[0, p] - 0.5 * (dx * lx[0, p] + dy * ly[0, p])
+        lo = min(q[0, nb].min(), q[0, p])
+        hi = max(q[0, nb].max(), q[0, p])
+        assert np.all(rec <= hi + 1e-9) and np.all(rec >= lo - 1e-9)
