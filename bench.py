@@ -1,23 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the implicit LSKUM hot path on one MI355X.
 
-Workload: the transonic NACA 0012-type case -- 640 x 256 = 163,840-point
-O-grid cloud with 4% of interior points jittered (seed 2406), Mach 0.85,
-AoA 1 deg, exact-JVP modified LU-SGS in FP64, CFL 100, first-order q-derivative
-pass only (no inner iterations: without a limiter the transonic start diverges
-with them).
-A step is one implicit iteration: q-derivatives, residual, forward and
-backward colour sweeps, state update.  ``value`` is point-iterations per
+Workload (the timed steps): the transonic NACA 0012-type case -- a
+640 x 256 = 163,840-point O-grid cloud with 4% of interior points jittered
+(seed 2406), Mach 0.85, AoA 1 deg; exact-JVP modified LU-SGS in FP64, CFL 100,
+one inner iteration of the q-derivatives, Venkatakrishnan limiter (K = 5) on
+the q~ reconstruction (the shock needs it to converge; the paper names none).
+A step is one implicit iteration: q-derivatives, limiter, residual, forward
+and backward colour sweeps, state update.  ``value`` is point-iterations per
 second over the timed steps (HIP-graph replay, inputs resident in HBM).
 
 Also reported: per-phase GPU times from HIP events, the roofline of the
-dominant kernel, time to a 1e-8 residual drop for the exact and the
-flux-difference Jacobian products, and the CPU oracle's rate on a bounded
-sample of the same workload.
+dominant kernel, time to a 1e-8 residual drop with exact and flux-difference
+Jacobian products (FP64) and with mixed precision, the batched 64-condition
+workload, and the CPU oracle's rate on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,15 +27,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-MACH, AOA, CFL, INNER = 0.85, 1.0, 100.0, 0
+MACH, AOA, CFL, INNER, LIMITER, LIMITER_K = 0.85, 1.0, 100.0, 1, 1, 5.0
 
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 
-# Algorithmic FP64 operation count of the residual per (point, neighbour,
-# split) and per (point, neighbour), with elementary functions costed at the
-# operation count of a standard software evaluation (documented in the design doc).
+# Algorithmic FP64 operation count of the residual, with elementary functions
+# costed at the operation count of a standard software evaluation.
 COST = {"exp": 14, "erf": 26, "sqrt": 8, "div": 8, "log": 20}
 # per neighbour: dx, dy; two q~ reconstructions (4 x 5 each); two q~ -> primitive
 # conversions (11 arithmetic + exp + sqrt + 2 div each)
@@ -43,6 +43,13 @@ NB_OPS = 2 + 40 + 2 * (11 + COST["exp"] + COST["sqrt"] + 2 * COST["div"])
 # + div each), difference, scale and accumulate (12)
 SPLIT_OPS = 3 + 2 * (25 + COST["erf"] + COST["exp"] + COST["div"]) + 12
 
+# Algorithmic bytes of one sweep (all colour phases) per point, each array
+# read or written once: own R 32 (forward) or dU* 32 (backward), D 8,
+# list offsets 8, coordinates 16, geometry split coefficients 64, type 1,
+# result 32; the point's linearisation data (96) and increment (32) read by
+# its neighbours; 4 bytes per list entry.
+SWEEP_POINT_BYTES = 32 + 8 + 8 + 16 + 64 + 1 + 32 + 96 + 32
+
 
 def residual_flops(cloud) -> float:
     """Algorithmic FP64 operations of one residual evaluation of the cloud."""
@@ -50,28 +57,84 @@ def residual_flops(cloud) -> float:
     typ = cloud.type
     deg = np.diff(cloud.nbr_off)
     active = typ != 2
-    # every neighbour of an interior point lies in one x-split and one y-split
-    # (ties dx == 0 / dy == 0 are rare); wall points: t-split plus n-split for
-    # fluid-side neighbours, counted here as 1.5 splits per neighbour
+    # every neighbour of an interior point lies in one x-split and one y-split;
+    # wall points: t-split plus the n-split for fluid-side neighbours (1.5)
     splits = np.where(typ == 1, 2.0, 1.5)
     return float(np.sum(deg[active] * (NB_OPS + splits[active] * SPLIT_OPS)))
 
 
-def time_to_tol(lk, gc, jvp_mode, precision, max_iters):
-    prm = lk.default_params(cfl=CFL, inner_iters=INNER, jvp_mode=jvp_mode, precision=precision,
-                            check_every=20, tol_rel=1e-8, max_iters=max_iters)
+def sweep_bytes(cloud) -> float:
+    """Algorithmic HBM bytes of one sweep direction over the whole cloud."""
+    return float(cloud.n * SWEEP_POINT_BYTES + 4 * cloud.nnz / 2)
+
+
+def device_source_hash() -> str:
+    src = os.path.join(ROOT, "paper_2406_07441_amd", "csrc", "lskum_device.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE counter runs,
+    when the summary in profiles/ was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_163840_transonic_fp64.md")
+    if not os.path.exists(path):
+        return None
+    out = {}
+    for line in open(path):
+        if line.startswith("source_sha256:"):
+            if line.split(":", 1)[1].strip() != device_source_hash():
+                return None
+        if line.startswith("| `") and "|" in line[3:]:
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            try:
+                out[cells[0].strip("`")] = float(cells[-1])
+            except ValueError:
+                pass
+    return out or None
+
+
+def params(lk, **kw):
+    base = dict(cfl=CFL, inner_iters=INNER, limiter=LIMITER, limiter_k=LIMITER_K)
+    base.update(kw)
+    return lk.default_params(**base)
+
+
+def time_to_tol(lk, gc, max_iters, **kw):
+    prm = params(lk, check_every=100, tol_rel=1e-8, max_iters=max_iters, **kw)
     st = lk.State(gc, MACH, AOA, prm)
     rep = st.solve()
     out = {"converged": rep.status == 0, "iters": rep.iters, "seconds": rep.seconds,
            "res_drop": rep.res_final / rep.res_fs if rep.res_fs else None,
-           "cl": rep.cl, "cd": rep.cd, "status": rep.status}
+           "cl": rep.cl, "cd": rep.cd}
     st.close()
+    return out
+
+
+def batch_run(lk, cloudgen, iters):
+    """64 conditions on 8 uneven clouds, FP32 sweeps / FP64 residual, autotuned."""
+    import numpy as np
+    clouds = cloudgen.batch_clouds()
+    gcs = [lk.Cloud(c) for c in clouds]
+    mach, aoa = cloudgen.batch_conditions()
+    prm = lk.default_params(cfl=CFL, inner_iters=INNER, precision=lk.MIXED, limiter=LIMITER,
+                            limiter_k=LIMITER_K, check_every=50, tol_rel=0.0, max_iters=iters)
+    b = lk.Batch(gcs, np.arange(64) % 8, mach, aoa, prm)
+    lanes = b.autotune(2)
+    reps, tot = b.solve()
+    pts = sum(r["iters"] * b.sizes[k] for k, r in enumerate(reps))
+    out = {"conditions": 64, "clouds": [c.n for c in clouds], "points": b.n_points,
+           "colour_phases": b.n_colours, "iters": iters, "seconds": tot,
+           "point_iters_per_s": pts / tot, "lanes": {"sweep": lanes[0], "residual": lanes[1]},
+           "failed": int(sum(r["status"] == lk.ERR_NONPHYSICAL for r in reps)),
+           "median_res_drop": float(np.median([r["res_final"] / r["res_fs"] for r in reps]))}
+    b.close()
     return out
 
 
 def cpu_baseline(cloud, iters: int):
     import oracle
-    o = oracle.Oracle(cloud, mach=MACH, aoa_deg=AOA, cfl=CFL, inner_iters=INNER)
+    o = oracle.Oracle(cloud, mach=MACH, aoa_deg=AOA, cfl=CFL, inner_iters=INNER,
+                      limiter=LIMITER, limiter_k=LIMITER_K)
     U = o.free_stream()
     t0 = time.perf_counter()
     for _ in range(iters):
@@ -87,11 +150,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
-    ap.add_argument("--tol-iters", type=int, default=20000,
+    ap.add_argument("--tol-iters", type=int, default=60000,
                     help="iteration cap of the time-to-1e-8 runs (0 skips them)")
+    ap.add_argument("--batch-iters", type=int, default=200,
+                    help="iterations of the 64-condition batch run (0 skips it)")
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle iterations (0 skips)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the timed steps (for profiler runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
@@ -101,16 +168,21 @@ def main():
         print("--steps and --warmup must be multiples of 10", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_2406_07441_amd import cloudgen
     from paper_2406_07441_amd import lskum as lk
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cloud = cloudgen.cloud_163840()
     gc = lk.Cloud(cloud)
-    prm = lk.default_params(cfl=CFL, inner_iters=INNER, check_every=10, tol_rel=0.0,
-                            max_iters=args.warmup)
+    prm = params(lk, check_every=10, tol_rel=0.0, max_iters=args.warmup)
     st = lk.State(gc, MACH, AOA, prm)
     print(f"# cloud n={cloud.n} nnz={cloud.nnz} colours={gc.n_colours} "
           f"degenerate={gc.n_degenerate}", file=sys.stderr, flush=True)
@@ -138,25 +210,46 @@ def main():
         ph = st.step_timed()
         acc = ph if acc is None else {k: acc[k] + ph[k] for k in acc}
     phases = {k: v / nt for k, v in acc.items()}
-    res_ms = phases["residual"]
-    flops = residual_flops(cloud)
-    achieved = flops / (res_ms * 1e-3) / 1e12
-    roofline = {"kernel": "k_residual", "bound": "alu", "achieved": achieved,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": None, "flops_per_launch": flops, "avg_ms": res_ms}
     st.close()
+    ncol = gc.n_colours
+    traffic = measured_traffic()
+    flops = residual_flops(cloud)
+    res_ms = phases["residual"]
+    res_tf = flops / (res_ms * 1e-3) / 1e12
+    sweep_ms = phases["forward_sweep"] / ncol          # average launch of a colour phase
+    sweep_b = sweep_bytes(cloud) / ncol                # algorithmic bytes per launch
+    sweep_gbs = sweep_b / (sweep_ms * 1e-3) / 1e9
+    kernels = {
+        "k_sweep_forward": {"bound": "hbm", "achieved": sweep_gbs, "peak": PEAK_HBM_GBS,
+                            "unit": "GB/s", "frac": sweep_gbs / PEAK_HBM_GBS,
+                            "traffic": (traffic or {}).get("k_sweep_forward"),
+                            "bytes_per_launch": sweep_b, "avg_ms": sweep_ms,
+                            "launches_per_step": ncol,
+                            "ms_per_step": phases["forward_sweep"]},
+        "k_residual": {"bound": "alu", "achieved": res_tf, "peak": PEAK_FP64_TFLOPS,
+                       "unit": "TFLOP/s", "frac": res_tf / PEAK_FP64_TFLOPS,
+                       "traffic": (traffic or {}).get("k_residual"),
+                       "flops_per_launch": flops, "avg_ms": res_ms, "launches_per_step": 1,
+                       "ms_per_step": res_ms},
+    }
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    roofline = {"kernel": dom, **{k: v for k, v in kernels[dom].items()
+                                  if k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}}
     if args.profile_only:
-        print(json.dumps({"ms_per_step": ms_per_step, "phases_ms": phases}))
+        print(json.dumps({"ms_per_step": ms_per_step, "phases_ms": phases, "roofline": roofline}))
         return
 
     extra = {}
     if args.tol_iters > 0:
         extra["time_to_1e-8"] = {
-            "exact_fp64": time_to_tol(lk, gc, lk.JVP_EXACT, lk.FP64, args.tol_iters),
-            "fluxdiff_fp64": time_to_tol(lk, gc, lk.JVP_FLUXDIFF, lk.FP64, args.tol_iters),
-            "exact_mixed": time_to_tol(lk, gc, lk.JVP_EXACT, lk.MIXED, args.tol_iters),
+            "exact_fp64": time_to_tol(lk, gc, args.tol_iters),
+            "fluxdiff_fp64": time_to_tol(lk, gc, args.tol_iters, jvp_mode=lk.JVP_FLUXDIFF),
+            "exact_mixed": time_to_tol(lk, gc, args.tol_iters, precision=lk.MIXED),
         }
         print(f"# time to tol: {json.dumps(extra['time_to_1e-8'])}", file=sys.stderr, flush=True)
+    if args.batch_iters > 0:
+        extra["batch_64_conditions"] = batch_run(lk, cloudgen, args.batch_iters)
+        print(f"# batch: {json.dumps(extra['batch_64_conditions'])}", file=sys.stderr, flush=True)
     cpu = cpu_baseline(cloud, args.cpu_iters) if args.cpu_iters > 0 else None
 
     line = {
@@ -165,9 +258,11 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "O-grid NACA0012-type cloud 640x256=163840 pts, 4% jittered, "
-                               "M0.85 AoA1, exact-JVP LU-SGS FP64, CFL100, no inner iterations",
-                   "points": cloud.n, "edges": cloud.nnz, "colours": gc.n_colours},
-        "roofline": roofline, "cpu_baseline": cpu, "phases_ms": phases, **extra,
+                               "M0.85 AoA1, exact-JVP LU-SGS FP64, CFL100, 1 inner iteration, "
+                               "limiter K5",
+                   "points": cloud.n, "edges": cloud.nnz, "colours": ncol},
+        "roofline": roofline, "roofline_kernels": kernels, "cpu_baseline": cpu,
+        "phases_ms": phases, **extra,
     }
     print(json.dumps(line))
 

@@ -224,6 +224,88 @@ int lskum_batch_autotune(lskum_batch* b, int32_t iters, int32_t* sweep_lanes,
 
 void lskum_batch_destroy(lskum_batch* b);
 
+/* ---- Learned warm start (an addition; the paper starts every solve from
+ * the free stream).  A per-point perceptron 5 -> 128 -> 128 -> 128 -> 4 with
+ * GELU (erf form) hidden layers maps the features of a point to its
+ * deviation from the free stream, (rho - 1, u - u_inf, v - v_inf,
+ * gamma p - 1).  Features: f0 = (x - 1/2) / (1 + r), f1 = y / (1 + r) with
+ * r = |(x - 1/2, y)|; f2 = 2 d / (d + 0.1) - 1 with d the distance to the
+ * nearest wall point of the point's own cloud; f3 = (M - 0.6) / 0.25;
+ * f4 = (aoa_deg - 2) / 6.
+ * Numerics: bfloat16 copies (round to nearest even) of the weights, the
+ * features and each hidden activation; fp32 accumulation (the two
+ * 128 x 128 layers and their backward products on the matrix cores); the
+ * backward pass rounds the pre-activation gradients of layers 3 and 2 to
+ * bfloat16; fp32 master weights and Adam moments.
+ * Parameters: one flat fp32 vector of LSKUM_MLP_PARAMS entries laid out as
+ * W1[128][5], b1[128], W2[128][128], b2, W3[128][128], b3, W4[4][128], b4[4]
+ * (W[out][in]).  Loss: mean over rows and outputs of (y - t)^2.
+ * Feature rows X are [m][5] fp32 and target/prediction rows [m][4] fp32,
+ * row-major, always device pointers.  Work runs on the stream given at
+ * lskum_mlp_create (NULL = a private stream); calls that take a state or
+ * batch synchronise both streams. */
+#define LSKUM_MLP_PARAMS 34308
+#define LSKUM_MLP_FEATURES 5
+#define LSKUM_MLP_OUTPUTS 4
+typedef struct lskum_mlp lskum_mlp;
+
+/* Creates a network on the current device with Glorot-uniform weights drawn
+ * from splitmix64(seed) (zero biases) and a workspace of max_rows rows
+ * (the largest m of lskum_mlp_gradient / train_step, and the minibatch
+ * limit of lskum_mlp_train).  Errors: ARG (max_rows < 1 or > 2^24), HIP, OOM. */
+int lskum_mlp_create(uint64_t seed, int64_t max_rows, void* hip_stream, lskum_mlp** out);
+void lskum_mlp_destroy(lskum_mlp* net);
+
+/* Copies the fp32 parameters out / in (LSKUM_MLP_PARAMS floats).  Setting
+ * the parameters also clears the Adam moments and step count. */
+int lskum_mlp_get_params(lskum_mlp* net, float* theta, int on_device);
+int lskum_mlp_set_params(lskum_mlp* net, const float* theta, int on_device);
+
+/* Predictions Y[m][4] for features X[m][5] (any m >= 0; processed in chunks
+ * of max_rows). */
+int lskum_mlp_forward(lskum_mlp* net, int64_t m, const float* X, float* Y);
+
+/* Loss (host double, may be NULL) and its gradient with respect to the
+ * parameters (device, LSKUM_MLP_PARAMS floats, may be NULL) over m rows
+ * (1 <= m <= max_rows), without changing the parameters. */
+int lskum_mlp_gradient(lskum_mlp* net, int64_t m, const float* X, const float* T, float* grad,
+                       double* loss);
+
+/* One full-batch Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate
+ * lr) on m rows (1 <= m <= max_rows); *loss (may be NULL) is the loss before
+ * the step. */
+int lskum_mlp_train_step(lskum_mlp* net, int64_t m, const float* X, const float* T, float lr,
+                         double* loss);
+
+/* Minibatch Adam training on a device data set of n rows: `steps` steps of
+ * `batch` rows (batch <= max_rows); row r of step t is data-set row
+ * floor(h n / 2^64), h = splitmix64(seed + t batch + r).  The learning rate
+ * decays from lr to lr_final on a half cosine.  loss_hist (host, `steps`
+ * doubles, may be NULL): minibatch loss of each step; *seconds (may be NULL):
+ * GPU wall time. */
+int lskum_mlp_train(lskum_mlp* net, int64_t n, const float* X, const float* T, int32_t steps,
+                    int32_t batch, float lr, float lr_final, uint64_t seed, double* loss_hist,
+                    double* seconds);
+
+/* Features X[n][5] of every point of a state / batch (points in storage
+ * order, conditions one after the other) and, with T != NULL, training
+ * targets T[n][4] from the current state U. */
+int lskum_state_features(lskum_state* s, float* X, float* T);
+int lskum_batch_features(lskum_batch* b, float* X, float* T);
+
+/* Warm start: sets U of every point to the network's prediction (outer
+ * points at the free stream, wall points with tangential velocity only),
+ * then judges each condition by its residual norm: a condition whose
+ * prediction is non-finite or non-physical (rho < 0.05 or gamma p < 0.05),
+ * or whose residual is not below its free-stream residual, goes back to the
+ * free stream.  fallback / res_warm (host, 1 entry for a state, n_cond for a
+ * batch; may be NULL): 1 where the free stream was kept, and the residual
+ * norm of the predicted state.  The tolerance of later solves stays
+ * tol_rel times the free-stream residual. */
+int lskum_mlp_warm_start(lskum_mlp* net, lskum_state* s, int32_t* fallback, double* res_warm);
+int lskum_mlp_warm_start_batch(lskum_mlp* net, lskum_batch* b, int32_t* fallback,
+                               double* res_warm);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char* lskum_last_error(void);
 

@@ -5,8 +5,9 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = [os.path.join(HERE, "csrc", "lskum_device.hip"), os.path.join(HERE, "csrc", "lskum_api.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "lskum_internal.h"),
+SOURCES = [os.path.join(HERE, "csrc", f) for f in
+           ("lskum_device.hip", "lskum_api.hip", "lskum_mlp.hip", "lskum_mlp_api.hip")]
+HEADERS = [os.path.join(HERE, "csrc", "lskum_internal.h"), os.path.join(HERE, "csrc", "lskum_mlp.h"),
            os.path.join(os.path.dirname(HERE), "include", "lskum.h")]
 LIB = os.path.join(HERE, "liblskum.so")
 

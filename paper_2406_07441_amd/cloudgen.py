@@ -11,9 +11,13 @@ published):
 
 * profile: symmetric NACA 4-digit thickness with the closed trailing-edge
   coefficient -0.1036, thickness ratio ``t``;
-* wall points j = 0..Nw-1 at phi_j = 2*pi*j/Nw, x_j = (1 + cos phi_j)/2,
-  y = +thickness for phi <= pi and -thickness otherwise (j = 0 is the trailing
-  edge, j = Nw/2 the leading edge, (j, Nw-j) are mirror pairs);
+* wall points j = 0..Nw-1 at x_j = 1 - cos(psi_j), psi_j = pi/2 |1 - 2j/Nw|
+  (clustered at the leading edge, linear at the trailing edge), y = +thickness
+  for j <= Nw/2 and -thickness otherwise (j = 0 is the trailing edge, j = Nw/2
+  the leading edge, (j, Nw-j) are mirror pairs).  The alternative
+  ``spacing="cosine"`` (x = (1 + cos 2 pi j/Nw)/2) also clusters at the
+  trailing edge; on the finer clouds its trailing-edge points (spacing
+  ~1e-5 chord against ~1e-3 normal) drive the implicit iteration unstable;
 * far field F_j = (0.5, 0) + 15 (cos phi_j, sin phi_j);
 * layers k = 0..K-1 at P_jk = W_j + s_k (F_j - W_j), s_k = (r^k - 1)/(r^(K-1) - 1);
 * point index p = k*Nw + j; k = 0 wall, k = K-1 outer (free stream), else interior;
@@ -91,12 +95,21 @@ def naca_thickness(x: np.ndarray, t: float) -> np.ndarray:
                       + 0.2843 * x ** 3 - 0.1036 * x ** 4)
 
 
-def wall_points(nw: int, t: float) -> tuple[np.ndarray, np.ndarray]:
+def wall_points(nw: int, t: float, spacing: str = "le") -> tuple[np.ndarray, np.ndarray]:
+    """Wall points: ``cosine`` x = (1 + cos phi)/2 clusters at both edges;
+    ``le`` x = 1 - cos(psi), psi = pi/2 |1 - 2 j/nw|, clusters at the leading
+    edge only and is linear near the trailing edge."""
     if nw < 8 or nw % 2:
         raise ValueError("nw must be even and >= 8")
     j = np.arange(nw)
     phi = 2.0 * np.pi * j / nw
-    xw = 0.5 * (1.0 + np.cos(phi))
+    if spacing == "cosine":
+        xw = 0.5 * (1.0 + np.cos(phi))
+    elif spacing == "le":
+        psi = 0.5 * np.pi * np.abs(1.0 - 2.0 * j / nw)
+        xw = 1.0 - np.cos(psi)
+    else:
+        raise ValueError(spacing)
     yt = naca_thickness(np.clip(xw, 0.0, 1.0), t)
     yw = np.where(j <= nw // 2, yt, -yt)
     yw[0] = 0.0
@@ -120,9 +133,9 @@ def far_field_points(nw: int) -> tuple[np.ndarray, np.ndarray]:
     return fx, fy
 
 
-def stretch_for_first_spacing(nw: int, nk: int, t: float) -> float:
+def stretch_for_first_spacing(nw: int, nk: int, t: float, spacing: str = "le") -> float:
     """Ratio r whose first normal spacing equals the mean wall spacing."""
-    xw, yw = wall_points(nw, t)
+    xw, yw = wall_points(nw, t, spacing)
     per = np.hypot(np.roll(xw, -1) - xw, np.roll(yw, -1) - yw).sum()
     fx, fy = far_field_points(nw)
     length = np.hypot(fx - xw, fy - yw).mean()
@@ -139,13 +152,14 @@ def stretch_for_first_spacing(nw: int, nk: int, t: float) -> float:
 
 
 def ogrid(nw: int, nk: int, r: float | None = None, t: float = 0.12,
-          jitter_p: float = 0.0, seed: int = 2406, name: str = "") -> Cloud:
+          jitter_p: float = 0.0, seed: int = 2406, name: str = "",
+          spacing: str = "le") -> Cloud:
     """O-grid point cloud around a NACA 00tt profile (see module docstring)."""
     if nk < 5:
         raise ValueError("need at least 5 rings")
     if r is None:
-        r = stretch_for_first_spacing(nw, nk, t)
-    xw, yw = wall_points(nw, t)
+        r = stretch_for_first_spacing(nw, nk, t, spacing)
+    xw, yw = wall_points(nw, t, spacing)
     fx, fy = far_field_points(nw)
     k = np.arange(nk, dtype=np.float64)
     s = (r ** k - 1.0) / (r ** (nk - 1) - 1.0)

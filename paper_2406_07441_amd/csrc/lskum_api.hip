@@ -20,18 +20,6 @@
 #include <string>
 #include <vector>
 
-struct lskum_cloud {
-    lskum::Cloud c;
-};
-struct lskum_state {
-    lskum::State s;
-};
-struct lskum_batch {
-    lskum::Cloud c;  // union of the conditions' clouds
-    lskum::State s;
-    std::vector<int32_t> cond_cloud;
-};
-
 namespace {
 
 thread_local std::string g_err;
@@ -71,7 +59,7 @@ void free_cloud(lskum::Cloud& c) {
     void* ptrs[] = {c.xy,     c.frame,     c.type,   c.off,      c.idx,      c.colour,
                     c.col_perm, c.wall_list, c.geom, c.lo_off,   c.lo_idx,   c.up_off,
                     c.up_idx, c.comp,      c.comp_off, c.wall_off, c.comp_inv_active,
-                    c.comp_orient};
+                    c.comp_orient, c.chunk_start, c.chunk_comp, c.comp_chunk_off};
     for (void* p : ptrs) (void)hipFree(p);
     c = lskum::Cloud{};
 }
@@ -236,6 +224,21 @@ int upload_cloud(lskum::Cloud& c) {
     chk(dalloc(&c.wall_off, c.ncomp + 1));
     chk(dalloc(&c.comp_inv_active, c.ncomp));
     chk(dalloc(&c.comp_orient, c.ncomp));
+    // reduction chunks of at most 1024 points, never straddling components
+    constexpr int64_t kChunk = 1024;
+    std::vector<int32_t> chunk_start, chunk_comp, comp_chunk_off(c.ncomp + 1, 0);
+    for (int32_t k = 0; k < c.ncomp; ++k) {
+        for (int64_t p = c.h_comp_off[k]; p < c.h_comp_off[k + 1]; p += kChunk) {
+            chunk_start.push_back((int32_t)p);
+            chunk_comp.push_back(k);
+        }
+        comp_chunk_off[k + 1] = (int32_t)chunk_comp.size();
+    }
+    chunk_start.push_back((int32_t)n);
+    c.nchunk = (int32_t)chunk_comp.size();
+    chk(dalloc(&c.chunk_start, chunk_start.size()));
+    chk(dalloc(&c.chunk_comp, chunk_comp.size()));
+    chk(dalloc(&c.comp_chunk_off, comp_chunk_off.size()));
     std::vector<int32_t> comp;
     if (c.ncomp > 1) {
         comp.resize(n);
@@ -261,6 +264,9 @@ int upload_cloud(lskum::Cloud& c) {
         chk(upload(c.comp_inv_active, c.h_comp_inv_active.data(), c.ncomp));
         chk(upload(c.comp_orient, c.h_comp_orient.data(), c.ncomp));
         if (c.comp) chk(upload(c.comp, comp.data(), n));
+        chk(upload(c.chunk_start, chunk_start.data(), chunk_start.size()));
+        chk(upload(c.chunk_comp, chunk_comp.data(), chunk_comp.size()));
+        chk(upload(c.comp_chunk_off, comp_chunk_off.data(), comp_chunk_off.size()));
     }
     if (e == hipSuccess) {
         hipError_t pe = lskum::launch_precompute(c, nullptr);
@@ -278,7 +284,7 @@ void free_state(lskum::State& s) {
         for (hipEvent_t ev : s.ev) (void)hipEventDestroy(ev);
     void* ptrs[] = {s.U,    s.q,      s.qx[0], s.qx[1],  s.qy[0],   s.qy[1],    s.qxl,
                     s.qyl,  s.R,      s.dU,    s.jv0,    s.jv1,     s.jv2,      s.D,
-                    s.jv0f, s.jv1f,   s.jv2f,  s.dUf,    s.Df,      s.rr,       s.fsum,
+                    s.jv0f, s.jv1f,   s.jv2f,  s.dUf,    s.Df,      s.rr,       s.fsum, s.partial,
                     s.res_hist, s.flags, s.active, s.status, s.iters, s.res_last, s.tol_abs,
                     s.vinf};
     for (void* p : ptrs) (void)hipFree(p);
@@ -411,6 +417,7 @@ int init_state(lskum::State& s, const lskum::Cloud& c, const lskum_params* prm,
     chk(dalloc(&s.Df, n));
     chk(dalloc(&s.rr, n));
     chk(dalloc(&s.fsum, 2 * nc));
+    chk(dalloc(&s.partial, c.nchunk));
     chk(dalloc(&s.res_hist, (size_t)s.res_cap * nc));
     chk(dalloc(&s.flags, 4));
     chk(dalloc(&s.active, nc));
@@ -558,6 +565,10 @@ void fill_report(lskum_report& r, const lskum::State& s, const SolveOut& o, int 
 }
 
 }  // namespace
+
+int lskum::api_error(int code, const std::string& msg) { return fail(code, msg); }
+
+void lskum::api_clear_error() { g_err.clear(); }
 
 extern "C" {
 

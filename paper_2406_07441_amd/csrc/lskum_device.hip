@@ -260,36 +260,65 @@ __global__ void __launch_bounds__(kBlock) k_q_from_U(int64_t n, double gamma,
 }
 
 // ---------------------------------------------------------------------------
-// q-derivatives (eq. 16): first-order pass and Jacobi inner passes.
+// q-derivatives (eq. 16): first-order pass and Jacobi inner passes, with the
+// optional limiter fused into the last pass.
+//
+// Venkatakrishnan's limiter on the q~ reconstruction (an addition: the paper
+// names no limiter).  Per point and component, phi = min over neighbours of
+//   (d1^2 + eps^2 + 2 d1 d2) / (d1^2 + 2 d2^2 + d1 d2 + eps^2),
+// d2 = -(dx qx + dy qy)/2 the reconstruction increment toward the neighbour,
+// d1 the largest (d2 > 0) or smallest (d2 < 0) neighbour difference,
+// eps^2 = (K h)^3 with h the nearest-neighbour distance; phi clamped to >= 0.
+// The denominator is positive, so the minimum is tracked as a fraction and
+// divided once.  The limited derivatives phi * (qx, qy) go to qxl, qyl.
+//
+// LANES consecutive lanes share one point and split its neighbours; the LS
+// right-hand sides, the neighbour extrema and the limiter minimum are
+// combined with cross-lane shuffles.
 // ---------------------------------------------------------------------------
-template <bool INNER>
-__global__ void __launch_bounds__(kBlock) k_qgrad(int64_t n, const D2* __restrict__ xy,
-                                                  const int32_t* __restrict__ off,
-                                                  const int32_t* __restrict__ idx,
-                                                  const PointGeom* __restrict__ geom,
-                                                  const int32_t* __restrict__ comp,
-                                                  const int32_t* __restrict__ active,
-                                                  const D4* __restrict__ q,
-                                                  const D4* __restrict__ qx_in,
-                                                  const D4* __restrict__ qy_in,
-                                                  D4* __restrict__ qx_out, D4* __restrict__ qy_out) {
-    const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (p >= n || !live(comp, active, p)) return;
+template <int LANES>
+__device__ __forceinline__ double lane_sum(double v) {
+#pragma unroll
+    for (int o = LANES / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <bool INNER, bool LIMIT, int LANES>
+__global__ void __launch_bounds__(kBlock) k_qgrad(
+    int64_t n, double K, const D2* __restrict__ xy, const int32_t* __restrict__ off,
+    const int32_t* __restrict__ idx, const PointGeom* __restrict__ geom,
+    const int32_t* __restrict__ comp, const int32_t* __restrict__ active,
+    const D4* __restrict__ q, const D4* __restrict__ qx_in, const D4* __restrict__ qy_in,
+    D4* __restrict__ qx_out, D4* __restrict__ qy_out, D4* __restrict__ qxl,
+    D4* __restrict__ qyl) {
+    const int64_t gt = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t p = gt / LANES;
+    const int lane = (int)(gt % LANES);
+    if (p >= n || !live(comp, active, p)) return;  // uniform over the lanes of a point
     const D2 r0 = xy[p];
     const D4 q0 = q[p];
+    const double qv[4] = {q0.x, q0.y, q0.z, q0.w};
     D4 gx0{}, gy0{};
     if (INNER) {
         gx0 = qx_in[p];
         gy0 = qy_in[p];
     }
     double bx[4] = {0, 0, 0, 0}, by[4] = {0, 0, 0, 0};
+    double dmax[4] = {0, 0, 0, 0}, dmin[4] = {0, 0, 0, 0};
     const int32_t e0 = off[p], e1 = off[p + 1];
-    for (int32_t e = e0; e < e1; ++e) {
+    for (int32_t e = e0 + lane; e < e1; e += LANES) {
         const int32_t i = idx[e];
         const D2 ri = xy[i];
         const double dx = ri.x - r0.x, dy = ri.y - r0.y;
         const D4 qi = q[i];
-        double dq[4] = {qi.x - q0.x, qi.y - q0.y, qi.z - q0.z, qi.w - q0.w};
+        double dq[4] = {qi.x - qv[0], qi.y - qv[1], qi.z - qv[2], qi.w - qv[3]};
+        if (LIMIT) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                dmax[v] = fmax(dmax[v], dq[v]);
+                dmin[v] = fmin(dmin[v], dq[v]);
+            }
+        }
         if (INNER) {
             const D4 gxi = qx_in[i], gyi = qy_in[i];
             dq[0] -= 0.5 * (dx * (gxi.x - gx0.x) + dy * (gyi.x - gy0.x));
@@ -303,68 +332,67 @@ __global__ void __launch_bounds__(kBlock) k_qgrad(int64_t n, const D2* __restric
             by[v] += dy * dq[v];
         }
     }
-    const D4 L = geom[p].lsq;
-    qx_out[p] = {L.x * bx[0] + L.y * by[0], L.x * bx[1] + L.y * by[1], L.x * bx[2] + L.y * by[2],
-                 L.x * bx[3] + L.y * by[3]};
-    qy_out[p] = {L.y * bx[0] + L.z * by[0], L.y * bx[1] + L.z * by[1], L.y * bx[2] + L.z * by[2],
-                 L.y * bx[3] + L.z * by[3]};
-}
-
-// Venkatakrishnan's limiter on the q~ reconstruction (an addition: the paper
-// names no limiter).  Per point and component, phi = min over neighbours of
-//   (d1^2 + eps^2 + 2 d1 d2) / (d1^2 + 2 d2^2 + d1 d2 + eps^2),
-// d2 = -(dx qx + dy qy)/2 the reconstruction increment toward the neighbour,
-// d1 the largest (d2 > 0) or smallest (d2 < 0) neighbour difference,
-// eps^2 = (K h)^3 with h the nearest-neighbour distance; phi clamped to >= 0.
-// Writes phi * (qx, qy).
-__global__ void __launch_bounds__(kBlock) k_limiter(int64_t n, double K, const D2* __restrict__ xy,
-                                                    const int32_t* __restrict__ off,
-                                                    const int32_t* __restrict__ idx,
-                                                    const PointGeom* __restrict__ geom,
-                                                    const int32_t* __restrict__ comp,
-                                                    const int32_t* __restrict__ active,
-                                                    const D4* __restrict__ q,
-                                                    const D4* __restrict__ qx,
-                                                    const D4* __restrict__ qy,
-                                                    D4* __restrict__ qxl, D4* __restrict__ qyl) {
-    const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (p >= n || !live(comp, active, p)) return;
-    const D2 r0 = xy[p];
-    const D4 q0 = q[p];
-    const D4 gx = qx[p], gy = qy[p];
-    const double g_x[4] = {gx.x, gx.y, gx.z, gx.w}, g_y[4] = {gy.x, gy.y, gy.z, gy.w};
-    const double qv[4] = {q0.x, q0.y, q0.z, q0.w};
-    double dmax[4] = {0, 0, 0, 0}, dmin[4] = {0, 0, 0, 0};
-    const int32_t e0 = off[p], e1 = off[p + 1];
-    for (int32_t e = e0; e < e1; ++e) {
-        const D4 qi = q[idx[e]];
-        const double d[4] = {qi.x - qv[0], qi.y - qv[1], qi.z - qv[2], qi.w - qv[3]};
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            dmax[v] = fmax(dmax[v], d[v]);
-            dmin[v] = fmin(dmin[v], d[v]);
-        }
+    for (int v = 0; v < 4; ++v) {
+        bx[v] = lane_sum<LANES>(bx[v]);
+        by[v] = lane_sum<LANES>(by[v]);
     }
-    const double kh = K * geom[p].lsq.w;
+    const PointGeom& G = geom[p];
+    const D4 L = G.lsq;
+    double gx[4], gy[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        gx[v] = L.x * bx[v] + L.y * by[v];
+        gy[v] = L.y * bx[v] + L.z * by[v];
+    }
+    if (lane == 0) {
+        qx_out[p] = {gx[0], gx[1], gx[2], gx[3]};
+        qy_out[p] = {gy[0], gy[1], gy[2], gy[3]};
+    }
+    if (!LIMIT) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int o = LANES / 2; o > 0; o >>= 1) {
+            dmax[v] = fmax(dmax[v], __shfl_xor(dmax[v], o, 64));
+            dmin[v] = fmin(dmin[v], __shfl_xor(dmin[v], o, 64));
+        }
+    const double kh = K * L.w;
     const double eps2 = kh * kh * kh;
-    double phi[4] = {1.0, 1.0, 1.0, 1.0};
-    for (int32_t e = e0; e < e1; ++e) {
+    double fn[4] = {1, 1, 1, 1}, fd[4] = {1, 1, 1, 1};  // running minimum fn/fd
+    for (int32_t e = e0 + lane; e < e1; e += LANES) {
         const D2 ri = xy[idx[e]];
         const double dx = ri.x - r0.x, dy = ri.y - r0.y;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const double d2 = -0.5 * (dx * g_x[v] + dy * g_y[v]);
+            const double d2 = -0.5 * (dx * gx[v] + dy * gy[v]);
             if (d2 == 0.0) continue;
             const double d1 = d2 > 0.0 ? dmax[v] : dmin[v];
-            const double f = (d1 * d1 + eps2 + 2.0 * d1 * d2) /
-                             (d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2);
-            phi[v] = fmin(phi[v], f);
+            const double nu = d1 * d1 + eps2 + 2.0 * d1 * d2;
+            const double de = d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2;
+            if (nu * fd[v] < fn[v] * de) {
+                fn[v] = nu;
+                fd[v] = de;
+            }
         }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) phi[v] = fmax(phi[v], 0.0);
-    qxl[p] = {phi[0] * gx.x, phi[1] * gx.y, phi[2] * gx.z, phi[3] * gx.w};
-    qyl[p] = {phi[0] * gy.x, phi[1] * gy.y, phi[2] * gy.z, phi[3] * gy.w};
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int o = LANES / 2; o > 0; o >>= 1) {
+            const double on = __shfl_xor(fn[v], o, 64), od = __shfl_xor(fd[v], o, 64);
+            if (on * fd[v] < fn[v] * od) {
+                fn[v] = on;
+                fd[v] = od;
+            }
+        }
+    if (lane == 0) {
+        double phi[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) phi[v] = fmax(fn[v] / fd[v], 0.0);
+        qxl[p] = {phi[0] * gx[0], phi[1] * gx[1], phi[2] * gx[2], phi[3] * gx[3]};
+        qyl[p] = {phi[0] * gy[0], phi[1] * gy[1], phi[2] * gy[2], phi[3] * gy[3]};
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -508,41 +536,57 @@ __global__ void __launch_bounds__(kBlock) k_residual(
     }
 }
 
-// Residual norm of each component (one block per component, fixed reduction
-// order): res = sqrt(sum of R_rho^2 over its non-outer points) / their count.
-// A component whose norm is not finite is retired as failed; one that
-// reaches tol_abs (> 0) is retired as converged.
-__global__ void __launch_bounds__(kBlock) k_norm_comp(const double* __restrict__ rr,
-                                                      const int32_t* __restrict__ comp_off,
-                                                      const double* __restrict__ inv_active,
-                                                      const double* __restrict__ tol_abs,
-                                                      int32_t* __restrict__ active,
-                                                      int32_t* __restrict__ status,
-                                                      int32_t* __restrict__ iters,
-                                                      double* __restrict__ res_last,
-                                                      double* __restrict__ out) {
+// Residual norm of each component in two deterministic stages: one block
+// per reduction chunk sums R_rho^2 over the chunk's points, then one thread
+// wavefront per component adds its chunks: res = sqrt(sum) / (non-outer count).
+// A component whose norm is not finite is retired as failed; one that reaches
+// tol_abs (> 0) is retired as converged.
+__global__ void __launch_bounds__(kBlock) k_norm_partial(const double* __restrict__ rr,
+                                                         const int32_t* __restrict__ chunk_start,
+                                                         const int32_t* __restrict__ chunk_comp,
+                                                         const int32_t* __restrict__ active,
+                                                         double* __restrict__ partial) {
     __shared__ double red[kBlock / 64];
-    const int k = blockIdx.x;
-    if (!active[k]) return;  // uniform over the block
+    const int c = blockIdx.x;
+    if (!active[chunk_comp[c]]) return;  // uniform over the block
     double s = 0.0;
-    for (int64_t p = comp_off[k] + threadIdx.x; p < comp_off[k + 1]; p += blockDim.x) s += rr[p];
+    for (int64_t p = chunk_start[c] + threadIdx.x; p < chunk_start[c + 1]; p += blockDim.x)
+        s += rr[p];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) t += red[w];
-        const double res = sqrt(t) * inv_active[k];
-        out[k] = res;
-        res_last[k] = res;
-        iters[k] += 1;
-        if (!(res <= 1e300)) {
-            status[k] = -1;
-            active[k] = 0;
-        } else if (tol_abs[k] > 0.0 && res <= tol_abs[k]) {
-            status[k] = 1;
-            active[k] = 0;
-        }
+        partial[c] = t;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_norm_comp(const double* __restrict__ partial,
+                                                  const int32_t* __restrict__ comp_chunk_off,
+                                                  const double* __restrict__ inv_active,
+                                                  const double* __restrict__ tol_abs,
+                                                  int32_t* __restrict__ active,
+                                                  int32_t* __restrict__ status,
+                                                  int32_t* __restrict__ iters,
+                                                  double* __restrict__ res_last,
+                                                  double* __restrict__ out) {
+    const int k = blockIdx.x;  // one wavefront per component
+    if (!active[k]) return;
+    double t = 0.0;
+    for (int c = comp_chunk_off[k] + threadIdx.x; c < comp_chunk_off[k + 1]; c += 64) t += partial[c];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if (threadIdx.x != 0) return;
+    const double res = sqrt(t) * inv_active[k];
+    out[k] = res;
+    res_last[k] = res;
+    iters[k] += 1;
+    if (!(res <= 1e300)) {
+        status[k] = -1;
+        active[k] = 0;
+    } else if (tol_abs[k] > 0.0 && res <= tol_abs[k]) {
+        status[k] = 1;
+        active[k] = 0;
     }
 }
 
@@ -916,22 +960,44 @@ hipError_t launch_q_from_U(State& s) {
     return hipGetLastError();
 }
 
-hipError_t launch_q_derivatives(State& s) {
+template <int LANES>
+static void qgrad_lanes(State& s) {
     const Cloud& c = *s.cloud;
-    const dim3 g(grid_for(c.n)), b(kBlock);
-    hipLaunchKernelGGL(k_qgrad<false>, g, b, 0, s.stream, c.n, c.xy, c.off, c.idx, c.geom, c.comp,
-                       s.active, s.q, nullptr, nullptr, s.qx[0], s.qy[0]);
+    const dim3 g(grid_for(c.n * LANES)), b(kBlock);
+    const double K = s.prm.limiter_k;
+    const int m = s.prm.inner_iters;
+    const bool lim = s.prm.limiter != 0;
+    // pass 0 (first order), then m inner passes; the limiter rides on the last
+    if (m == 0 && lim)
+        hipLaunchKernelGGL((k_qgrad<false, true, LANES>), g, b, 0, s.stream, c.n, K, c.xy, c.off,
+                           c.idx, c.geom, c.comp, s.active, s.q, nullptr, nullptr, s.qx[0],
+                           s.qy[0], s.qxl, s.qyl);
+    else
+        hipLaunchKernelGGL((k_qgrad<false, false, LANES>), g, b, 0, s.stream, c.n, K, c.xy, c.off,
+                           c.idx, c.geom, c.comp, s.active, s.q, nullptr, nullptr, s.qx[0],
+                           s.qy[0], nullptr, nullptr);
     int cur = 0;
-    for (int it = 0; it < s.prm.inner_iters; ++it) {
-        hipLaunchKernelGGL(k_qgrad<true>, g, b, 0, s.stream, c.n, c.xy, c.off, c.idx, c.geom,
-                           c.comp, s.active, s.q, s.qx[cur], s.qy[cur], s.qx[1 - cur],
-                           s.qy[1 - cur]);
+    for (int it = 0; it < m; ++it) {
+        if (it == m - 1 && lim)
+            hipLaunchKernelGGL((k_qgrad<true, true, LANES>), g, b, 0, s.stream, c.n, K, c.xy,
+                               c.off, c.idx, c.geom, c.comp, s.active, s.q, s.qx[cur], s.qy[cur],
+                               s.qx[1 - cur], s.qy[1 - cur], s.qxl, s.qyl);
+        else
+            hipLaunchKernelGGL((k_qgrad<true, false, LANES>), g, b, 0, s.stream, c.n, K, c.xy,
+                               c.off, c.idx, c.geom, c.comp, s.active, s.q, s.qx[cur], s.qy[cur],
+                               s.qx[1 - cur], s.qy[1 - cur], nullptr, nullptr);
         cur = 1 - cur;
     }
     s.qsel = cur;
-    if (s.prm.limiter)
-        hipLaunchKernelGGL(k_limiter, g, b, 0, s.stream, c.n, s.prm.limiter_k, c.xy, c.off, c.idx,
-                           c.geom, c.comp, s.active, s.q, s.qx[cur], s.qy[cur], s.qxl, s.qyl);
+}
+
+hipError_t launch_q_derivatives(State& s) {
+    switch (s.qgrad_lanes) {
+        case 1: qgrad_lanes<1>(s); break;
+        case 2: qgrad_lanes<2>(s); break;
+        case 8: qgrad_lanes<8>(s); break;
+        default: qgrad_lanes<4>(s); break;
+    }
     return hipGetLastError();
 }
 
@@ -967,9 +1033,11 @@ hipError_t launch_residual(State& s, int slot) {
 
 hipError_t launch_norm(State& s, int slot) {
     const Cloud& c = *s.cloud;
-    hipLaunchKernelGGL(k_norm_comp, dim3(c.ncomp), dim3(kBlock), 0, s.stream, s.rr, c.comp_off,
-                       c.comp_inv_active, s.tol_abs, s.active, s.status, s.iters, s.res_last,
-                       s.res_hist + (size_t)slot * c.ncomp);
+    hipLaunchKernelGGL(k_norm_partial, dim3(c.nchunk), dim3(kBlock), 0, s.stream, s.rr,
+                       c.chunk_start, c.chunk_comp, s.active, s.partial);
+    hipLaunchKernelGGL(k_norm_comp, dim3(c.ncomp), dim3(64), 0, s.stream, s.partial,
+                       c.comp_chunk_off, c.comp_inv_active, s.tol_abs, s.active, s.status, s.iters,
+                       s.res_last, s.res_hist + (size_t)slot * c.ncomp);
     return hipGetLastError();
 }
 

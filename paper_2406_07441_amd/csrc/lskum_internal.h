@@ -71,6 +71,12 @@ struct Cloud {
     std::vector<double> h_comp_inv_active;
     double* comp_inv_active = nullptr;  // device, 1 / non-outer points per component
     double* comp_orient = nullptr;      // device, wall polygon orientation per component
+    // reduction chunks: chunk c covers points [chunk_start[c], chunk_start[c+1]) of
+    // component chunk_comp[c]; component k owns chunks [comp_chunk_off[k], ...+1)
+    int32_t nchunk = 0;
+    int32_t* chunk_start = nullptr;     // device, nchunk + 1
+    int32_t* chunk_comp = nullptr;      // device, nchunk
+    int32_t* comp_chunk_off = nullptr;  // device, ncomp + 1
     // host copies kept for building batch clouds
     std::vector<double> h_x, h_y, h_tx, h_ty;
     std::vector<int8_t> h_type;
@@ -113,6 +119,7 @@ struct State {
     bool own_stream = false;
     int sweep_lanes = 4;         // lanes per point in the sweep kernels (1, 2, 4 or 8)
     int residual_lanes = 4;      // lanes per point in the residual kernel (1, 2, 4 or 8)
+    int qgrad_lanes = 4;         // lanes per point in the q-derivative kernels
     double res_fs = 0.0;
     // fp64
     D4* U = nullptr;
@@ -135,6 +142,7 @@ struct State {
     float* Df = nullptr;
     // reductions
     double* fsum = nullptr;      // 2 doubles per component: pressure force
+    double* partial = nullptr;   // one partial sum of R_rho^2 per reduction chunk
     double* res_hist = nullptr;  // residual norms, [slot][component]
     int res_cap = 0;             // slots
     int32_t* flags = nullptr;    // [0] non-physical
@@ -166,4 +174,22 @@ hipError_t launch_aos_to_soa(const D4* aos, double* soa, int64_t n, hipStream_t 
 hipError_t launch_aosf_to_soa(const F4* aos, double* soa, int64_t n, hipStream_t st);
 hipError_t launch_clear_flags(int32_t* flags, hipStream_t st);
 
+// Error reporting shared by the C-ABI source files: records msg for
+// lskum_last_error() and returns code.
+int api_error(int code, const std::string& msg);
+void api_clear_error();
+
 }  // namespace lskum
+
+// Opaque handles of the C ABI.
+struct lskum_cloud {
+    lskum::Cloud c;
+};
+struct lskum_state {
+    lskum::State s;
+};
+struct lskum_batch {
+    lskum::Cloud c;  // union of the conditions' clouds
+    lskum::State s;
+    std::vector<int32_t> cond_cloud;
+};

@@ -1,0 +1,472 @@
+// Per-point warm-start MLP on gfx950: 5 -> 128 -> 128 -> 128 -> 4, GELU (erf
+// form) on the hidden layers, bfloat16 weights/activations with fp32
+// accumulation, Adam on fp32 master weights.
+//
+// The two 128 x 128 layers and their backward products are dense
+// contractions and run on the matrix cores (v_mfma_f32_16x16x32_bf16): one
+// wavefront computes one 16 x 16 output tile, K is walked 32 at a time.
+// Operand registers: lane l holds row (A) or column (B) l % 16 and the eight
+// consecutive K entries 8 (l / 16) .. 8 (l / 16) + 7; the accumulator lane l
+// holds column l % 16 of rows 4 (l / 16) .. 4 (l / 16) + 3.  The thin 5 -> 128
+// and 128 -> 4 layers run on the vector ALUs.
+//
+// Quantisation points (shared with the float64 reference of the tests):
+// bf16 copies of W1..W4, of the input features and of each hidden activation;
+// the backward pass rounds the pre-activation gradients of layers 3 and 2 to
+// bf16 before their products; everything else is fp32.
+#include "lskum_mlp.h"
+
+#include <cmath>
+
+namespace lskum {
+namespace mlp {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr float kInvSqrt2 = 0.70710678118654752f;
+constexpr float kInvSqrt2Pi = 0.39894228040143268f;
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * kInvSqrt2)); }
+__device__ __forceinline__ float gelu_prime(float z) {
+    return 0.5f * (1.0f + erff(z * kInvSqrt2)) + z * expf(-0.5f * z * z) * kInvSqrt2Pi;
+}
+
+// One 16 x 16 tile of C = A B over K range [k0, k1) (k1 - k0 a multiple of 32).
+// a(r, k) = A[r * a_rs + k * a_ks], b(k, c) = B[k * b_ks + c * b_cs].
+__device__ __forceinline__ f32x4 tile_mma(const __bf16* __restrict__ A, int64_t a_rs,
+                                          int64_t a_ks, const __bf16* __restrict__ B,
+                                          int64_t b_ks, int64_t b_cs, int r0, int c0, int k0,
+                                          int k1) {
+    const int l = threadIdx.x & 63;
+    const int rr = r0 + (l & 15), cc = c0 + (l & 15), kq = 8 * (l >> 4);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k = k0; k < k1; k += 32) {
+        bf16x8 a, b;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            a[t] = A[rr * a_rs + (int64_t)(k + kq + t) * a_ks];
+            b[t] = B[(int64_t)(k + kq + t) * b_ks + cc * b_cs];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Forward dense layer: Z = H W^T + b (H [M][128] bf16, W [128][128] bf16
+// [out][in]); writes Z (fp32) and bf16(GELU(Z)).  Grid: (M/16 * 8) waves.
+__global__ void __launch_bounds__(64) k_dense_fwd(int M, const __bf16* __restrict__ H,
+                                                  const __bf16* __restrict__ W,
+                                                  const float* __restrict__ bias,
+                                                  float* __restrict__ Z, __bf16* __restrict__ Hn) {
+    const int tile = blockIdx.x;
+    const int r0 = 16 * (tile >> 3), c0 = 16 * (tile & 7);
+    if (r0 >= M) return;
+    const f32x4 acc = tile_mma(H, kWidth, 1, W, 1, kWidth, r0, c0, 0, kWidth);
+    const int l = threadIdx.x;
+    const int c = c0 + (l & 15);
+    const float bc = bias[c];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int r = r0 + 4 * (l >> 4) + t;
+        const float z = acc[t] + bc;
+        Z[(int64_t)r * kWidth + c] = z;
+        Hn[(int64_t)r * kWidth + c] = (__bf16)gelu(z);
+    }
+}
+
+// Backward through a dense layer: dH = dZn W (dZn [M][128] bf16, W [out][in]),
+// then dZ = dH * GELU'(Zprev); stored as bf16 (ROUND) or fp32.
+template <bool ROUND>
+__global__ void __launch_bounds__(64) k_dense_bwd_data(int M, const __bf16* __restrict__ dZn,
+                                                       const __bf16* __restrict__ W,
+                                                       const float* __restrict__ Zprev,
+                                                       __bf16* __restrict__ dZb,
+                                                       float* __restrict__ dZf) {
+    const int tile = blockIdx.x;
+    const int r0 = 16 * (tile >> 3), c0 = 16 * (tile & 7);
+    if (r0 >= M) return;
+    // C[m][i] = sum_o dZn[m][o] W[o][i]: A row stride 128, B k stride 128
+    const f32x4 acc = tile_mma(dZn, kWidth, 1, W, kWidth, 1, r0, c0, 0, kWidth);
+    const int l = threadIdx.x;
+    const int c = c0 + (l & 15);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t o = (int64_t)(r0 + 4 * (l >> 4) + t) * kWidth + c;
+        const float v = acc[t] * gelu_prime(Zprev[o]);
+        if (ROUND) dZb[o] = (__bf16)v;
+        else dZf[o] = v;
+    }
+}
+
+// Weight gradient partials: P[chunk][o][i] = sum_{m in chunk} dZ[m][o] H[m][i]
+// (both [M][128] bf16).  Grid: (64 tiles, nchunks).
+__global__ void __launch_bounds__(64) k_dense_wgrad(int M, int mchunk, const __bf16* __restrict__ dZ,
+                                                    const __bf16* __restrict__ H,
+                                                    float* __restrict__ P) {
+    const int tile = blockIdx.x, ch = blockIdx.y;
+    const int r0 = 16 * (tile >> 3), c0 = 16 * (tile & 7);
+    const int k0 = ch * mchunk, k1 = min(M, k0 + mchunk);
+    if (k0 >= k1) return;
+    // C[o][i] = sum_m A[o][m] B[m][i]: A = dZ^T (row stride 1, k stride 128)
+    const f32x4 acc = tile_mma(dZ, 1, kWidth, H, kWidth, 1, r0, c0, k0, k1);
+    const int l = threadIdx.x;
+    const int c = c0 + (l & 15);
+    float* out = P + (int64_t)ch * kWidth * kWidth;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) out[(r0 + 4 * (l >> 4) + t) * kWidth + c] = acc[t];
+}
+
+// Layer 1 (5 -> 128) on the vector units: Z1 = bf16(X) W1^T + b1.
+__global__ void __launch_bounds__(256) k_layer_in(int M, int Mvalid, const float* __restrict__ X,
+                                                  const __bf16* __restrict__ W1,
+                                                  const float* __restrict__ b1,
+                                                  __bf16* __restrict__ Xb, float* __restrict__ Z,
+                                                  __bf16* __restrict__ H) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)M * kWidth) return;
+    const int m = (int)(g / kWidth), n = (int)(g % kWidth);
+    float z = b1[n];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) {
+        const __bf16 xb = (__bf16)(m < Mvalid ? X[(int64_t)m * kIn + k] : 0.0f);
+        if (n == 0) Xb[(int64_t)m * kIn + k] = xb;
+        z += (float)xb * (float)W1[n * kIn + k];
+    }
+    Z[g] = z;
+    H[g] = (__bf16)gelu(z);
+}
+
+// Layer 4 (128 -> 4): Y = H3 W4^T + b4; with targets, dY = 2 (Y - T) / (4 Mvalid)
+// (0 on padding rows) and per-row squared errors for the loss.
+__global__ void __launch_bounds__(256) k_layer_out(int M, int Mvalid, const __bf16* __restrict__ H,
+                                                   const __bf16* __restrict__ W4,
+                                                   const float* __restrict__ b4,
+                                                   const float* __restrict__ T,
+                                                   float* __restrict__ Y, float* __restrict__ dY,
+                                                   float* __restrict__ se) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)M * kOut) return;
+    const int m = (int)(g / kOut), o = (int)(g % kOut);
+    float y = b4[o];
+    for (int k = 0; k < kWidth; ++k) y += (float)H[(int64_t)m * kWidth + k] * (float)W4[o * kWidth + k];
+    if (Y && m < Mvalid) Y[(int64_t)m * kOut + o] = y;
+    if (T) {
+        const float r = m < Mvalid ? y - T[(int64_t)m * kOut + o] : 0.0f;
+        dY[g] = 2.0f * r / (4.0f * (float)Mvalid);
+        se[g] = r * r;
+    }
+}
+
+// Layer 4 backward: dZ3 = bf16((dY W4) * GELU'(Z3)).
+__global__ void __launch_bounds__(256) k_layer_out_bwd(int M, const float* __restrict__ dY,
+                                                       const __bf16* __restrict__ W4,
+                                                       const float* __restrict__ Z3,
+                                                       __bf16* __restrict__ dZ3) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)M * kWidth) return;
+    const int m = (int)(g / kWidth), k = (int)(g % kWidth);
+    float s = 0.0f;
+#pragma unroll
+    for (int o = 0; o < kOut; ++o) s += dY[(int64_t)m * kOut + o] * (float)W4[o * kWidth + k];
+    dZ3[g] = (__bf16)(s * gelu_prime(Z3[g]));
+}
+
+// Sums of small products over the points, one thread per output, points in
+// fixed order: out[r][c] = sum_m P[m][r] Q[m][c] (Q == nullptr: sum_m P[m][r]).
+// P is fp32 or bf16 (template), Q bf16 or fp32 (template).
+template <class TP, class TQ>
+__global__ void __launch_bounds__(256) k_colsum(int M, int R, int Cn, const TP* __restrict__ P,
+                                               int ldp, const TQ* __restrict__ Q, int ldq,
+                                               float* __restrict__ out) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= R * Cn) return;
+    const int r = g / Cn, c = g % Cn;
+    float s = 0.0f;
+    for (int m = 0; m < M; ++m) {
+        const float pv = (float)P[(int64_t)m * ldp + r];
+        s += Q ? pv * (float)Q[(int64_t)m * ldq + c] : pv;
+    }
+    out[g] = s;
+}
+
+// out[k] = sum_ch P[ch][k] (fixed order).
+__global__ void __launch_bounds__(256) k_sum_chunks(int n, int nch, const float* __restrict__ P,
+                                                    float* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    float s = 0.0f;
+    for (int c = 0; c < nch; ++c) s += P[(int64_t)c * n + k];
+    out[k] = s;
+}
+
+__global__ void __launch_bounds__(256) k_sum_all(int n, const float* __restrict__ v,
+                                                 double* __restrict__ out) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) s += v[k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = red[0] + red[1] + red[2] + red[3];
+}
+
+// bf16 copies of the weights (and the transposes are not needed: the MFMA
+// operands address W through strides).
+__global__ void __launch_bounds__(256) k_refresh(const float* __restrict__ theta,
+                                                 __bf16* __restrict__ W1, __bf16* __restrict__ W2,
+                                                 __bf16* __restrict__ W3, __bf16* __restrict__ W4) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < kWidth * kIn) W1[k] = (__bf16)theta[kOffW1 + k];
+    if (k < kWidth * kWidth) {
+        W2[k] = (__bf16)theta[kOffW2 + k];
+        W3[k] = (__bf16)theta[kOffW3 + k];
+    }
+    if (k < kOut * kWidth) W4[k] = (__bf16)theta[kOffW4 + k];
+}
+
+// Adam (fp32): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+// theta -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+__global__ void __launch_bounds__(256) k_adam(int n, float lr, float b1, float b2, float eps,
+                                              float c1, float c2, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              float* __restrict__ theta) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.0f - b1) * gk;
+    const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    theta[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+// Minibatch gather: row r takes dataset row floor(h * n / 2^64), h the
+// splitmix64 hash of seed + step * B + r.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(256) k_gather(int64_t n, int B, uint64_t seed, int64_t step,
+                                                const float* __restrict__ X,
+                                                const float* __restrict__ T,
+                                                float* __restrict__ Xo, float* __restrict__ To) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= B) return;
+    const uint64_t h = splitmix64(seed + (uint64_t)step * (uint64_t)B + (uint64_t)r);
+    const int64_t i = (int64_t)__umul64hi(h, (uint64_t)n);
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) Xo[(int64_t)r * kIn + k] = X[i * kIn + k];
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) To[(int64_t)r * kOut + k] = T[i * kOut + k];
+}
+
+// Features of a point: position squashed into the unit disc about mid-chord,
+// distance to the nearest wall point of its own cloud, Mach number and angle
+// of attack recovered from the free-stream velocity.
+__global__ void __launch_bounds__(256) k_features(int64_t p0, int64_t m, const D2* __restrict__ xy,
+                                                  const int32_t* __restrict__ comp,
+                                                  const int32_t* __restrict__ wall_list,
+                                                  const int32_t* __restrict__ wall_off,
+                                                  const double* __restrict__ vinf,
+                                                  const D4* __restrict__ U, double gamma,
+                                                  float* __restrict__ X, float* __restrict__ T) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const int64_t p = p0 + r;
+    const int k = comp ? comp[p] : 0;
+    const D2 c = xy[p];
+    double d2 = 1e300;
+    for (int w = wall_off[k]; w < wall_off[k + 1]; ++w) {
+        const D2 q = xy[wall_list[w]];
+        const double dx = c.x - q.x, dy = c.y - q.y;
+        d2 = fmin(d2, dx * dx + dy * dy);
+    }
+    const double d = wall_off[k + 1] > wall_off[k] ? sqrt(d2) : 1e3;
+    const double ex = c.x - 0.5, rc = sqrt(ex * ex + c.y * c.y);
+    const double u1 = vinf[2 * k], u2 = vinf[2 * k + 1];
+    const double mach = sqrt(u1 * u1 + u2 * u2);
+    const double aoa = atan2(u2, u1) * (180.0 / 3.14159265358979323846);
+    float* x = X + r * kIn;
+    x[0] = (float)(ex / (1.0 + rc));
+    x[1] = (float)(c.y / (1.0 + rc));
+    x[2] = (float)(2.0 * d / (d + 0.1) - 1.0);
+    x[3] = (float)((mach - 0.6) / 0.25);
+    x[4] = (float)((aoa - 2.0) / 6.0);
+    if (T) {
+        const D4 u = U[p];
+        const double irho = 1.0 / u.x, v1 = u.y * irho, v2 = u.z * irho;
+        const double pr = (gamma - 1.0) * (u.w - 0.5 * u.x * (v1 * v1 + v2 * v2));
+        float* t = T + r * kOut;
+        t[0] = (float)(u.x - 1.0);
+        t[1] = (float)(v1 - u1);
+        t[2] = (float)(v2 - u2);
+        t[3] = (float)(gamma * pr - 1.0);
+    }
+}
+
+// U of points [p0, p0 + m) from predicted deviations from the free stream
+// (rho - 1, u - u_inf, v - v_inf, gamma p - 1).  Outer points stay at the free
+// stream and wall points keep only the tangential velocity.  With FALLBACK,
+// only points of components flagged in bad are written, at the free stream.
+template <bool FALLBACK>
+__global__ void __launch_bounds__(256) k_pred_to_U(int64_t p0, int64_t m, const float* __restrict__ Y,
+                                                   const int8_t* __restrict__ type,
+                                                   const D2* __restrict__ frame,
+                                                   const int32_t* __restrict__ comp,
+                                                   const double* __restrict__ vinf, double gamma,
+                                                   int32_t* __restrict__ bad, D4* __restrict__ U) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const int64_t p = p0 + r;
+    const int k = comp ? comp[p] : 0;
+    if (FALLBACK && !bad[k]) return;
+    double rho = 1.0, u1 = vinf[2 * k], u2 = vinf[2 * k + 1], gp = 1.0;
+    if (!FALLBACK && type[p] != 2) {
+        const float* y = Y + r * kOut;
+        rho += (double)y[0];
+        u1 += (double)y[1];
+        u2 += (double)y[2];
+        gp += (double)y[3];
+        // unusable prediction: the judge sends the whole component back to the free stream
+        if (!(rho > 0.05) || !(gp > 0.05) || !(fabs(u1) + fabs(u2) < 1e3)) {
+            bad[k] = 1;
+            rho = 1.0;
+            u1 = vinf[2 * k];
+            u2 = vinf[2 * k + 1];
+            gp = 1.0;
+        }
+    }
+    if (type[p] == 0) {
+        const D2 t = frame[p];
+        const double ut = u1 * t.x + u2 * t.y;
+        u1 = ut * t.x;
+        u2 = ut * t.y;
+    }
+    const double pr = gp / gamma;
+    U[p] = {rho, rho * u1, rho * u2, pr / (gamma - 1.0) + 0.5 * rho * (u1 * u1 + u2 * u2)};
+}
+
+__global__ void k_judge(int ncomp, const double* __restrict__ res, const double* __restrict__ res_fs,
+                        int32_t* __restrict__ bad) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ncomp) return;
+    if (!(res[k] < res_fs[k])) bad[k] = 1;
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t refresh_weights(Net& net) {
+    hipLaunchKernelGGL(k_refresh, dim3(nblk(kWidth * kWidth, 256)), dim3(256), 0, net.stream,
+                       net.theta, net.W1b, net.W2b, net.W3b, net.W4b);
+    return hipGetLastError();
+}
+
+// Forward over rows [0, M) of the workspace (M a multiple of 16, Mvalid <= M).
+hipError_t forward(Net& net, const float* X, int M, int Mvalid, const float* T, float* Y) {
+    hipStream_t st = net.stream;
+    const float* th = net.theta;
+    hipLaunchKernelGGL(k_layer_in, dim3(nblk((int64_t)M * kWidth, 256)), dim3(256), 0, st, M,
+                       Mvalid, X, net.W1b, th + kOffB1, net.Xb, net.Z1, net.H1);
+    hipLaunchKernelGGL(k_dense_fwd, dim3((M / 16) * 8), dim3(64), 0, st, M, net.H1, net.W2b,
+                       th + kOffB2, net.Z2, net.H2);
+    hipLaunchKernelGGL(k_dense_fwd, dim3((M / 16) * 8), dim3(64), 0, st, M, net.H2, net.W3b,
+                       th + kOffB3, net.Z3, net.H3);
+    hipLaunchKernelGGL(k_layer_out, dim3(nblk((int64_t)M * kOut, 256)), dim3(256), 0, st, M,
+                       Mvalid, net.H3, net.W4b, th + kOffB4, T, Y, net.dY, net.se);
+    return hipGetLastError();
+}
+
+// Backward after a forward with targets: gradient (flat, fp32) into net.grad.
+hipError_t backward(Net& net, int M) {
+    hipStream_t st = net.stream;
+    float* g = net.grad;
+    // layer 4
+    hipLaunchKernelGGL((k_colsum<float, __bf16>), dim3(nblk(kOut * kWidth, 256)), dim3(256), 0, st,
+                       M, kOut, kWidth, net.dY, kOut, net.H3, kWidth, g + kOffW4);
+    hipLaunchKernelGGL((k_colsum<float, float>), dim3(1), dim3(256), 0, st, M, kOut, 1, net.dY,
+                       kOut, (const float*)nullptr, 0, g + kOffB4);
+    hipLaunchKernelGGL(k_layer_out_bwd, dim3(nblk((int64_t)M * kWidth, 256)), dim3(256), 0, st, M,
+                       net.dY, net.W4b, net.Z3, net.dZ3);
+    // layer 3
+    const int nch = (M + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL(k_dense_wgrad, dim3(64, nch), dim3(64), 0, st, M, kChunk, net.dZ3, net.H2,
+                       net.part);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(kWidth * kWidth, 256)), dim3(256), 0, st,
+                       kWidth * kWidth, nch, net.part, g + kOffW3);
+    hipLaunchKernelGGL((k_colsum<__bf16, float>), dim3(1), dim3(256), 0, st, M, kWidth, 1,
+                       net.dZ3, kWidth, (const float*)nullptr, 0, g + kOffB3);
+    hipLaunchKernelGGL(k_dense_bwd_data<true>, dim3((M / 16) * 8), dim3(64), 0, st, M, net.dZ3,
+                       net.W3b, net.Z2, net.dZ2, (float*)nullptr);
+    // layer 2
+    hipLaunchKernelGGL(k_dense_wgrad, dim3(64, nch), dim3(64), 0, st, M, kChunk, net.dZ2, net.H1,
+                       net.part);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(kWidth * kWidth, 256)), dim3(256), 0, st,
+                       kWidth * kWidth, nch, net.part, g + kOffW2);
+    hipLaunchKernelGGL((k_colsum<__bf16, float>), dim3(1), dim3(256), 0, st, M, kWidth, 1,
+                       net.dZ2, kWidth, (const float*)nullptr, 0, g + kOffB2);
+    hipLaunchKernelGGL(k_dense_bwd_data<false>, dim3((M / 16) * 8), dim3(64), 0, st, M, net.dZ2,
+                       net.W2b, net.Z1, (__bf16*)nullptr, net.dZ1);
+    // layer 1
+    hipLaunchKernelGGL((k_colsum<float, __bf16>), dim3(nblk(kWidth * kIn, 256)), dim3(256), 0, st,
+                       M, kWidth, kIn, net.dZ1, kWidth, net.Xb, kIn, g + kOffW1);
+    hipLaunchKernelGGL((k_colsum<float, float>), dim3(1), dim3(256), 0, st, M, kWidth, 1, net.dZ1,
+                       kWidth, (const float*)nullptr, 0, g + kOffB1);
+    return hipGetLastError();
+}
+
+hipError_t loss(Net& net, int M, double* d_out) {
+    hipLaunchKernelGGL(k_sum_all, dim3(1), dim3(256), 0, net.stream, M * kOut, net.se, d_out);
+    return hipGetLastError();
+}
+
+hipError_t adam_step(Net& net, float lr) {
+    net.step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - std::pow(b1, (float)net.step);
+    const float c2 = 1.0f - std::pow(b2, (float)net.step);
+    hipLaunchKernelGGL(k_adam, dim3(nblk(kParams, 256)), dim3(256), 0, net.stream, kParams, lr, b1,
+                       b2, 1e-8f, c1, c2, net.grad, net.m, net.v, net.theta);
+    return refresh_weights(net);
+}
+
+hipError_t gather(Net& net, int64_t n, const float* X, const float* T, int B, uint64_t seed,
+                  int64_t step) {
+    hipLaunchKernelGGL(k_gather, dim3(nblk(B, 256)), dim3(256), 0, net.stream, n, B, seed, step, X,
+                       T, net.Xin, net.Tin);
+    return hipGetLastError();
+}
+
+hipError_t features(const State& s, int64_t p0, int64_t m, float* Xout, float* Tout) {
+    const Cloud& c = *s.cloud;
+    hipLaunchKernelGGL(k_features, dim3(nblk(m, 256)), dim3(256), 0, s.stream, p0, m, c.xy, c.comp,
+                       c.wall_list, c.wall_off, s.vinf, s.U, s.prm.gamma, Xout, Tout);
+    return hipGetLastError();
+}
+
+hipError_t pred_to_U(Net& net, const State& s, int64_t p0, int64_t m, const float* Y) {
+    const Cloud& c = *s.cloud;
+    hipLaunchKernelGGL(k_pred_to_U<false>, dim3(nblk(m, 256)), dim3(256), 0, s.stream, p0, m, Y,
+                       c.type, c.frame, c.comp, s.vinf, s.prm.gamma, net.d_bad, s.U);
+    return hipGetLastError();
+}
+
+hipError_t judge_and_fallback(Net& net, const State& s, const double* res) {
+    const Cloud& c = *s.cloud;
+    hipLaunchKernelGGL(k_judge, dim3(nblk(c.ncomp, 256)), dim3(256), 0, s.stream, c.ncomp, res,
+                       net.d_res_fs, net.d_bad);
+    hipLaunchKernelGGL(k_pred_to_U<true>, dim3(nblk(c.n, 256)), dim3(256), 0, s.stream, (int64_t)0,
+                       c.n, (const float*)nullptr, c.type, c.frame, c.comp, s.vinf, s.prm.gamma,
+                       net.d_bad, s.U);
+    return hipGetLastError();
+}
+
+}  // namespace mlp
+}  // namespace lskum

@@ -79,6 +79,22 @@ _SIGS = {
     "lskum_batch_set_U": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int]),
     "lskum_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "lskum_batch_destroy": (None, [C.c_void_p]),
+    "lskum_mlp_create": (C.c_int, [C.c_uint64, C.c_int64, C.c_void_p, C.c_void_p]),
+    "lskum_mlp_destroy": (None, [C.c_void_p]),
+    "lskum_mlp_get_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "lskum_mlp_set_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int]),
+    "lskum_mlp_forward": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "lskum_mlp_gradient": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]),
+    "lskum_mlp_train_step": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_float,
+                                       C.c_void_p]),
+    "lskum_mlp_train": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32,
+                                  C.c_int32, C.c_float, C.c_float, C.c_uint64, C.c_void_p,
+                                  C.c_void_p]),
+    "lskum_state_features": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lskum_batch_features": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lskum_mlp_warm_start": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lskum_mlp_warm_start_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lskum_last_error": (C.c_char_p, []),
 }
 
@@ -259,6 +275,10 @@ class State:
         _check(lib().lskum_forces(self.h, C.byref(cl), C.byref(cd)))
         return cl.value, cd.value
 
+    def features(self, targets: bool = False):
+        """Warm-start features [n][5] (and targets [n][4]) as device tensors."""
+        return _features(lib().lskum_state_features, self.h, self.n, targets)
+
 
 class Batch:
     """Many flow conditions iterated together (one launch per kernel/phase).
@@ -332,3 +352,118 @@ class Batch:
         _check(lib().lskum_batch_autotune(self.h, int(iters), C.byref(sl), C.byref(rl)))
         self.params.sweep_lanes, self.params.residual_lanes = sl.value, rl.value
         return sl.value, rl.value
+
+    def features(self, targets: bool = False):
+        """Features [n_points][5] (and targets [n_points][4]) of all conditions."""
+        return _features(lib().lskum_batch_features, self.h, self.n_points, targets)
+
+
+def _features(fn, h, n, targets):
+    import torch
+    X = torch.empty((n, MLP_FEATURES), dtype=torch.float32, device="cuda")
+    T = torch.empty((n, MLP_OUTPUTS), dtype=torch.float32, device="cuda") if targets else None
+    torch.cuda.current_stream().synchronize()
+    _check(fn(h, X.data_ptr(), None if T is None else T.data_ptr()))
+    return (X, T) if targets else X
+
+
+MLP_PARAMS, MLP_FEATURES, MLP_OUTPUTS = 34308, 5, 4
+
+
+def _f32_dev(t, cols):
+    import torch
+    assert t.is_cuda and t.dtype == torch.float32 and t.dim() == 2 and t.shape[1] == cols
+    return t.contiguous()
+
+
+class MLP:
+    """Per-point warm-start network (BF16 weights/activations, FP32 accumulate).
+
+    Feature, target and prediction arrays are float32 torch tensors on the
+    device, [m][5] and [m][4]; parameters are exchanged as numpy float32.
+    """
+
+    def __init__(self, seed: int = 0, max_rows: int = 65536, stream=None):
+        handle = None
+        if stream is not None:
+            handle = stream if isinstance(stream, int) else stream.cuda_stream
+        h = C.c_void_p()
+        _check(lib().lskum_mlp_create(int(seed) & (2**64 - 1), int(max_rows), handle, C.byref(h)))
+        self.h = h
+        self.max_rows = int(max_rows)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lskum_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(MLP_PARAMS, np.float32)
+        _check(lib().lskum_mlp_get_params(self.h, _ptr(out), 0))
+        return out
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(theta, np.float32)
+        assert th.shape == (MLP_PARAMS,)
+        _check(lib().lskum_mlp_set_params(self.h, _ptr(th), 0))
+
+    def forward(self, X):
+        import torch
+        X = _f32_dev(X, MLP_FEATURES)
+        Y = torch.empty((X.shape[0], MLP_OUTPUTS), dtype=torch.float32, device=X.device)
+        torch.cuda.current_stream().synchronize()
+        _check(lib().lskum_mlp_forward(self.h, X.shape[0], X.data_ptr(), Y.data_ptr()))
+        return Y
+
+    def gradient(self, X, T):
+        """(loss, gradient as numpy float32) without changing the parameters."""
+        import torch
+        X, T = _f32_dev(X, MLP_FEATURES), _f32_dev(T, MLP_OUTPUTS)
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+        loss = C.c_double()
+        torch.cuda.current_stream().synchronize()
+        _check(lib().lskum_mlp_gradient(self.h, X.shape[0], X.data_ptr(), T.data_ptr(),
+                                        g.data_ptr(), C.byref(loss)))
+        return loss.value, g.cpu().numpy()
+
+    def train_step(self, X, T, lr: float) -> float:
+        import torch
+        X, T = _f32_dev(X, MLP_FEATURES), _f32_dev(T, MLP_OUTPUTS)
+        loss = C.c_double()
+        torch.cuda.current_stream().synchronize()
+        _check(lib().lskum_mlp_train_step(self.h, X.shape[0], X.data_ptr(), T.data_ptr(),
+                                          float(lr), C.byref(loss)))
+        return loss.value
+
+    def train(self, X, T, steps: int, batch: int, lr: float, lr_final: float = 0.0,
+              seed: int = 0):
+        """Minibatch Adam; returns (loss history, seconds)."""
+        import torch
+        X, T = _f32_dev(X, MLP_FEATURES), _f32_dev(T, MLP_OUTPUTS)
+        assert X.shape[0] == T.shape[0]
+        hist = np.zeros(max(int(steps), 1))
+        secs = C.c_double()
+        torch.cuda.current_stream().synchronize()
+        _check(lib().lskum_mlp_train(self.h, X.shape[0], X.data_ptr(), T.data_ptr(), int(steps),
+                                     int(batch), float(lr), float(lr_final),
+                                     int(seed) & (2**64 - 1), _ptr(hist), C.byref(secs)))
+        return hist[:int(steps)], secs.value
+
+    def warm_start(self, target):
+        """Warm-starts a State or Batch; returns (fallback flags, residual norms)."""
+        if isinstance(target, Batch):
+            k = target.n_cond
+            fn = lib().lskum_mlp_warm_start_batch
+        else:
+            k = 1
+            fn = lib().lskum_mlp_warm_start
+        fb = np.zeros(k, np.int32)
+        res = np.zeros(k)
+        _check(fn(self.h, target.h, _ptr(fb), _ptr(res)))
+        return fb, res

@@ -1,0 +1,253 @@
+"""Parity of the warm-start MLP kernels (through the C ABI) with the float64
+oracle that applies the same bfloat16 roundings, and the warm start itself.
+
+Bars.  The kernels accumulate exact bf16 x bf16 products in fp32 (128 terms:
+about 1e-6 relative) and evaluate erf/exp in fp32; the oracle does both in
+float64.  A hidden activation whose fp32 and fp64 values straddle a bf16
+rounding boundary rounds to neighbouring bf16 values on the two sides (one
+bf16 ulp, 2^-8 relative, for that activation): correct on both sides, rare,
+and bounded.  Hence: 99% of outputs within 1e-4 of the output scale and all
+within 2e-2; gradient blocks within 2e-3 relative (L2); one Adam step within
+lr/100 wherever |g| exceeds 1e-3 of its block's largest entry.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mlp as OM
+from paper_2406_07441_amd import cloudgen as cg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lk():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2406_07441_amd import lskum
+    lskum.lib()
+    return lskum
+
+
+def theta0(seed=1):
+    """Glorot-uniform weights and small biases (float32)."""
+    rng = np.random.default_rng(seed)
+    parts = {}
+    for name, shape in OM.SHAPES:
+        if len(shape) == 2:
+            a = math.sqrt(6.0 / (shape[0] + shape[1]))
+            parts[name] = rng.uniform(-a, a, shape)
+        else:
+            parts[name] = rng.uniform(-0.1, 0.1, shape)
+    return OM.pack(parts).astype(np.float32)
+
+
+def data(m, seed=2):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1, 1, (m, 5)).astype(np.float32)
+    T = (0.3 * np.sin(np.pi * X[:, :4]) * X[:, 4:5]).astype(np.float32)
+    return X, T
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def check_outputs(y, ref):
+    scale = float(np.abs(ref).max())
+    err = np.abs(y - ref) / scale
+    assert np.quantile(err, 0.99) <= 1e-4, np.quantile(err, 0.99)
+    assert err.max() <= 2e-2, err.max()
+
+
+def test_forward_parity_ragged(lk):
+    th = theta0()
+    X, _ = data(1000)
+    net = lk.MLP(seed=0, max_rows=4096)
+    net.set_params(th)
+    assert np.array_equal(net.get_params(), th)
+    Y = net.forward(dev(X)).cpu().numpy()
+    ref, _ = OM.forward(th.astype(np.float64), X.astype(np.float64))
+    check_outputs(Y, ref)
+    net.close()
+
+
+def test_forward_chunking_is_exact(lk):
+    th = theta0(4)
+    X, _ = data(1000, seed=5)
+    a = lk.MLP(max_rows=256)   # four chunks
+    b = lk.MLP(max_rows=8192)  # one chunk
+    a.set_params(th)
+    b.set_params(th)
+    ya = a.forward(dev(X)).cpu().numpy()
+    yb = b.forward(dev(X)).cpu().numpy()
+    assert np.array_equal(ya, yb)
+    assert a.forward(dev(X[:0])).shape == (0, 4)
+    a.close()
+    b.close()
+
+
+def test_gradient_parity(lk):
+    th = theta0(6)
+    X, T = data(777, seed=7)
+    net = lk.MLP(max_rows=1024)
+    net.set_params(th)
+    loss, g = net.gradient(dev(X), dev(T))
+    rl, rg = OM.loss_and_grad(th.astype(np.float64), X.astype(np.float64), T.astype(np.float64))
+    assert abs(loss - rl) <= 1e-4 * rl
+    o = 0
+    for name, shape in OM.SHAPES:
+        k = int(np.prod(shape))
+        a, b = g[o:o + k].astype(np.float64), rg[o:o + k]
+        assert np.linalg.norm(a - b) <= 2e-3 * np.linalg.norm(b), name
+        o += k
+    # the parameters are unchanged
+    assert np.array_equal(net.get_params(), th)
+    net.close()
+
+
+def test_adam_step_parity(lk):
+    th = theta0(8)
+    X, T = data(512, seed=9)
+    net = lk.MLP(max_rows=512)
+    net.set_params(th)
+    lr = 1e-3
+    loss = net.train_step(dev(X), dev(T), lr)
+    rl, rg = OM.loss_and_grad(th.astype(np.float64), X.astype(np.float64), T.astype(np.float64))
+    assert abs(loss - rl) <= 1e-4 * rl
+    new, _, _ = OM.adam(th, np.zeros(OM.N_PARAMS, np.float32), np.zeros(OM.N_PARAMS, np.float32),
+                        rg, 1, lr)
+    got = net.get_params()
+    assert np.abs(got - th).max() <= lr * 1.001 + 1e-7
+    o = 0
+    for name, shape in OM.SHAPES:
+        k = int(np.prod(shape))
+        sel = np.abs(rg[o:o + k]) > 1e-3 * np.abs(rg[o:o + k]).max()
+        assert np.abs(got[o:o + k][sel] - new[o:o + k][sel]).max() <= lr / 100, name
+        o += k
+    net.close()
+
+
+def test_training_reduces_loss(lk):
+    X, T = data(20000, seed=11)
+    net = lk.MLP(seed=3, max_rows=2048)
+    hist, secs = net.train(dev(X), dev(T), steps=400, batch=1024, lr=3e-3, lr_final=3e-4, seed=5)
+    assert hist.shape == (400,) and np.all(np.isfinite(hist))
+    assert hist[-20:].mean() < 0.1 * hist[:5].mean()
+    # the final full-data loss agrees with the oracle's loss of the trained weights
+    th = net.get_params().astype(np.float64)
+    loss, _ = net.gradient(dev(X[:2048]), dev(T[:2048]))
+    rl, _ = OM.loss_and_grad(th, X[:2048].astype(np.float64), T[:2048].astype(np.float64))
+    assert abs(loss - rl) <= 1e-3 * rl
+    net.close()
+
+
+@pytest.fixture(scope="module")
+def small(lk):
+    c = cg.ogrid(64, 20, r=None, seed=3)
+    return c, lk.Cloud(c)
+
+
+def test_features_parity(lk, small):
+    c, gc = small
+    st = lk.State(gc, 0.72, -1.5)
+    X, T = st.features(targets=True)
+    ref = OM.features(c.x, c.y, c.type, 0.72, -1.5)
+    assert np.abs(X.cpu().numpy() - ref).max() <= 1e-6
+    # targets of the free stream vanish (wall points: the normal velocity is removed)
+    o = O.Oracle(c, mach=0.72, aoa_deg=-1.5)
+    Tref = OM.targets(o.free_stream(), 0.72, -1.5)
+    assert np.abs(T.cpu().numpy() - Tref).max() <= 1e-6
+    # batch features are the conditions' features one after the other
+    b = lk.Batch([gc], [0, 0], [0.5, 0.8], [1.0, 4.0])
+    Xb = b.features().cpu().numpy()
+    assert np.abs(Xb[:c.n] - OM.features(c.x, c.y, c.type, 0.5, 1.0)).max() <= 1e-6
+    assert np.abs(Xb[c.n:] - OM.features(c.x, c.y, c.type, 0.8, 4.0)).max() <= 1e-6
+    st.close()
+    b.close()
+
+
+def test_warm_start_zero_network_keeps_free_stream(lk, small):
+    c, gc = small
+    st = lk.State(gc, 0.6, 2.0)
+    U0 = st.get_U()
+    _, res_fs = st.residual(want_R=False)
+    net = lk.MLP(max_rows=512)  # several chunks over the cloud
+    net.set_params(np.zeros(OM.N_PARAMS, np.float32))
+    fb, res = net.warm_start(st)
+    # the prediction is the free stream itself: its residual is not below the
+    # free-stream residual, so the judge keeps the free stream
+    assert fb[0] == 1 and res[0] == res_fs
+    assert np.array_equal(st.get_U(), U0)
+    bad = np.zeros(OM.N_PARAMS, np.float32)
+    bad[OM.N_PARAMS - 4:] = np.nan
+    net.set_params(bad)
+    fb, res = net.warm_start(st)
+    assert fb[0] == 1 and np.array_equal(st.get_U(), U0)
+    net.close()
+    st.close()
+
+
+def test_warm_start_state_and_judge(lk, small):
+    """A network with constant output c: U is the prediction map of c (or the
+    free stream when the judge rejects it) and the judged residual equals
+    the oracle's residual of that state."""
+    c, gc = small
+    mach, aoa = 0.6, 2.0
+    o = O.Oracle(c, mach=mach, aoa_deg=aoa)
+    _, res_fs = o.residual(o.free_stream())
+    net = lk.MLP(max_rows=1024)
+    for cst in ([0.01, 0.02, -0.01, 0.03], [-0.002, 0.004, 0.001, -0.003]):
+        th = np.zeros(OM.N_PARAMS, np.float32)
+        th[OM.N_PARAMS - 4:] = cst
+        net.set_params(th)
+        st = lk.State(gc, mach, aoa)
+        fb, res = net.warm_start(st)
+        Y = np.tile(np.asarray(cst, np.float32).astype(np.float64), (c.n, 1))
+        Up = OM.state_from_prediction(Y, c.type, c.tx, c.ty, mach, aoa)
+        _, rp = o.residual(Up)
+        assert abs(res[0] - rp) <= 1e-11 * rp
+        assert fb[0] == (0 if rp < res_fs else 1)
+        want = Up if fb[0] == 0 else o.free_stream()
+        assert np.abs(st.get_U() - want).max() <= 1e-14
+        st.close()
+    net.close()
+
+
+def test_warm_start_gain_held_out(lk):
+    """Trained on converged fields of 24 conditions (batched solves), the
+    network's warm start reaches the 1e-8 tolerance (relative to each
+    condition's own free-stream residual) in fewer iterations than the
+    free-stream start on 3 held-out conditions, with the same forces."""
+    import torch
+    c = cg.ogrid(96, 32, r=None, seed=21)
+    gc = lk.Cloud(c)
+    rng = np.random.default_rng(31)
+    Mtr, Atr = rng.uniform(0.3, 0.7, 24), rng.uniform(-2.0, 6.0, 24)
+    prm = lk.default_params(precision=lk.MIXED, tol_rel=1e-6, max_iters=20000, check_every=50)
+    b = lk.Batch([gc], np.zeros(24, np.int32), Mtr, Atr, prm)
+    reps, _ = b.solve()
+    assert all(r["status"] == 0 for r in reps)
+    X, T = b.features(targets=True)
+    b.close()
+    net = lk.MLP(seed=7, max_rows=4096)
+    hist, _ = net.train(X, T, steps=1500, batch=4096, lr=2e-3, lr_final=1e-4, seed=9)
+    assert hist[-50:].mean() < 0.05 * hist[:5].mean()
+    prm64 = lk.default_params(tol_rel=1e-8, max_iters=40000, check_every=50)
+    for mach, aoa in ((0.45, 1.0), (0.62, 4.5), (0.55, -1.0)):
+        fs = lk.State(gc, mach, aoa, prm64)
+        r_fs = fs.solve()
+        ws = lk.State(gc, mach, aoa, prm64)
+        fb, res = net.warm_start(ws)
+        r_ws = ws.solve()
+        assert r_fs.status == 0 and r_ws.status == 0
+        assert fb[0] == 0 and res[0] < 0.5 * r_fs.res_fs
+        assert r_ws.iters < r_fs.iters, (mach, aoa, r_ws.iters, r_fs.iters)
+        assert abs(r_ws.cl - r_fs.cl) <= 1e-6 and abs(r_ws.cd - r_fs.cd) <= 1e-6
+        fs.close()
+        ws.close()
+    net.close()
+    torch.cuda.synchronize()

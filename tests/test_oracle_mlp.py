@@ -1,0 +1,128 @@
+"""Pins of the warm-start MLP oracle (float64 reference of the HIP kernels).
+
+* GELU against its definition through the normal CDF and its derivative
+  against central differences;
+* the unquantised backward pass against central differences of the loss;
+* bfloat16 rounding: exact on representable values, ties to even, relative
+  error at most 2^-9;
+* the quantised and unquantised networks agree to bfloat16 accuracy;
+* Adam's first step moves every parameter by lr (bias-corrected m/sqrt(v) = sign(g)).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.stats import norm
+
+from oracle import mlp
+
+
+def params(seed=0, scale=1.0):
+    rng = np.random.default_rng(seed)
+    th = np.zeros(mlp.N_PARAMS)
+    o = 0
+    for name, shape in mlp.SHAPES:
+        k = int(np.prod(shape))
+        fan_in = shape[1] if len(shape) == 2 else 1
+        th[o:o + k] = rng.uniform(-1, 1, k) * scale / math.sqrt(fan_in) if len(shape) == 2 else \
+            rng.uniform(-0.1, 0.1, k)
+        o += k
+    return th
+
+
+def test_gelu_definition_and_derivative():
+    z = np.linspace(-6, 6, 101)
+    assert np.allclose(mlp.gelu(z), z * norm.cdf(z), rtol=1e-14, atol=1e-15)
+    h = 1e-5
+    fd = (mlp.gelu(z + h) - mlp.gelu(z - h)) / (2 * h)
+    assert np.allclose(mlp.gelu_prime(z), fd, rtol=1e-8, atol=1e-9)
+
+
+def test_unquantized_gradient_matches_central_differences():
+    rng = np.random.default_rng(1)
+    th = params(1)
+    X = rng.standard_normal((7, 5))
+    T = rng.standard_normal((7, 4)) * 0.3
+    loss, g = mlp.loss_and_grad(th, X, T, quantize=False)
+    idx = rng.choice(mlp.N_PARAMS, 60, replace=False)
+    idx = np.concatenate([idx, [0, 640, 768 + 5, 768 + 128 + 16384 + 7, mlp.N_PARAMS - 1]])
+    for i in idx:
+        h = 1e-6
+        tp, tm = th.copy(), th.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (mlp.loss_and_grad(tp, X, T, False)[0] - mlp.loss_and_grad(tm, X, T, False)[0]) / (2 * h)
+        assert fd == pytest.approx(g[i], rel=1e-6, abs=1e-10), i
+
+
+def test_bf16_rounding():
+    exact = np.array([1.0, -2.5, 0.15625, 3.0e38 * 0 + 1024.0])
+    assert np.array_equal(mlp.bf16(exact), exact)
+    # 1 + 2^-8 lies halfway between 1 and 1 + 2^-7: ties to even -> 1
+    assert mlp.bf16(np.array([1.0 + 2.0 ** -8]))[0] == 1.0
+    # 1 + 3*2^-8 is halfway between 1 + 2^-7 and 1 + 2^-6: ties to even -> 1 + 2^-6
+    assert mlp.bf16(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6
+    x = np.random.default_rng(2).standard_normal(10000) * 100
+    r = mlp.bf16(x)
+    # 8 significant bits: the rounding error is at most half a unit, 2^-8 relative
+    assert np.all(np.abs(r - x) <= 2.0 ** -8 * np.abs(x) * (1 + 1e-6))
+
+
+def test_quantized_network_close_to_float64():
+    rng = np.random.default_rng(3)
+    th = params(3)
+    X = rng.standard_normal((64, 5))
+    yq, _ = mlp.forward(th, X, True)
+    y, _ = mlp.forward(th, X, False)
+    assert np.abs(yq - y).max() < 0.05 * np.abs(y).max()
+
+
+def test_adam_first_step():
+    th = params(4).astype(np.float32)
+    g = np.random.default_rng(4).standard_normal(mlp.N_PARAMS)
+    g = np.where(np.abs(g) < 0.01, 0.01, g)   # |g| >> eps
+    m = np.zeros(mlp.N_PARAMS, np.float32)
+    v = np.zeros(mlp.N_PARAMS, np.float32)
+    th2, m2, v2 = mlp.adam(th, m, v, g, 1, 1e-3)
+    step = th - th2
+    assert np.allclose(step, 1e-3 * np.sign(g.astype(np.float32)), rtol=1e-3, atol=1e-9)
+
+
+def test_features_closed_forms():
+    # wall points: distance 0; a point on the chord line extension at (0.5 + t, 0)
+    # has f0 = t / (1 + |t|), f1 = 0; flow features are affine in (M, aoa)
+    x = np.array([0.0, 1.0, 0.5, 3.5, 0.5])
+    y = np.array([0.0, 0.0, 0.0, 0.0, -2.0])
+    t = np.array([0, 0, 1, 1, 1], np.int8)
+    F = mlp.features(x, y, t, 0.85, -4.0)
+    assert F[0, 2] == -1.0 and F[1, 2] == -1.0
+    assert F[3, 0] == pytest.approx(3.0 / 4.0) and F[3, 1] == 0.0
+    assert F[2, 2] == pytest.approx(2 * 0.5 / 0.6 - 1)          # nearest wall point 0.5 away
+    assert F[3, 2] == pytest.approx(2 * 2.5 / 2.6 - 1)
+    assert F[4, 1] == pytest.approx(-2.0 / 3.0) and F[4, 0] == 0.0
+    assert np.all(F[:, 3] == pytest.approx(1.0)) and np.all(F[:, 4] == pytest.approx(-1.0))
+
+
+def test_prediction_state_round_trip_and_free_stream():
+    import oracle as O
+    from paper_2406_07441_amd import cloudgen as cg
+    c = cg.ogrid(48, 12)
+    o = O.Oracle(c, mach=0.7, aoa_deg=3.0)
+    U = o.free_stream()
+    # the free stream (the oracle's own construction) is the zero deviation
+    Y0 = mlp.state_from_prediction(np.zeros((c.n, 4)), c.type, c.tx, c.ty, 0.7, 3.0)
+    assert np.allclose(Y0, U, rtol=0, atol=1e-15)
+    T = mlp.targets(U, 0.7, 3.0)
+    assert np.allclose(T[c.type != 0], 0.0, atol=1e-15)
+    # interior points: targets invert the prediction map exactly (up to rounding)
+    rng = np.random.default_rng(3)
+    Y = rng.uniform(-0.2, 0.2, (c.n, 4))
+    Us = mlp.state_from_prediction(Y, c.type, c.tx, c.ty, 0.7, 3.0)
+    back = mlp.targets(Us, 0.7, 3.0)
+    inter = c.type == 1
+    assert np.allclose(back[inter], Y[inter], rtol=0, atol=1e-13)
+    assert np.allclose(back[c.type == 2], 0.0, atol=1e-13)
+    # wall points: velocity tangent to the wall
+    w = c.type == 0
+    un = Us[1, w] * (-c.ty[w]) + Us[2, w] * c.tx[w]
+    assert np.abs(un).max() < 1e-14
