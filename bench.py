@@ -131,6 +131,86 @@ def batch_run(lk, cloudgen, iters):
     return out
 
 
+MLP_FLOP_PER_ROW = 2 * (5 * 128 + 2 * 128 * 128 + 128 * 4)   # 67,840
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def warm_start_run(lk, cloudgen, train_steps: int, held_out: int):
+    """Learned warm start, scaled down from the 640k-point / 512-field recipe:
+    converged fields of 32 conditions on 4 clouds of 20k-60k points (mixed
+    precision, to 1e-6) train the network; 4 held-out conditions on a held-out
+    640 x 256 cloud are then solved in FP64 to 1e-8 (of each condition's
+    free-stream residual) from the free stream and from the warm start."""
+    import numpy as np
+    import torch
+    clouds = cloudgen.batch_clouds(seed=40, count=4, nmin=20_000, nmax=60_000)
+    gcs = [lk.Cloud(c) for c in clouds]
+    mach, aoa = cloudgen.batch_conditions(seed=41, count=32)
+    prm = lk.default_params(cfl=CFL, inner_iters=INNER, precision=lk.MIXED, limiter=LIMITER,
+                            limiter_k=LIMITER_K, check_every=50, tol_rel=1e-6, max_iters=40000)
+    t0 = time.perf_counter()
+    b = lk.Batch(gcs, np.arange(32) % 4, mach, aoa, prm)
+    reps, _ = b.solve()
+    ok = [r["status"] == 0 for r in reps]
+    X, T = b.features(targets=True)
+    # rows of conditions that did not converge are left out of the training set
+    keep = torch.cat([torch.full((b.sizes[k],), bool(ok[k]), device="cuda") for k in range(32)])
+    X, T = X[keep].contiguous(), T[keep].contiguous()
+    b.close()
+    gen_s = time.perf_counter() - t0
+    net = lk.MLP(seed=11, max_rows=8192)
+    hist, train_s = net.train(X, T, steps=train_steps, batch=8192, lr=2e-3, lr_final=5e-5, seed=13)
+    rows = X.shape[0]
+
+    held = cloudgen.ogrid(640, 256, r=None, t=0.12, name="heldout640x256")
+    gh = lk.Cloud(held)
+    hm, ha = cloudgen.batch_conditions(seed=42, count=held_out)
+    prm64 = lk.default_params(cfl=CFL, inner_iters=INNER, limiter=LIMITER, limiter_k=LIMITER_K,
+                              check_every=50, tol_rel=1e-8, max_iters=60000)
+    cc = np.zeros(held_out, np.int32)
+    fs = lk.Batch([gh], cc, hm, ha, prm64)
+    r_fs, t_fs = fs.solve()
+    fs.close()
+    ws = lk.Batch([gh], cc, hm, ha, prm64)
+    # inference throughput on the held-out batch's points (features from the library)
+    Xh = ws.features()
+    torch.cuda.synchronize()
+    ti = time.perf_counter()
+    net.forward(Xh)
+    torch.cuda.synchronize()
+    infer_s = time.perf_counter() - ti
+    tw = time.perf_counter()
+    fb, res_w = net.warm_start(ws)
+    warm_s = time.perf_counter() - tw
+    r_ws, t_ws = ws.solve()
+    ws.close()
+    out = {
+        "training": {"clouds": [c.n for c in clouds], "conditions": 32,
+                     "converged": int(sum(ok)), "rows": rows, "field_gen_s": gen_s,
+                     "steps": train_steps, "batch": 8192, "train_s": train_s,
+                     "loss_first": float(hist[:10].mean()), "loss_last": float(hist[-50:].mean()),
+                     "train_tflops": 3 * MLP_FLOP_PER_ROW * 8192 * train_steps / train_s / 1e12},
+        "held_out": {"cloud": held.n, "conditions": [[float(m), float(a)] for m, a in zip(hm, ha)],
+                     "fallback": fb.tolist(),
+                     "res_warm_over_res_fs": [float(res_w[k] / r_fs[k]["res_fs"])
+                                              for k in range(held_out)],
+                     "iters_free_stream": [r["iters"] for r in r_fs],
+                     "iters_warm": [r["iters"] for r in r_ws],
+                     "status_free_stream": [r["status"] for r in r_fs],
+                     "status_warm": [r["status"] for r in r_ws],
+                     "seconds_free_stream": t_fs, "seconds_warm": t_ws + warm_s,
+                     "warm_start_s": warm_s,
+                     "max_abs_dcl": max(abs(r_ws[k]["cl"] - r_fs[k]["cl"]) for k in range(held_out)),
+                     "max_abs_dcd": max(abs(r_ws[k]["cd"] - r_fs[k]["cd"]) for k in range(held_out))},
+        "inference": {"rows": int(Xh.shape[0]), "seconds": infer_s,
+                      "tflops": MLP_FLOP_PER_ROW * Xh.shape[0] / infer_s / 1e12,
+                      "frac_bf16_peak": MLP_FLOP_PER_ROW * Xh.shape[0] / infer_s / 1e12
+                      / PEAK_BF16_TFLOPS},
+    }
+    net.close()
+    return out
+
+
 def cpu_baseline(cloud, iters: int):
     import oracle
     o = oracle.Oracle(cloud, mach=MACH, aoa_deg=AOA, cfl=CFL, inner_iters=INNER,
@@ -155,6 +235,10 @@ def main():
     ap.add_argument("--batch-iters", type=int, default=200,
                     help="iterations of the 64-condition batch run (0 skips it)")
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle iterations (0 skips)")
+    ap.add_argument("--warm-steps", type=int, default=3000,
+                    help="training steps of the warm-start leg (0 skips it)")
+    ap.add_argument("--warm-held-out", type=int, default=4,
+                    help="held-out conditions of the warm-start leg")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the timed steps (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -250,6 +334,9 @@ def main():
     if args.batch_iters > 0:
         extra["batch_64_conditions"] = batch_run(lk, cloudgen, args.batch_iters)
         print(f"# batch: {json.dumps(extra['batch_64_conditions'])}", file=sys.stderr, flush=True)
+    if args.warm_steps > 0:
+        extra["warm_start"] = warm_start_run(lk, cloudgen, args.warm_steps, args.warm_held_out)
+        print(f"# warm start: {json.dumps(extra['warm_start'])}", file=sys.stderr, flush=True)
     cpu = cpu_baseline(cloud, args.cpu_iters) if args.cpu_iters > 0 else None
 
     line = {

@@ -122,6 +122,23 @@ def test_iteration_parity_flux_difference(lk, cfg1):
         assert e < 1e-10
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+def test_sweep_lanes_parity(lk, cfg1, jit, lanes):
+    """The sweeps at every lane count give the oracle's increment."""
+    for case, it in ((cfg1, 10), (jit, 3)):
+        prm = lk.default_params(cfl=100.0, inner_iters=1, sweep_lanes=lanes)
+        mach, aoa = (0.63, 2.0) if case is cfg1 else (0.85, 1.0)
+        st = lk.State(case.gc, mach, aoa, prm)
+        U = case.states[it]
+        st.set_U(U)
+        st.step()
+        _, _, dUo, _ = case.o.iteration(U)
+        e = rel(st.get_dU(), dUo)
+        print(f"lanes={lanes} dU rel err {e:.3e}")
+        assert e < TOL
+        st.close()
+
+
 def test_jittered_transonic_parity(jit):
     for it in (0, 3):
         U = jit.states[it]
