@@ -77,8 +77,8 @@ typedef struct {
     int32_t check_every;/* lskum_solve reads the residual every k steps */
     double tol_rel;     /* lskum_solve stops when res <= tol_rel * res_fs */
     int32_t max_iters;  /* lskum_solve iteration cap */
-    int32_t sweep_lanes;    /* lanes per point in the sweep kernels: 1, 2, 4, 8;
-                               0 = library choice */
+    int32_t sweep_lanes;    /* lanes per point in the sweep kernels: 1, 2, 4, 8,
+                               16; 0 = library choice */
     int32_t residual_lanes; /* lanes per point in the residual kernel: 1, 2, 4,
                                8; 0 = library choice */
     int32_t limiter;        /* 0: none (the paper's scheme); 1: Venkatakrishnan
@@ -215,9 +215,9 @@ int lskum_batch_step_timed(lskum_batch* b, double* ms);
 int lskum_batch_get_U(lskum_batch* b, int32_t cond, double* U, int on_device);
 int lskum_batch_set_U(lskum_batch* b, int32_t cond, const double* U, int on_device);
 
-/* Autotuner: times `iters` iterations with 1, 2, 4 and 8 lanes per point
- * and keeps the fastest lane count for the sweep and for the residual
- * kernels (written to *sweep_lanes, *residual_lanes).  The batch's state is
+/* Autotuner: times `iters` iterations with 1, 2, 4, 8 (and, for the sweeps,
+ * 16) lanes per point and keeps the fastest lane count for the sweep and for
+ * the residual kernels (written to *sweep_lanes, *residual_lanes).  The batch's state is
  * restored afterwards. */
 int lskum_batch_autotune(lskum_batch* b, int32_t iters, int32_t* sweep_lanes,
                          int32_t* residual_lanes);

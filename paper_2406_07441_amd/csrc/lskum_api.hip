@@ -58,7 +58,8 @@ hipError_t upload(T* dst, const T* src, size_t count) {
 void free_cloud(lskum::Cloud& c) {
     void* ptrs[] = {c.xy,     c.frame,     c.type,   c.off,      c.idx,      c.colour,
                     c.col_perm, c.wall_list, c.geom, c.lo_off,   c.lo_idx,   c.up_off,
-                    c.up_idx, c.comp,      c.comp_off, c.wall_off, c.comp_inv_active,
+                    c.up_idx, c.lo_w,      c.up_w,     c.lo_code,  c.up_code,  c.comp,
+                    c.comp_off, c.wall_off, c.comp_inv_active,
                     c.comp_orient, c.chunk_start, c.chunk_comp, c.comp_chunk_off};
     for (void* p : ptrs) (void)hipFree(p);
     c = lskum::Cloud{};
@@ -150,17 +151,19 @@ int upload_cloud(lskum::Cloud& c) {
     std::vector<int32_t> perm(n), fill(c.h_col_off.begin(), c.h_col_off.end() - 1);
     for (int64_t p = 0; p < n; ++p) perm[fill[c.h_colour[p]]++] = (int32_t)p;
 
+    // sweep lists in colour-sorted point order
     std::vector<int32_t> lo_off(n + 1, 0), up_off(n + 1, 0), lo_idx, up_idx;
     lo_idx.reserve(nnz / 2 + 1);
     up_idx.reserve(nnz / 2 + 1);
-    for (int64_t p = 0; p < n; ++p) {
+    for (int64_t q = 0; q < n; ++q) {
+        const int32_t p = perm[q];
         for (int32_t e = c.h_off[p]; e < c.h_off[p + 1]; ++e) {
             const int32_t i = c.h_idx[e];
             if (c.h_colour[i] < c.h_colour[p]) lo_idx.push_back(i);
             else up_idx.push_back(i);
         }
-        lo_off[p + 1] = (int32_t)lo_idx.size();
-        up_off[p + 1] = (int32_t)up_idx.size();
+        lo_off[q + 1] = (int32_t)lo_idx.size();
+        up_off[q + 1] = (int32_t)up_idx.size();
     }
 
     // wall list per component (storage order) and polygon orientation
@@ -220,6 +223,10 @@ int upload_cloud(lskum::Cloud& c) {
     chk(dalloc(&c.up_off, n + 1));
     chk(dalloc(&c.lo_idx, lo_idx.size()));
     chk(dalloc(&c.up_idx, up_idx.size()));
+    chk(dalloc(&c.lo_w, lo_idx.size()));
+    chk(dalloc(&c.up_w, up_idx.size()));
+    chk(dalloc(&c.lo_code, lo_idx.size()));
+    chk(dalloc(&c.up_code, up_idx.size()));
     chk(dalloc(&c.comp_off, c.ncomp + 1));
     chk(dalloc(&c.wall_off, c.ncomp + 1));
     chk(dalloc(&c.comp_inv_active, c.ncomp));
@@ -274,6 +281,10 @@ int upload_cloud(lskum::Cloud& c) {
             return fail(LSKUM_ERR_DEGENERATE, "a point's full stencil has a singular LS matrix");
         chk(pe);
     }
+    if (e == hipSuccess) {
+        chk(lskum::launch_sweep_weights(c, nullptr));
+        if (e == hipSuccess) chk(hipStreamSynchronize(nullptr));
+    }
     if (e != hipSuccess) return hip_fail(e, "cloud upload");
     return LSKUM_OK;
 }
@@ -299,8 +310,8 @@ int check_params(const lskum_params* p) {
         p->check_every < 1 || p->check_every > 4096 || p->max_iters < 0 || !(p->tol_rel >= 0.0))
         return fail(LSKUM_ERR_ARG, "invalid lskum_params");
     auto lanes_ok = [](int l) { return l == 0 || l == 1 || l == 2 || l == 4 || l == 8; };
-    if (!lanes_ok(p->sweep_lanes) || !lanes_ok(p->residual_lanes))
-        return fail(LSKUM_ERR_ARG, "lanes must be 0, 1, 2, 4 or 8");
+    if (!(lanes_ok(p->sweep_lanes) || p->sweep_lanes == 16) || !lanes_ok(p->residual_lanes))
+        return fail(LSKUM_ERR_ARG, "lanes must be 0, 1, 2, 4 or 8 (16 for the sweeps)");
     if ((p->limiter != 0 && p->limiter != 1) || !(p->limiter_k > 0.0))
         return fail(LSKUM_ERR_ARG, "limiter must be 0 or 1 with limiter_k > 0");
     if (p->precision == 1 && p->jvp_mode == 1)
@@ -1045,7 +1056,7 @@ int lskum_batch_set_U(lskum_batch* b, int32_t cond, const double* U, int on_devi
     return LSKUM_OK;
 }
 
-// Times each candidate lane count (1, 2, 4, 8 lanes per point) for the sweep
+// Times each candidate lane count (1, 2, 4, 8 lanes per point; 16 for the sweeps) for the sweep
 // and the residual kernels on the batch itself and keeps the fastest of each.
 // The batch's state is saved before and restored after the trial steps.
 int lskum_batch_autotune(lskum_batch* b, int32_t iters, int32_t* sweep_lanes,
@@ -1057,15 +1068,15 @@ int lskum_batch_autotune(lskum_batch* b, int32_t iters, int32_t* sweep_lanes,
                           s.stream));
     HIPCHK(hipStreamSynchronize(s.stream));
     const lskum::Params keep = s.prm;
-    const int cands[4] = {1, 2, 4, 8};
+    const int cands[5] = {1, 2, 4, 8, 16};
     double best_sw = 1e300, best_rs = 1e300;
     int bsw = 8, brs = 2;
     lskum_state tmp;
     std::swap(tmp.s, b->s);
     int rc = LSKUM_OK;
-    for (int li = 0; li < 4 && rc == LSKUM_OK; ++li) {
+    for (int li = 0; li < 5 && rc == LSKUM_OK; ++li) {
         tmp.s.prm.sweep_lanes = cands[li];
-        tmp.s.prm.residual_lanes = cands[li];
+        tmp.s.prm.residual_lanes = li < 4 ? cands[li] : 8;
         apply_lanes(tmp.s);
         double ms[6], sw = 0, rs = 0;
         for (int it = 0; it < iters + 1 && rc == LSKUM_OK; ++it) {
@@ -1078,7 +1089,7 @@ int lskum_batch_autotune(lskum_batch* b, int32_t iters, int32_t* sweep_lanes,
             best_sw = sw;
             bsw = cands[li];
         }
-        if (rs < best_rs) {
+        if (li < 4 && rs < best_rs) {
             best_rs = rs;
             brs = cands[li];
         }

@@ -2,21 +2,25 @@
 //
 // One iteration (Section 4, Algorithm 3, with the colour sweeps of
 // Algorithms 6-7):
-//   k_qgrad_first / k_qgrad_inner   q-derivatives, eq. (16)
-//   k_residual                      LSKUM residual eq. (11), (15); local time
+//   k_qgrad<...>   x (1 + m)        q-derivatives, eq. (16): first-order pass and
+//                                   m inner passes; the optional limiter is
+//                                   applied in the last pass
+//   k_residual<...>                 LSKUM residual eq. (11), (15); local time
 //                                   step and scalar diagonal eq. (25), (34)-(35);
 //                                   per-point linearisation data for the sweeps
+//   k_norm_partial, k_norm_comp     density residual norm per component and the
+//                                   convergence test
 //   k_sweep<...>   x C colours      forward sweep, eq. (27) first line
 //   k_sweep<...>   x C colours      backward sweep, eq. (27) second line
 //   k_update                        U += dU and the q-variables of eq. (14)
-//   k_norm_final                    density residual norm
 //
-// Mapping: one thread per point, points of a block contiguous in storage so
-// that the ring-structured neighbour gathers of a wavefront fall on a few
-// cache lines; block ids are remapped so that consecutive point ranges stay
-// on one XCD (each XCD has its own L2).  All per-point sums run over the CSR
-// neighbour order.  The per-point 4x4 algebra is not a dense contraction, so
-// no matrix cores are used.
+// Mapping: LANES consecutive lanes share a point and split its neighbour
+// loop, combining partial sums with cross-lane shuffles in a fixed order;
+// points of a block are contiguous (storage order, or colour order in the
+// sweeps); block ids are remapped so that consecutive point ranges stay on one
+// XCD (each XCD has its own L2).  All per-point sums run in CSR neighbour
+// order.  The per-point 4x4 algebra is not a dense contraction, so no matrix
+// cores are used.
 #include "lskum_internal.h"
 
 #include <cmath>
@@ -687,13 +691,68 @@ __device__ __forceinline__ Lin<T> load_lin(const Vec4<T>* jv0, const Vec4<T>* jv
     return Lin<T>{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 }
 
+// Split weights and bits of the sweep-list entries of the colour-sorted point
+// q (thread per q): for interior points the x split (a) and y split (b) the
+// neighbour falls in, for wall points the t split (a) and, on the fluid side,
+// the n- split (b) -- membership and weights exactly as the residual forms them.
+__global__ void __launch_bounds__(kBlock) k_sweep_weights(int64_t n,
+                                                          const int32_t* __restrict__ col_perm,
+                                                          const D2* __restrict__ xy,
+                                                          const D2* __restrict__ frame,
+                                                          const int8_t* __restrict__ type,
+                                                          const PointGeom* __restrict__ geom,
+                                                          const int32_t* __restrict__ off,
+                                                          const int32_t* __restrict__ idx,
+                                                          D2* __restrict__ w,
+                                                          uint8_t* __restrict__ code) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int32_t p = col_perm[q];
+    const int8_t ty = type[p];
+    const D2 r0 = xy[p], t = frame[p];
+    const PointGeom& G = geom[p];
+    for (int32_t e = off[q]; e < off[q + 1]; ++e) {
+        const D2 ri = xy[idx[e]];
+        const double dx = ri.x - r0.x, dy = ri.y - r0.y;
+        uint8_t cd = 0;
+        double wa = 0.0, wb = 0.0;
+        if (ty == kWall) {
+            const double ds = dot_nc(dx, dy, t.x, t.y);
+            const double dn = dot_nc(dx, dy, -t.y, t.x);
+            cd |= kSwWall;
+            if (ds != 0.0) {
+                const D2 cc = ds < 0.0 ? G.split[0] : G.split[1];
+                cd |= kSwA | (ds < 0.0 ? kSwNegA : 0);
+                wa = cc.x * ds + cc.y * dn;
+            }
+            if (dn > 0.0) {
+                cd |= kSwB;
+                wb = G.split[2].x * dn + G.split[2].y * ds;
+            }
+        } else if (ty != kOuter) {
+            if (dx != 0.0) {
+                const D2 cc = dx < 0.0 ? G.split[0] : G.split[1];
+                cd |= kSwA | (dx < 0.0 ? kSwNegA : 0);
+                wa = cc.x * dx + cc.y * dy;
+            }
+            if (dy != 0.0) {
+                const D2 cc = dy < 0.0 ? G.split[2] : G.split[3];
+                cd |= kSwB | (dy < 0.0 ? kSwNegB : 0);
+                wb = cc.x * dy + cc.y * dx;
+            }
+        }
+        w[e] = {wa, wb};
+        code[e] = cd;
+    }
+}
+
 // Contribution sum_k w_i^k A_k(U_i) dU_i of neighbour i to point p's sweep
-// sum (eq. 22-27): interior points use the x and y split the neighbour
-// falls in, wall points the t split and, on the fluid side, the n- split.
+// sum (eq. 22-27) from the entry's weights and split bits: interior points
+// use the x and y split the neighbour falls in, wall points the t split and,
+// on the fluid side, the n- split (wall frame t of point p).
 template <class T, int MODE>
-__device__ __forceinline__ void sweep_contrib(int8_t ty, const D2& t, const D2& c0, const D2& c1,
-                                              const D2& c2, const D2& c3, double dx, double dy,
-                                              int32_t i, const Vec4<T>* __restrict__ jv0,
+__device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const D2& w, int32_t i,
+                                              const Vec4<T>* __restrict__ jv0,
                                               const Vec4<T>* __restrict__ jv1,
                                               const Vec4<T>* __restrict__ jv2,
                                               const D4* __restrict__ U,
@@ -704,14 +763,10 @@ __device__ __forceinline__ void sweep_contrib(int8_t ty, const D2& t, const D2& 
     const T dv[4] = {di.x, di.y, di.z, di.w};
     const Lin<T> L = load_lin(jv0, jv1, i);
     T J[4];
-    if (ty == kWall) {
-        const double ds = dot_nc(dx, dy, t.x, t.y);
-        const double dn = dot_nc(dx, dy, -t.y, t.x);
+    if (cd & kSwWall) {
         // wall-frame directions: erf/exp at the neighbour state are formed here
-        if (ds != 0.0) {
-            const D2 cc = ds < 0.0 ? c0 : c1;
-            const double sg = ds < 0.0 ? 1.0 : -1.0;
-            const T w = T(cc.x * ds + cc.y * dn);
+        if (cd & kSwA) {
+            const double sg = (cd & kSwNegA) ? 1.0 : -1.0;
             if constexpr (MODE == 1) {
                 const double S = (L.u1 * t.x + L.u2 * t.y) * L.sb;
                 jvp_fluxdiff(L, erf(S), exp(-(S * S)), U[i], t.x, t.y, sg, dv, gamma,
@@ -720,11 +775,11 @@ __device__ __forceinline__ void sweep_contrib(int8_t ty, const D2& t, const D2& 
                 const T S = (L.u1 * T(t.x) + L.u2 * T(t.y)) * L.sb;
                 jvp_exact<T>(L, erf(S), exp(-(S * S)), T(t.x), T(t.y), T(sg), dv, gm1, inv_gm1, J);
             }
+            const T wa = T(w.x);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
+            for (int v = 0; v < 4; ++v) acc[v] += wa * J[v];
         }
-        if (dn > 0.0) {
-            const T w = T(c2.x * dn + c2.y * ds);
+        if (cd & kSwB) {
             if constexpr (MODE == 1) {
                 const double S = (-L.u1 * t.y + L.u2 * t.x) * L.sb;
                 jvp_fluxdiff(L, erf(S), exp(-(S * S)), U[i], -t.y, t.x, -1.0, dv, gamma,
@@ -733,33 +788,32 @@ __device__ __forceinline__ void sweep_contrib(int8_t ty, const D2& t, const D2& 
                 const T S = (-L.u1 * T(t.y) + L.u2 * T(t.x)) * L.sb;
                 jvp_exact<T>(L, erf(S), exp(-(S * S)), T(-t.y), T(t.x), T(-1), dv, gm1, inv_gm1, J);
             }
+            const T wb = T(w.y);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
+            for (int v = 0; v < 4; ++v) acc[v] += wb * J[v];
         }
         return;
     }
     const Vec4<T> k2 = jv2[i];
-    if (dx != 0.0) {
-        const D2 cc = dx < 0.0 ? c0 : c1;
-        const T sg = dx < 0.0 ? T(1) : T(-1);
-        const T w = T(cc.x * dx + cc.y * dy);
+    if (cd & kSwA) {
+        const T sg = (cd & kSwNegA) ? T(1) : T(-1);
         if constexpr (MODE == 1)
             jvp_fluxdiff(L, k2.x, k2.y, U[i], 1.0, 0.0, sg, dv, gamma, 1.0 / (gamma - 1.0), J);
         else
             jvp_exact<T>(L, k2.x, k2.y, T(1), T(0), sg, dv, gm1, inv_gm1, J);
+        const T wa = T(w.x);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
+        for (int v = 0; v < 4; ++v) acc[v] += wa * J[v];
     }
-    if (dy != 0.0) {
-        const D2 cc = dy < 0.0 ? c2 : c3;
-        const T sg = dy < 0.0 ? T(1) : T(-1);
-        const T w = T(cc.x * dy + cc.y * dx);
+    if (cd & kSwB) {
+        const T sg = (cd & kSwNegB) ? T(1) : T(-1);
         if constexpr (MODE == 1)
             jvp_fluxdiff(L, k2.z, k2.w, U[i], 0.0, 1.0, sg, dv, gamma, 1.0 / (gamma - 1.0), J);
         else
             jvp_exact<T>(L, k2.z, k2.w, T(0), T(1), sg, dv, gm1, inv_gm1, J);
+        const T wb = T(w.y);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] += w * J[v];
+        for (int v = 0; v < 4; ++v) acc[v] += wb * J[v];
     }
 }
 
@@ -767,22 +821,26 @@ __device__ __forceinline__ void sweep_contrib(int8_t ty, const D2& t, const D2& 
 // backward: dU_0 = dU*_0 - (sum_upper w A dU) / D_0.  MODE 0 exact tangent,
 // 1 flux difference.  T is the arithmetic of the products and increments.
 // LANES consecutive lanes share one point: each walks every LANES-th entry of
-// the point's lower (forward) or upper (backward) neighbour list, and the
-// partial sums are combined with cross-lane shuffles.
+// the point's lower (forward) or upper (backward) list, and the partial sums
+// are combined with cross-lane shuffles.  The phase's points are the
+// colour-sorted positions [start, start + count) and their lists one
+// contiguous block.
 template <class T, bool FWD, int MODE, int LANES>
 __global__ void __launch_bounds__(kBlock) k_sweep(
     int32_t start, int32_t count, const int32_t* __restrict__ col_perm,
-    const D2* __restrict__ xy, const D2* __restrict__ frame, const int8_t* __restrict__ type,
+    const D2* __restrict__ frame, const int8_t* __restrict__ type,
     const int32_t* __restrict__ loff, const int32_t* __restrict__ lidx,
-    const PointGeom* __restrict__ geom, const int32_t* __restrict__ comp,
-    const int32_t* __restrict__ active, const Vec4<T>* __restrict__ jv0,
-    const Vec4<T>* __restrict__ jv1, const Vec4<T>* __restrict__ jv2,
-    const D4* __restrict__ U, const D4* __restrict__ R, const T* __restrict__ Dg,
-    Vec4<T>* __restrict__ dU, double gamma) {
+    const D2* __restrict__ lw, const uint8_t* __restrict__ lcode,
+    const int32_t* __restrict__ comp, const int32_t* __restrict__ active,
+    const Vec4<T>* __restrict__ jv0, const Vec4<T>* __restrict__ jv1,
+    const Vec4<T>* __restrict__ jv2, const D4* __restrict__ U, const D4* __restrict__ R,
+    const T* __restrict__ Dg, Vec4<T>* __restrict__ dU, double gamma) {
     const int gt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int pt = gt / LANES, lane = gt % LANES;
     if (pt >= count) return;  // uniform over the lanes of a point
-    const int32_t p = col_perm[start + pt];
+    const int32_t q = start + pt;
+    const int32_t p = col_perm[q];
+    const int32_t e0 = loff[q], e1 = loff[q + 1];
     if (!live(comp, active, p)) return;
     const int8_t ty = type[p];
     if (ty == kOuter) {
@@ -790,17 +848,9 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
         return;
     }
     T acc[4] = {T(0), T(0), T(0), T(0)};
-    const D2 r0 = xy[p];
-    const PointGeom& G = geom[p];
-    const D2 c0 = G.split[0], c1 = G.split[1], c2 = G.split[2], c3 = G.split[3];
     const D2 t = frame[p];
-    const int32_t e1 = loff[p + 1];
-    for (int32_t e = loff[p] + lane; e < e1; e += LANES) {
-        const int32_t i = lidx[e];
-        const D2 ri = xy[i];
-        sweep_contrib<T, MODE>(ty, t, c0, c1, c2, c3, ri.x - r0.x, ri.y - r0.y, i, jv0, jv1, jv2,
-                               U, dU, gamma, acc);
-    }
+    for (int32_t e = e0 + lane; e < e1; e += LANES)
+        sweep_contrib<T, MODE>(lcode[e], t, lw[e], lidx[e], jv0, jv1, jv2, U, dU, gamma, acc);
 #pragma unroll
     for (int o = LANES / 2; o > 0; o >>= 1)
 #pragma unroll
@@ -946,6 +996,18 @@ hipError_t launch_precompute(Cloud& c, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_sweep_weights(Cloud& c, hipStream_t st) {
+    if (c.n > 0) {
+        hipLaunchKernelGGL(k_sweep_weights, dim3(grid_for(c.n)), dim3(kBlock), 0, st, c.n,
+                           c.col_perm, c.xy, c.frame, c.type, c.geom, c.lo_off, c.lo_idx, c.lo_w,
+                           c.lo_code);
+        hipLaunchKernelGGL(k_sweep_weights, dim3(grid_for(c.n)), dim3(kBlock), 0, st, c.n,
+                           c.col_perm, c.xy, c.frame, c.type, c.geom, c.up_off, c.up_idx, c.up_w,
+                           c.up_code);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_free_stream(State& s) {
     const Cloud& c = *s.cloud;
     hipLaunchKernelGGL(k_free_stream, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream, c.n, c.type,
@@ -1059,12 +1121,14 @@ static void sweep_lanes(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T
         const dim3 g(grid_for((int64_t)cnt * LANES)), b(kBlock);
         if (forward)
             hipLaunchKernelGGL((k_sweep<T, true, MODE, LANES>), g, b, 0, s.stream, start, cnt,
-                               c.col_perm, c.xy, c.frame, c.type, c.lo_off, c.lo_idx, c.geom,
-                               c.comp, s.active, jv0, jv1, jv2, s.U, s.R, Dg, dU, s.prm.gamma);
+                               c.col_perm, c.frame, c.type, c.lo_off, c.lo_idx, c.lo_w,
+                               c.lo_code, c.comp, s.active, jv0, jv1, jv2, s.U, s.R, Dg, dU,
+                               s.prm.gamma);
         else
             hipLaunchKernelGGL((k_sweep<T, false, MODE, LANES>), g, b, 0, s.stream, start, cnt,
-                               c.col_perm, c.xy, c.frame, c.type, c.up_off, c.up_idx, c.geom,
-                               c.comp, s.active, jv0, jv1, jv2, s.U, s.R, Dg, dU, s.prm.gamma);
+                               c.col_perm, c.frame, c.type, c.up_off, c.up_idx, c.up_w,
+                               c.up_code, c.comp, s.active, jv0, jv1, jv2, s.U, s.R, Dg, dU,
+                               s.prm.gamma);
     }
 }
 
@@ -1075,6 +1139,7 @@ static void sweep_t(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* j
         case 1: sweep_lanes<T, MODE, 1>(s, forward, jv0, jv1, jv2, Dg, dU); break;
         case 2: sweep_lanes<T, MODE, 2>(s, forward, jv0, jv1, jv2, Dg, dU); break;
         case 8: sweep_lanes<T, MODE, 8>(s, forward, jv0, jv1, jv2, Dg, dU); break;
+        case 16: sweep_lanes<T, MODE, 16>(s, forward, jv0, jv1, jv2, Dg, dU); break;
         default: sweep_lanes<T, MODE, 4>(s, forward, jv0, jv1, jv2, Dg, dU); break;
     }
 }

@@ -35,6 +35,8 @@ struct alignas(32) PointGeom {
     D4 ls1;
 };
 
+constexpr uint8_t kSwA = 1, kSwNegA = 2, kSwB = 4, kSwNegB = 8, kSwWall = 16;
+
 struct Cloud {
     int device = 0;
     int64_t n = 0, nnz = 0;
@@ -52,12 +54,21 @@ struct Cloud {
     int32_t* colour = nullptr;
     int32_t* col_perm = nullptr;   // points sorted by colour, then index
     int32_t* wall_list = nullptr;  // wall points in storage order
-    // neighbours of each point split by colour, CSR order kept within each list:
-    // lower colours (read by the forward sweep) and higher colours (backward)
+    // Sweep lists: the neighbours of each point split by colour -- lower
+    // colours (read by the forward sweep) and higher colours (backward) --
+    // with CSR order kept, laid out in colour-sorted point order (list of the
+    // point col_perm[q] at entries [lo_off[q], lo_off[q+1])), so that a colour
+    // phase reads one contiguous block.  Per entry: the neighbour, the weights
+    // (w_a, w_b) of the point's a-split (x+/x-, or t+/t- at a wall) and b-split
+    // (y+/y-, or n- at a wall) the neighbour lies in, and kSw* split bits.
     int32_t* lo_off = nullptr;
     int32_t* lo_idx = nullptr;
+    D2* lo_w = nullptr;
+    uint8_t* lo_code = nullptr;
     int32_t* up_off = nullptr;
     int32_t* up_idx = nullptr;
+    D2* up_w = nullptr;
+    uint8_t* up_code = nullptr;
     // Components: a batch cloud is the disjoint union of one copy of a cloud
     // per flow condition.  Component k owns points [comp_off[k], comp_off[k+1])
     // and wall-list entries [wall_off[k], wall_off[k+1]).  A plain cloud has
@@ -157,6 +168,8 @@ struct State {
 
 // Kernel launchers (lskum_device.hip).  All enqueue on s->stream.
 hipError_t launch_precompute(Cloud& c, hipStream_t st);
+// split weights and bits of the sweep lists (after launch_precompute)
+hipError_t launch_sweep_weights(Cloud& c, hipStream_t st);
 hipError_t launch_free_stream(State& s);
 hipError_t launch_q_from_U(State& s);
 hipError_t launch_q_derivatives(State& s);  // includes the limiter when on

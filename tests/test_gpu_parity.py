@@ -122,7 +122,7 @@ def test_iteration_parity_flux_difference(lk, cfg1):
         assert e < 1e-10
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
 def test_sweep_lanes_parity(lk, cfg1, jit, lanes):
     """The sweeps at every lane count give the oracle's increment."""
     for case, it in ((cfg1, 10), (jit, 3)):
