@@ -41,7 +41,7 @@ class _Cloud(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("mach", C.c_double),
                 ("aoa_deg", C.c_double), ("inner_iters", C.c_int32), ("jvp_mode", C.c_int32),
-                ("limiter", C.c_int32), ("pad", C.c_int32), ("limiter_k", C.c_double)]
+                ("limiter", C.c_int32), ("variant", C.c_int32), ("limiter_k", C.c_double)]
 
 
 _lib = None
@@ -72,6 +72,8 @@ def lib():
             "ora_lusgs": (None, [P, P, P, P, P, P]),
             "ora_residual_norm": (D, [P, P]),
             "ora_iteration": (I32, [P, P, P, P, P, P]),
+            "ora_unsplit_jvp": (None, [P, P, D, D, P, P]),
+            "ora_manish_source": (None, [P, P, P, P, P]),
             "ora_solve": (I32, [P, P, P, I32, D, P]),
             "ora_forces": (I32, [P, P, P, P, P]),
         }
@@ -105,9 +107,21 @@ def split_flux(U, d, s, gamma=GAMMA):
     return G
 
 
+ANANDH, MANISH = 0, 1
+
+
 def params(mach=0.63, aoa_deg=2.0, cfl=100.0, inner_iters=1, jvp_mode=0, gamma=GAMMA, limiter=0,
-           limiter_k=5.0):
-    return _Params(gamma, cfl, mach, aoa_deg, inner_iters, jvp_mode, limiter, 0, limiter_k)
+           limiter_k=5.0, variant=ANANDH):
+    return _Params(gamma, cfl, mach, aoa_deg, inner_iters, jvp_mode, limiter, variant, limiter_k)
+
+
+def unsplit_jvp(U, dU, d, jvp_mode=0, gamma=GAMMA):
+    """Unsplit Euler flux Jacobian product A_d(U) dU (exact or flux difference)."""
+    J = np.empty(4)
+    prm = params(jvp_mode=jvp_mode, gamma=gamma)
+    lib().ora_unsplit_jvp(_p(_f64(U)), _p(_f64(dU)), float(d[0]), float(d[1]), C.byref(prm),
+                          _p(J))
+    return J
 
 
 def flux_jvp(U, dU, d, s, jvp_mode=0, gamma=GAMMA):
@@ -138,7 +152,7 @@ class Oracle:
     """Oracle bound to one cloud and one flow condition."""
 
     def __init__(self, cloud, mach=0.63, aoa_deg=2.0, cfl=100.0, inner_iters=1, jvp_mode=0,
-                 gamma=GAMMA, colours=None, limiter=0, limiter_k=5.0):
+                 gamma=GAMMA, colours=None, limiter=0, limiter_k=5.0, variant=ANANDH):
         self.cloud = cloud
         self._keep = [_f64(cloud.x), _f64(cloud.y), _f64(cloud.tx), _f64(cloud.ty),
                       np.ascontiguousarray(cloud.type, dtype=np.int8),
@@ -153,7 +167,8 @@ class Oracle:
         k = self._keep
         self.c = _Cloud(cloud.n, _p(k[0]), _p(k[1]), _p(k[2]), _p(k[3]), _p(k[4]), _p(k[5]),
                         _p(k[6]), _p(col), nc)
-        self.prm = params(mach, aoa_deg, cfl, inner_iters, jvp_mode, gamma, limiter, limiter_k)
+        self.prm = params(mach, aoa_deg, cfl, inner_iters, jvp_mode, gamma, limiter, limiter_k,
+                          variant)
         self.n = cloud.n
 
     # -- state -------------------------------------------------------------
@@ -219,10 +234,18 @@ class Oracle:
     def residual_norm(self, R):
         return float(lib().ora_residual_norm(C.byref(self.c), _p(_f64(R))))
 
-    def iteration(self, U):
-        """One iteration; returns (U_new, R, dU, res)."""
+    def manish_source(self, U, dU_prev):
+        S = np.empty((4, self.n))
+        lib().ora_manish_source(C.byref(self.c), C.byref(self.prm), _p(_f64(U)),
+                                _p(None if dU_prev is None else _f64(dU_prev)), _p(S))
+        return S
+
+    def iteration(self, U, dU_prev=None):
+        """One iteration; returns (U_new, R, dU, res).  dU_prev: the previous
+        iteration's increment (Manish variant; None = zero)."""
         U = _f64(U).copy()
-        R, dU = np.empty((4, self.n)), np.empty((4, self.n))
+        R = np.empty((4, self.n))
+        dU = np.zeros((4, self.n)) if dU_prev is None else _f64(dU_prev).copy()
         res = C.c_double(0.0)
         st = lib().ora_iteration(C.byref(self.c), C.byref(self.prm), _p(U), _p(R), _p(dU),
                                  C.byref(res))

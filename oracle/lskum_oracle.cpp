@@ -171,6 +171,7 @@ struct Params {
     int32_t inner_iters, jvp_mode;  // jvp_mode 0 exact tangent, 1 flux difference
     int32_t limiter;                // 0 none (the paper), 1 Venkatakrishnan on q~
     double limiter_k;
+    int32_t variant;                // 0 Anandhanarayanan et al., 1 Manish et al.
 };
 
 enum { OK = 0, ERR_ARG = -1, ERR_CONN = -2, ERR_DEGEN = -3, ERR_COLOUR = -4, ERR_NONPHYS = -5 };
@@ -453,11 +454,46 @@ void flux_jvp(const double U[4], const double dU[4], const Split& k, const Param
     for (int v = 0; v < 4; ++v) J[v] = G[v].d;
 }
 
-// Local time step and scalar diagonal (eq. 25 with eq. 34-35).
+// Unsplit Euler flux along unit direction d (eq. 2):
+//   (rho u_d, p d + rho u u_d, (rho E + p) u_d).
+template <class T>
+void unsplit_flux(const Prim<T>& w, double dx, double dy, double gamma, T G[4]) {
+    T ud = w.u1 * dx + w.u2 * dy;
+    T rhoE = w.p / (gamma - 1.0) + 0.5 * w.rho * (w.u1 * w.u1 + w.u2 * w.u2);
+    G[0] = w.rho * ud;
+    G[1] = w.p * dx + w.rho * w.u1 * ud;
+    G[2] = w.p * dy + w.rho * w.u2 * ud;
+    G[3] = (rhoE + w.p) * ud;
+}
+
+// Unsplit flux Jacobian product A_d(U) dU: exact by forward-mode AD
+// (jvp_mode 0) or the flux difference G_d(U + dU) - G_d(U) (jvp_mode 1), the
+// same two treatments as the split products.
+void unsplit_jvp(const double U[4], const double dU[4], double dx, double dy, const Params& P,
+                 double J[4]) {
+    if (P.jvp_mode == 1) {
+        double Ua[4], Ga[4], Gb[4];
+        for (int v = 0; v < 4; ++v) Ua[v] = U[v] + dU[v];
+        unsplit_flux(prim_from_U(Ua, P.gamma), dx, dy, P.gamma, Ga);
+        unsplit_flux(prim_from_U(U, P.gamma), dx, dy, P.gamma, Gb);
+        for (int v = 0; v < 4; ++v) J[v] = Ga[v] - Gb[v];
+        return;
+    }
+    Dual Ud[4], G[4];
+    for (int v = 0; v < 4; ++v) Ud[v] = Dual(U[v], dU[v]);
+    unsplit_flux(prim_from_U(Ud, P.gamma), dx, dy, P.gamma, G);
+    for (int v = 0; v < 4; ++v) J[v] = G[v].d;
+}
+
+// Local time step and scalar diagonal.
 // Reading (time step, not given in the paper):
 //   dt_0 = CFL * min_i |r_i - r_0| / (|u_0| + a_0).
-// Diagonal: D_0 = 1/dt_0 - sum_k s_k LS_k(1) rho(A_k^{s_k}), with the spectral
-// radii of eq. (35): rho(A+) = max(u_d + a, 0), rho(A-) = max(a - u_d, 0).
+// Anandhanarayanan et al. (eq. 25 with eq. 34-35): the split Jacobians are
+// replaced by +-rho(A^+-) I with rho(A+) = max(u_d + a, 0), rho(A-) =
+// max(a - u_d, 0), so D_0 = 1/dt_0 - sum_k s_k LS_k(1) rho(A_k^{s_k}).
+// Manish et al. (eq. 29-33): A^+- = (A +- rho(A) I)/2 with rho(A) = |u_d| + a;
+// the rho part gives the scalar D_0 = 1/dt_0 - sum_k s_k LS_k(1) rho(A_k)/2 and
+// the A part the term S of manish_source.
 void timestep_diag(const Cloud& c, const Params& P, const double* U, double* dt, double* D) {
     for (int64_t p = 0; p < c.n; ++p) {
         double Up[4] = {U[p], U[c.n + p], U[2 * c.n + p], U[3 * c.n + p]};
@@ -478,12 +514,43 @@ void timestep_diag(const Cloud& c, const Params& P, const double* U, double* dt,
         for (int k = 0; k < ns; ++k) {
             Stencil stn = split_stencil(c, p, sp[k]);
             double ud = w.u1 * sp[k].dx + w.u2 * sp[k].dy;
+            if (P.variant == 1) {
+                Dp -= (double)sp[k].s * stn.ls1 * 0.5 * (std::fabs(ud) + a);
+                continue;
+            }
             double rad = (double)sp[k].s * ud + a;
             if (rad < 0.0) rad = 0.0;
             Dp -= (double)sp[k].s * stn.ls1 * rad;
         }
         dt[p] = dtp;
         D[p] = Dp;
+    }
+}
+
+// The term S of Manish et al. (eq. 33, kept on the explicit side, eq. 36-38):
+//   S_0 = -1/2 sum_k LS_k(1) (A_{d_k}(U_0) dU_0),
+// the unsplit Jacobian of each split's direction at the point's own state.
+// Reading: S is evaluated with the increment of the previous iteration
+// (dU_prev; zero at the first iteration), the only increment known when the
+// forward sweep's right-hand side R - S is formed.  On a symmetric stencil
+// LS_k+(1) = -LS_k-(1) and S vanishes.
+void manish_source(const Cloud& c, const Params& P, const double* U, const double* dU_prev,
+                   double* S) {
+    for (int64_t p = 0; p < c.n; ++p) {
+        double Sp[4] = {0, 0, 0, 0};
+        Split sp[4];
+        int ns = splits_of(c, p, sp);
+        double Up[4] = {U[p], U[c.n + p], U[2 * c.n + p], U[3 * c.n + p]};
+        double dUp[4] = {0, 0, 0, 0};
+        if (dU_prev)
+            for (int v = 0; v < 4; ++v) dUp[v] = dU_prev[v * c.n + p];
+        for (int k = 0; k < ns; ++k) {
+            Stencil stn = split_stencil(c, p, sp[k]);
+            double J[4];
+            unsplit_jvp(Up, dUp, sp[k].dx, sp[k].dy, P, J);
+            for (int v = 0; v < 4; ++v) Sp[v] -= 0.5 * stn.ls1 * J[v];
+        }
+        for (int v = 0; v < 4; ++v) S[v * c.n + p] = Sp[v];
     }
 }
 
@@ -585,7 +652,7 @@ typedef struct {
 typedef struct {
     double gamma, cfl, mach, aoa_deg;
     int32_t inner_iters, jvp_mode;
-    int32_t limiter, pad;
+    int32_t limiter, variant;
     double limiter_k;
 } ora_params;
 
@@ -593,8 +660,8 @@ static Cloud to_cloud(const ora_cloud* c) {
     return Cloud{c->n, c->x, c->y, c->tx, c->ty, c->type, c->off, c->idx, c->colour, c->ncolour};
 }
 static Params to_params(const ora_params* p) {
-    return Params{p->gamma,       p->cfl,      p->mach,    p->aoa_deg,
-                  p->inner_iters, p->jvp_mode, p->limiter, p->limiter_k};
+    return Params{p->gamma,       p->cfl,      p->mach,    p->aoa_deg, p->inner_iters,
+                  p->jvp_mode,    p->limiter,  p->limiter_k, p->variant};
 }
 
 // Point colouring, Algorithm 4: colour(first point) = first colour; then for
@@ -749,22 +816,41 @@ double ora_residual_norm(const ora_cloud* oc, const double* R) {
     return residual_norm(to_cloud(oc), R);
 }
 
+void ora_unsplit_jvp(const double* U, const double* dU, double dx, double dy,
+                     const ora_params* prm, double* J) {
+    unsplit_jvp(U, dU, dx, dy, to_params(prm), J);
+}
+
+void ora_manish_source(const ora_cloud* oc, const ora_params* prm, const double* U,
+                       const double* dU_prev, double* S) {
+    manish_source(to_cloud(oc), to_params(prm), U, dU_prev, S);
+}
+
 // One implicit iteration (body of Algorithm 1): q_variables, q_derivatives,
-// flux_residual, LUSGS, state_update.  U is updated in place; R and dU
-// (optional) receive this iteration's residual and increment; *res the norm
-// of R.  Returns 0, or ERR_NONPHYS (-5) / ERR_DEGEN (-3).
+// flux_residual, LUSGS, state_update.  U is updated in place; R (optional)
+// receives this iteration's residual and *res its norm.  dU_io (optional): on
+// entry the previous iteration's increment (read by the Manish variant's S;
+// NULL = zero), on exit this iteration's increment.  Returns 0, or
+// ERR_NONPHYS (-5) / ERR_DEGEN (-3).
 int32_t ora_iteration(const ora_cloud* oc, const ora_params* prm, double* U, double* R_out,
-                      double* dU_out, double* res) {
+                      double* dU_io, double* res) {
     Cloud c = to_cloud(oc);
     Params P = to_params(prm);
     std::vector<double> R(4 * c.n), dU(4 * c.n), dt(c.n), D(c.n);
     int st = ora_residual(oc, prm, U, R.data(), res, nullptr);
     if (st) return st;
     timestep_diag(c, P, U, dt.data(), D.data());
-    lusgs(c, P, U, R.data(), D.data(), dU.data());
+    std::vector<double> rhs(R);
+    if (P.variant == 1) {
+        // forward-sweep right-hand side R - S (eq. 38)
+        std::vector<double> S(4 * c.n);
+        manish_source(c, P, U, dU_io, S.data());
+        for (int64_t i = 0; i < 4 * c.n; ++i) rhs[i] = R[i] - S[i];
+    }
+    lusgs(c, P, U, rhs.data(), D.data(), dU.data());
     st = state_update(c, P, U, dU.data());
     if (R_out) std::memcpy(R_out, R.data(), sizeof(double) * 4 * c.n);
-    if (dU_out) std::memcpy(dU_out, dU.data(), sizeof(double) * 4 * c.n);
+    if (dU_io) std::memcpy(dU_io, dU.data(), sizeof(double) * 4 * c.n);
     return st;
 }
 
@@ -773,9 +859,10 @@ int32_t ora_iteration(const ora_cloud* oc, const ora_params* prm, double* U, dou
 // Returns the number of iterations run, or a negative status.
 int32_t ora_solve(const ora_cloud* oc, const ora_params* prm, double* U, int32_t max_iters,
                   double tol_abs, double* history) {
+    std::vector<double> dU(4 * oc->n, 0.0);  // increment carried between iterations
     for (int32_t it = 0; it < max_iters; ++it) {
         double res = 0.0;
-        int32_t st = ora_iteration(oc, prm, U, nullptr, nullptr, &res);
+        int32_t st = ora_iteration(oc, prm, U, nullptr, dU.data(), &res);
         if (history) history[it] = res;
         if (st) return st;
         if (res <= tol_abs) return it + 1;
