@@ -131,6 +131,92 @@ def batch_run(lk, cloudgen, iters):
     return out
 
 
+CHUNK_ITERS = 2000   # long solves run in chunks, each printing a progress line
+
+
+def solve_chunked(obj, prm, max_iters, n_cond, label):
+    """Solves a State (n_cond 1) or Batch to its tolerance in chunks of
+    CHUNK_ITERS iterations; returns per-condition (iters, seconds, status, cl,
+    cd) at first convergence and the total seconds."""
+    done = [None] * n_cond
+    total_it, total_s = 0, 0.0
+    last = None
+    while total_it < max_iters and any(d is None for d in done):
+        prm.max_iters = min(CHUNK_ITERS, max_iters - total_it)
+        obj.set_params(prm)
+        if n_cond == 1:
+            r = obj.solve()
+            reps, secs = [r.as_dict()], r.seconds
+        else:
+            reps, secs = obj.solve()
+        for k, r in enumerate(reps):
+            if done[k] is None and r["status"] == 0:
+                done[k] = {"iters": total_it + r["iters"], "seconds": total_s + r["seconds"],
+                           "status": 0, "cl": r["cl"], "cd": r["cd"],
+                           "res_drop": r["res_final"] / r["res_fs"]}
+        total_it += prm.max_iters
+        total_s += secs
+        last = reps
+        print(f"# {label}: {total_it} iterations, {total_s:.1f} s, "
+              f"{sum(d is not None for d in done)}/{n_cond} converged", file=sys.stderr, flush=True)
+        if any(r["status"] == -5 for r in reps):
+            break
+    for k in range(n_cond):
+        if done[k] is None:
+            done[k] = {"iters": total_it, "seconds": total_s, "status": last[k]["status"],
+                       "cl": last[k]["cl"], "cd": last[k]["cd"],
+                       "res_drop": last[k]["res_final"] / last[k]["res_fs"]}
+    return done, total_s
+
+
+def batch_converge(lk, cloudgen, max_iters):
+    """The 64-condition batch solved to 1e-8 of each condition's free-stream
+    residual: time until all retire, per-condition iterations."""
+    import numpy as np
+    clouds = cloudgen.batch_clouds()
+    gcs = [lk.Cloud(c) for c in clouds]
+    mach, aoa = cloudgen.batch_conditions()
+    prm = lk.default_params(cfl=CFL, inner_iters=INNER, precision=lk.MIXED, limiter=LIMITER,
+                            limiter_k=LIMITER_K, check_every=100, tol_rel=1e-8)
+    b = lk.Batch(gcs, np.arange(64) % 8, mach, aoa, prm)
+    lanes = b.autotune(2)
+    prm.sweep_lanes, prm.residual_lanes = lanes[0], lanes[1]
+    done, tot = solve_chunked(b, prm, max_iters, 64, "batch to 1e-8")
+    pts = sum(d["iters"] * b.sizes[k] for k, d in enumerate(done))
+    out = {"conditions": 64, "points": b.n_points,
+           "seconds_until_all_retired": max(d["seconds"] for d in done),
+           "point_iters_per_s": pts / tot, "lanes": {"sweep": lanes[0], "residual": lanes[1]},
+           "iters": [d["iters"] for d in done],
+           "not_converged": [k for k, d in enumerate(done) if d["status"] != 0]}
+    b.close()
+    return out
+
+
+def config3_run(lk, cloudgen, max_iters):
+    """2560 x 1024 cloud, M 0.5, AoA 3 deg: FP64 against mixed precision to 1e-8
+    (limiter on: without it the impulsive start goes non-physical on this cloud
+    within 2,000 iterations)."""
+    import numpy as np
+    cloud = cloudgen.cloud_2621440()
+    gc = lk.Cloud(cloud)
+    out, U = {}, {}
+    for name, prec in (("fp64", lk.FP64), ("mixed", lk.MIXED)):
+        prm = lk.default_params(cfl=CFL, inner_iters=INNER, precision=prec, check_every=100,
+                                tol_rel=1e-8, limiter=LIMITER, limiter_k=LIMITER_K)
+        st = lk.State(gc, 0.5, 3.0, prm)
+        (d,), secs = solve_chunked(st, prm, max_iters, 1, f"2.6M {name}")
+        U[name] = st.get_U()
+        out[name] = {"converged": d["status"] == 0, "iters": d["iters"], "seconds": d["seconds"],
+                     "point_iters_per_s": cloud.n * d["iters"] / d["seconds"],
+                     "res_drop": d["res_drop"], "cl": d["cl"], "cd": d["cd"]}
+        st.close()
+    out["max_abs_dU_mixed_vs_fp64"] = float(np.abs(U["mixed"] - U["fp64"]).max())
+    out["dcl"] = out["mixed"]["cl"] - out["fp64"]["cl"]
+    out["dcd"] = out["mixed"]["cd"] - out["fp64"]["cd"]
+    out["points"] = cloud.n
+    return out
+
+
 MLP_FLOP_PER_ROW = 2 * (5 * 128 + 2 * 128 * 128 + 128 * 4)   # 67,840
 PEAK_BF16_TFLOPS = 2500.0
 
@@ -138,9 +224,11 @@ PEAK_BF16_TFLOPS = 2500.0
 def warm_start_run(lk, cloudgen, train_steps: int, held_out: int):
     """Learned warm start, scaled down from the 640k-point / 512-field recipe:
     converged fields of 32 conditions on 4 clouds of 20k-60k points (mixed
-    precision, to 1e-6) train the network; 4 held-out conditions on a held-out
-    640 x 256 cloud are then solved in FP64 to 1e-8 (of each condition's
-    free-stream residual) from the free stream and from the warm start."""
+    precision, to 1e-6) train the network; `held_out` conditions on a held-out
+    640 x 256 cloud are then solved to 1e-8 of each condition's free-stream
+    residual three ways: the plain FP64 solver one condition at a time from the
+    free stream (baseline); the mixed-precision batch from the free stream; the
+    mixed-precision batch from the warm start."""
     import numpy as np
     import torch
     clouds = cloudgen.batch_clouds(seed=40, count=4, nmin=20_000, nmax=60_000)
@@ -158,57 +246,80 @@ def warm_start_run(lk, cloudgen, train_steps: int, held_out: int):
     X, T = X[keep].contiguous(), T[keep].contiguous()
     b.close()
     gen_s = time.perf_counter() - t0
+    print(f"# warm start: {int(sum(ok))}/32 training fields in {gen_s:.1f} s", file=sys.stderr,
+          flush=True)
     net = lk.MLP(seed=11, max_rows=8192)
-    hist, train_s = net.train(X, T, steps=train_steps, batch=8192, lr=2e-3, lr_final=5e-5, seed=13)
+    hist, train_s = net.train(X, T, steps=train_steps, batch=8192, lr=3e-3, lr_final=1e-5, seed=13)
     rows = X.shape[0]
+    print(f"# warm start: trained {train_steps} steps in {train_s:.1f} s", file=sys.stderr,
+          flush=True)
 
     held = cloudgen.ogrid(640, 256, r=None, t=0.12, name="heldout640x256")
     gh = lk.Cloud(held)
     hm, ha = cloudgen.batch_conditions(seed=42, count=held_out)
-    prm64 = lk.default_params(cfl=CFL, inner_iters=INNER, limiter=LIMITER, limiter_k=LIMITER_K,
-                              check_every=50, tol_rel=1e-8, max_iters=60000)
+    common = dict(cfl=CFL, inner_iters=INNER, limiter=LIMITER, limiter_k=LIMITER_K,
+                  check_every=50, tol_rel=1e-8, max_iters=60000)
+    # (a) baseline: plain FP64 solver, one condition at a time, free-stream start
+    base = []
+    for m, a_ in zip(hm, ha):
+        st = lk.State(gh, float(m), float(a_), lk.default_params(**common))
+        r = st.solve()
+        base.append(r.as_dict())
+        st.close()
+    base_s = sum(r["seconds"] for r in base)
+    print(f"# warm start: FP64 baseline {base_s:.1f} s", file=sys.stderr, flush=True)
     cc = np.zeros(held_out, np.int32)
-    fs = lk.Batch([gh], cc, hm, ha, prm64)
-    r_fs, t_fs = fs.solve()
-    fs.close()
-    ws = lk.Batch([gh], cc, hm, ha, prm64)
-    # inference throughput on the held-out batch's points (features from the library)
-    Xh = ws.features()
+    prm_mx = lk.default_params(precision=lk.MIXED, **common)
+    # (b) mixed-precision batch, free-stream start
+    bf = lk.Batch([gh], cc, hm, ha, prm_mx)
+    r_bf, t_bf = bf.solve()
+    bf.close()
+    # (c) mixed-precision batch, warm start (inference and judge inside the timing)
+    bw = lk.Batch([gh], cc, hm, ha, prm_mx)
+    Xh = bw.features()
     torch.cuda.synchronize()
     ti = time.perf_counter()
     net.forward(Xh)
     torch.cuda.synchronize()
     infer_s = time.perf_counter() - ti
     tw = time.perf_counter()
-    fb, res_w = net.warm_start(ws)
+    fb, res_w = net.warm_start(bw)
     warm_s = time.perf_counter() - tw
-    r_ws, t_ws = ws.solve()
-    ws.close()
-    out = {
+    r_bw, t_bw = bw.solve()
+    bw.close()
+    net.close()
+    return {
         "training": {"clouds": [c.n for c in clouds], "conditions": 32,
                      "converged": int(sum(ok)), "rows": rows, "field_gen_s": gen_s,
                      "steps": train_steps, "batch": 8192, "train_s": train_s,
                      "loss_first": float(hist[:10].mean()), "loss_last": float(hist[-50:].mean()),
                      "train_tflops": 3 * MLP_FLOP_PER_ROW * 8192 * train_steps / train_s / 1e12},
-        "held_out": {"cloud": held.n, "conditions": [[float(m), float(a)] for m, a in zip(hm, ha)],
-                     "fallback": fb.tolist(),
-                     "res_warm_over_res_fs": [float(res_w[k] / r_fs[k]["res_fs"])
-                                              for k in range(held_out)],
-                     "iters_free_stream": [r["iters"] for r in r_fs],
-                     "iters_warm": [r["iters"] for r in r_ws],
-                     "status_free_stream": [r["status"] for r in r_fs],
-                     "status_warm": [r["status"] for r in r_ws],
-                     "seconds_free_stream": t_fs, "seconds_warm": t_ws + warm_s,
-                     "warm_start_s": warm_s,
-                     "max_abs_dcl": max(abs(r_ws[k]["cl"] - r_fs[k]["cl"]) for k in range(held_out)),
-                     "max_abs_dcd": max(abs(r_ws[k]["cd"] - r_fs[k]["cd"]) for k in range(held_out))},
+        "held_out": {
+            "cloud": held.n, "conditions": [[float(m), float(a_)] for m, a_ in zip(hm, ha)],
+            "fp64_single_free_stream": {"iters": [r["iters"] for r in base],
+                                        "status": [r["status"] for r in base],
+                                        "seconds": base_s},
+            "mixed_batch_free_stream": {"iters": [r["iters"] for r in r_bf],
+                                        "status": [r["status"] for r in r_bf],
+                                        "seconds": t_bf},
+            "mixed_batch_warm_start": {"iters": [r["iters"] for r in r_bw],
+                                       "status": [r["status"] for r in r_bw],
+                                       "seconds": t_bw + warm_s, "warm_start_s": warm_s,
+                                       "fallback": fb.tolist(),
+                                       "res_warm_over_res_fs": [float(res_w[k] / r_bw[k]["res_fs"])
+                                                                for k in range(held_out)]},
+            "speedup_vs_fp64_baseline": base_s / (t_bw + warm_s),
+            "warm_start_iteration_saving": 1.0 - sum(r["iters"] for r in r_bw)
+            / max(1, sum(r["iters"] for r in r_bf)),
+            "max_abs_dcl_vs_baseline": max(abs(r_bw[k]["cl"] - base[k]["cl"])
+                                           for k in range(held_out)),
+            "max_abs_dcd_vs_baseline": max(abs(r_bw[k]["cd"] - base[k]["cd"])
+                                           for k in range(held_out))},
         "inference": {"rows": int(Xh.shape[0]), "seconds": infer_s,
                       "tflops": MLP_FLOP_PER_ROW * Xh.shape[0] / infer_s / 1e12,
                       "frac_bf16_peak": MLP_FLOP_PER_ROW * Xh.shape[0] / infer_s / 1e12
                       / PEAK_BF16_TFLOPS},
     }
-    net.close()
-    return out
 
 
 def cpu_baseline(cloud, iters: int):
@@ -235,10 +346,14 @@ def main():
     ap.add_argument("--batch-iters", type=int, default=200,
                     help="iterations of the 64-condition batch run (0 skips it)")
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle iterations (0 skips)")
-    ap.add_argument("--warm-steps", type=int, default=3000,
+    ap.add_argument("--warm-steps", type=int, default=6000,
                     help="training steps of the warm-start leg (0 skips it)")
     ap.add_argument("--warm-held-out", type=int, default=4,
                     help="held-out conditions of the warm-start leg")
+    ap.add_argument("--batch-converge-iters", type=int, default=0,
+                    help="solve the 64-condition batch to 1e-8 with this cap (0 skips)")
+    ap.add_argument("--config3-iters", type=int, default=0,
+                    help="2,621,440-point FP64 vs mixed run to 1e-8 with this cap (0 skips)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the timed steps (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -334,6 +449,13 @@ def main():
     if args.batch_iters > 0:
         extra["batch_64_conditions"] = batch_run(lk, cloudgen, args.batch_iters)
         print(f"# batch: {json.dumps(extra['batch_64_conditions'])}", file=sys.stderr, flush=True)
+    if args.batch_converge_iters > 0:
+        extra["batch_64_to_1e-8"] = batch_converge(lk, cloudgen, args.batch_converge_iters)
+        print(f"# batch to 1e-8: {json.dumps(extra['batch_64_to_1e-8'])}", file=sys.stderr,
+              flush=True)
+    if args.config3_iters > 0:
+        extra["cloud_2621440_to_1e-8"] = config3_run(lk, cloudgen, args.config3_iters)
+        print(f"# 2.6M: {json.dumps(extra['cloud_2621440_to_1e-8'])}", file=sys.stderr, flush=True)
     if args.warm_steps > 0:
         extra["warm_start"] = warm_start_run(lk, cloudgen, args.warm_steps, args.warm_held_out)
         print(f"# warm start: {json.dumps(extra['warm_start'])}", file=sys.stderr, flush=True)

@@ -60,6 +60,7 @@ enum {
 
 enum { LSKUM_JVP_EXACT = 0, LSKUM_JVP_FLUXDIFF = 1 };
 enum { LSKUM_FP64 = 0, LSKUM_MIXED = 1 };
+enum { LSKUM_ANANDH = 0, LSKUM_MANISH = 1 };
 
 typedef struct lskum_cloud lskum_cloud; /* device geometry, CSR, colours */
 typedef struct lskum_state lskum_state; /* device flow state and work arrays */
@@ -86,6 +87,12 @@ typedef struct {
                                for flows with shocks) */
     double limiter_k;       /* limiter constant K: eps^2 = (K h)^3, h the
                                nearest-neighbour distance */
+    int32_t variant;        /* LSKUM_ANANDH: scalar diagonal of Anandhanarayanan
+                               et al. (eq. 34-35); LSKUM_MANISH: Manish et al.
+                               (eq. 29-33, 36-38): diagonal with rho(A)/2 and
+                               the term S on the forward right-hand side R - S,
+                               S from the previous iteration's increment (zero
+                               after state creation or a new U) */
 } lskum_params;
 
 typedef struct {
@@ -100,7 +107,7 @@ typedef struct {
 
 /* Fills p with the defaults: gamma 1.4, cfl 100, inner_iters 1, exact JVP,
  * fp64, check_every 10, tol_rel 1e-8, max_iters 20000, lanes 0 (library
- * choice), no limiter (limiter_k 5). */
+ * choice), no limiter (limiter_k 5), Anandhanarayanan variant. */
 void lskum_default_params(lskum_params* p);
 
 /* Creates a cloud on the current HIP device from host arrays of n points.

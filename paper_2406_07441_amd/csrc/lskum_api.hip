@@ -293,7 +293,7 @@ void free_state(lskum::State& s) {
     if (s.graph) (void)hipGraphExecDestroy(s.graph);
     if (s.have_events)
         for (hipEvent_t ev : s.ev) (void)hipEventDestroy(ev);
-    void* ptrs[] = {s.U,    s.q,      s.qx[0], s.qx[1],  s.qy[0],   s.qy[1],    s.qxl,
+    void* ptrs[] = {s.U,    s.q,      s.qx[0], s.qx[1],  s.qy[0],   s.qy[1],    s.qxl, s.Rs,
                     s.qyl,  s.R,      s.dU,    s.jv0,    s.jv1,     s.jv2,      s.D,
                     s.jv0f, s.jv1f,   s.jv2f,  s.dUf,    s.Df,      s.rr,       s.fsum, s.partial,
                     s.res_hist, s.flags, s.active, s.status, s.iters, s.res_last, s.tol_abs,
@@ -314,6 +314,8 @@ int check_params(const lskum_params* p) {
         return fail(LSKUM_ERR_ARG, "lanes must be 0, 1, 2, 4 or 8 (16 for the sweeps)");
     if ((p->limiter != 0 && p->limiter != 1) || !(p->limiter_k > 0.0))
         return fail(LSKUM_ERR_ARG, "limiter must be 0 or 1 with limiter_k > 0");
+    if (p->variant != 0 && p->variant != 1)
+        return fail(LSKUM_ERR_ARG, "variant must be LSKUM_ANANDH or LSKUM_MANISH");
     if (p->precision == 1 && p->jvp_mode == 1)
         return fail(LSKUM_ERR_ARG, "mixed precision supports the exact Jacobian products only");
     return LSKUM_OK;
@@ -322,7 +324,8 @@ int check_params(const lskum_params* p) {
 lskum::Params to_params(const lskum_params* p) {
     return lskum::Params{p->gamma,       p->cfl,            p->inner_iters, p->jvp_mode,
                          p->precision,   p->check_every,    p->tol_rel,     p->max_iters,
-                         p->sweep_lanes, p->residual_lanes, p->limiter,     p->limiter_k};
+                         p->sweep_lanes, p->residual_lanes, p->limiter,     p->limiter_k,
+                         p->variant};
 }
 
 // Lanes per point: the caller's choice, else 8 for the latency-bound sweeps
@@ -416,6 +419,7 @@ int init_state(lskum::State& s, const lskum::Cloud& c, const lskum_params* prm,
     chk(dalloc(&s.qxl, n));
     chk(dalloc(&s.qyl, n));
     chk(dalloc(&s.R, n));
+    chk(dalloc(&s.Rs, n));
     chk(dalloc(&s.dU, n));
     chk(dalloc(&s.jv0, n));
     chk(dalloc(&s.jv1, n));
@@ -452,6 +456,7 @@ int init_state(lskum::State& s, const lskum::Cloud& c, const lskum_params* prm,
     HIPCHK(lskum::launch_reset_components(s));
     HIPCHK(lskum::launch_free_stream(s));
     HIPCHK(lskum::launch_q_from_U(s));
+    HIPCHK(lskum::clear_increment(s, 0, n));
     // residual norms of the free-stream state: the anchors of the relative tolerance
     HIPCHK(lskum::launch_q_derivatives(s));
     HIPCHK(lskum::launch_residual(s, 0));
@@ -598,6 +603,7 @@ void lskum_default_params(lskum_params* p) {
     p->max_iters = 20000;
     p->limiter = 0;
     p->limiter_k = 5.0;
+    p->variant = LSKUM_ANANDH;
 }
 
 int lskum_cloud_create(int64_t n, const double* x, const double* y, const int8_t* type,
@@ -728,12 +734,17 @@ int lskum_state_set_params(lskum_state* so, const lskum_params* prm) {
                               np.jvp_mode == s.prm.jvp_mode && np.precision == s.prm.precision &&
                               np.limiter == s.prm.limiter && np.limiter_k == s.prm.limiter_k &&
                               np.sweep_lanes == s.prm.sweep_lanes &&
-                              np.residual_lanes == s.prm.residual_lanes;
+                              np.residual_lanes == s.prm.residual_lanes &&
+                              np.variant == s.prm.variant;
     if (s.graph && !same_kernels) {
         (void)hipGraphExecDestroy(s.graph);
         s.graph = nullptr;
     }
-    if (np.precision != s.prm.precision) s.have_dU = false;
+    if (np.precision != s.prm.precision) {
+        // the lagged increment of the Manish variant lives in the sweep precision's array
+        s.have_dU = false;
+        HIPCHK(lskum::clear_increment(s, 0, s.cloud->n));
+    }
     s.prm = np;
     apply_lanes(s);
     return LSKUM_OK;
@@ -754,6 +765,7 @@ int lskum_state_set_U(lskum_state* so, const double* U, int on_device) {
     }
     HIPCHK(lskum::launch_clear_flags(s.flags, s.stream));
     HIPCHK(lskum::launch_q_from_U(s));
+    HIPCHK(lskum::clear_increment(s, 0, n));
     int32_t f = 0;
     if (int r = read_flags(s, &f)) return r;
     s.have_dU = false;
@@ -1050,6 +1062,7 @@ int lskum_batch_set_U(lskum_batch* b, int32_t cond, const double* U, int on_devi
     }
     HIPCHK(lskum::launch_clear_flags(s.flags, s.stream));
     HIPCHK(lskum::launch_q_from_U(s));
+    HIPCHK(lskum::clear_increment(s, p0, n));
     int32_t f = 0;
     if (int r = read_flags(s, &f)) return r;
     if (f) return fail(LSKUM_ERR_NONPHYSICAL, "state has rho <= 0 or p <= 0");

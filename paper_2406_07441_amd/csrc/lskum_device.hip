@@ -399,6 +399,37 @@ __global__ void __launch_bounds__(kBlock) k_qgrad(
     }
 }
 
+// Unsplit Euler flux Jacobian product A_d(U) dU along unit direction d
+// (eq. 2 differentiated by hand): with u_d' = ((dm . d) - u_d drho)/rho and
+// p' = (gamma-1)(dE - u . dm + |u|^2 drho / 2),
+//   (dm . d, dm u_d + m u_d' + p' d, (dE + p') u_d + (E + p) u_d');
+// FD = true: the flux difference G_d(U + dU) - G_d(U) instead.
+template <bool FD>
+__device__ __forceinline__ void unsplit_jvp(const D4& u, const double dv[4], double dx, double dy,
+                                            double gm1, double J[4]) {
+    if (FD) {
+        const double a0 = u.x + dv[0], a1 = u.y + dv[1], a2 = u.z + dv[2], a3 = u.w + dv[3];
+        const double ua = (a1 * dx + a2 * dy) / a0, ub = (u.y * dx + u.z * dy) / u.x;
+        const double pa = gm1 * (a3 - 0.5 * (a1 * a1 + a2 * a2) / a0);
+        const double pb = gm1 * (u.w - 0.5 * (u.y * u.y + u.z * u.z) / u.x);
+        J[0] = (a1 * dx + a2 * dy) - (u.y * dx + u.z * dy);
+        J[1] = (a1 * ua + pa * dx) - (u.y * ub + pb * dx);
+        J[2] = (a2 * ua + pa * dy) - (u.z * ub + pb * dy);
+        J[3] = (a3 + pa) * ua - (u.w + pb) * ub;
+        return;
+    }
+    const double irho = 1.0 / u.x, u1 = u.y * irho, u2 = u.z * irho;
+    const double ud = u1 * dx + u2 * dy;
+    const double p = gm1 * (u.w - 0.5 * u.x * (u1 * u1 + u2 * u2));
+    const double dmd = dv[1] * dx + dv[2] * dy;
+    const double udd = (dmd - ud * dv[0]) * irho;
+    const double pd = gm1 * (dv[3] - (u1 * dv[1] + u2 * dv[2]) + 0.5 * (u1 * u1 + u2 * u2) * dv[0]);
+    J[0] = dmd;
+    J[1] = dv[1] * ud + u.y * udd + pd * dx;
+    J[2] = dv[2] * ud + u.z * udd + pd * dy;
+    J[3] = (dv[3] + pd) * ud + (u.w + p) * udd;
+}
+
 // ---------------------------------------------------------------------------
 // Residual (eq. 11 with the q~ reconstruction of eq. 15), local time step,
 // scalar diagonal (eq. 25, 34-35) and the sweep linearisation data.
@@ -416,7 +447,8 @@ __global__ void __launch_bounds__(kBlock) k_residual(
     const D4* __restrict__ qy, D4* __restrict__ R, double* __restrict__ Dg,
     D4* __restrict__ jv0, D4* __restrict__ jv1, D4* __restrict__ jv2, F4* __restrict__ jv0f,
     F4* __restrict__ jv1f, F4* __restrict__ jv2f, float* __restrict__ Df,
-    double* __restrict__ rr_out, int32_t* __restrict__ flags) {
+    double* __restrict__ rr_out, int32_t* __restrict__ flags, int variant, int fd,
+    const D4* __restrict__ dUprev, const F4* __restrict__ dUprevf, D4* __restrict__ Rs) {
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t gt = (int64_t)lb * blockDim.x + threadIdx.x;
     const int64_t p = gt / LANES;
@@ -513,16 +545,63 @@ __global__ void __launch_bounds__(kBlock) k_residual(
             const PointGeom& G = geom[p];
             const double dt = cfl * G.lsq.w / (sqrt(usq) + a);
             double Dp = 1.0 / dt;
-            if (ty == kWall) {
-                const double ut = u1 * t.x + u2 * t.y, un = -u1 * t.y + u2 * t.x;
-                Dp -= G.ls1.x * fmax(ut + a, 0.0);
-                Dp += G.ls1.y * fmax(a - ut, 0.0);
-                Dp += G.ls1.z * fmax(a - un, 0.0);
-            } else if (ty != kOuter) {
-                Dp -= G.ls1.x * fmax(u1 + a, 0.0);
-                Dp += G.ls1.y * fmax(a - u1, 0.0);
-                Dp -= G.ls1.z * fmax(u2 + a, 0.0);
-                Dp += G.ls1.w * fmax(a - u2, 0.0);
+            if (variant == 0) {
+                // Anandhanarayanan et al.: split Jacobians -> +-rho(A+-) I (eq. 34-35)
+                if (ty == kWall) {
+                    const double ut = u1 * t.x + u2 * t.y, un = -u1 * t.y + u2 * t.x;
+                    Dp -= G.ls1.x * fmax(ut + a, 0.0);
+                    Dp += G.ls1.y * fmax(a - ut, 0.0);
+                    Dp += G.ls1.z * fmax(a - un, 0.0);
+                } else if (ty != kOuter) {
+                    Dp -= G.ls1.x * fmax(u1 + a, 0.0);
+                    Dp += G.ls1.y * fmax(a - u1, 0.0);
+                    Dp -= G.ls1.z * fmax(u2 + a, 0.0);
+                    Dp += G.ls1.w * fmax(a - u2, 0.0);
+                }
+            } else {
+                // Manish et al.: A+- = (A +- rho(A) I)/2, rho(A) = |u_d| + a (eq. 29-33); the
+                // A part, S_0 = -1/2 sum_k LS_k(1) A_k dU_0, is taken with the previous
+                // iteration's increment onto the forward right-hand side R - S (eq. 36-38)
+                double dv[4] = {0, 0, 0, 0};
+                if (MIXED) {
+                    const F4 d = dUprevf[p];
+                    dv[0] = d.x; dv[1] = d.y; dv[2] = d.z; dv[3] = d.w;
+                } else {
+                    const D4 d = dUprev[p];
+                    dv[0] = d.x; dv[1] = d.y; dv[2] = d.z; dv[3] = d.w;
+                }
+                double Sv[4] = {0, 0, 0, 0}, Ja[4], Jb[4];
+                double ca = 0.0, cb = 0.0;
+                if (ty == kWall) {
+                    const double ut = u1 * t.x + u2 * t.y, un = -u1 * t.y + u2 * t.x;
+                    Dp -= 0.5 * (fabs(ut) + a) * (G.ls1.x - G.ls1.y);
+                    Dp += 0.5 * (fabs(un) + a) * G.ls1.z;
+                    if (fd) {
+                        unsplit_jvp<true>(u, dv, t.x, t.y, gamma - 1.0, Ja);
+                        unsplit_jvp<true>(u, dv, -t.y, t.x, gamma - 1.0, Jb);
+                    } else {
+                        unsplit_jvp<false>(u, dv, t.x, t.y, gamma - 1.0, Ja);
+                        unsplit_jvp<false>(u, dv, -t.y, t.x, gamma - 1.0, Jb);
+                    }
+                    ca = G.ls1.x + G.ls1.y;
+                    cb = G.ls1.z;
+                } else if (ty != kOuter) {
+                    Dp -= 0.5 * (fabs(u1) + a) * (G.ls1.x - G.ls1.y);
+                    Dp -= 0.5 * (fabs(u2) + a) * (G.ls1.z - G.ls1.w);
+                    if (fd) {
+                        unsplit_jvp<true>(u, dv, 1.0, 0.0, gamma - 1.0, Ja);
+                        unsplit_jvp<true>(u, dv, 0.0, 1.0, gamma - 1.0, Jb);
+                    } else {
+                        unsplit_jvp<false>(u, dv, 1.0, 0.0, gamma - 1.0, Ja);
+                        unsplit_jvp<false>(u, dv, 0.0, 1.0, gamma - 1.0, Jb);
+                    }
+                    ca = G.ls1.x + G.ls1.y;
+                    cb = G.ls1.z + G.ls1.w;
+                }
+                if (ty != kOuter)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) Sv[v] = -0.5 * (ca * Ja[v] + cb * Jb[v]);
+                Rs[p] = {Rp[0] - Sv[0], Rp[1] - Sv[1], Rp[2] - Sv[2], Rp[3] - Sv[3]};
             }
             if (MIXED) {
                 jv0f[p] = {(float)j0.x, (float)j0.y, (float)j0.z, (float)j0.w};
@@ -1071,7 +1150,8 @@ static void residual_lanes(State& s) {
                        s.prm.gamma, s.prm.cfl, c.xy, c.frame, c.type, c.off, c.idx, c.geom, c.comp,
                        s.active, s.U, s.q, s.prm.limiter ? s.qxl : s.qx[s.qsel],
                        s.prm.limiter ? s.qyl : s.qy[s.qsel], s.R, s.D, s.jv0, s.jv1, s.jv2,
-                       s.jv0f, s.jv1f, s.jv2f, s.Df, s.rr, s.flags);
+                       s.jv0f, s.jv1f, s.jv2f, s.Df, s.rr, s.flags, s.prm.variant,
+                       s.prm.jvp_mode, s.dU, s.dUf, s.Rs);
 }
 
 template <bool MIXED>
@@ -1122,8 +1202,8 @@ static void sweep_lanes(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T
         if (forward)
             hipLaunchKernelGGL((k_sweep<T, true, MODE, LANES>), g, b, 0, s.stream, start, cnt,
                                c.col_perm, c.frame, c.type, c.lo_off, c.lo_idx, c.lo_w,
-                               c.lo_code, c.comp, s.active, jv0, jv1, jv2, s.U, s.R, Dg, dU,
-                               s.prm.gamma);
+                               c.lo_code, c.comp, s.active, jv0, jv1, jv2, s.U,
+                               s.prm.variant ? s.Rs : s.R, Dg, dU, s.prm.gamma);
         else
             hipLaunchKernelGGL((k_sweep<T, false, MODE, LANES>), g, b, 0, s.stream, start, cnt,
                                c.col_perm, c.frame, c.type, c.up_off, c.up_idx, c.up_w,
@@ -1198,6 +1278,13 @@ hipError_t launch_aosf_to_soa(const F4* aos, double* soa, int64_t n, hipStream_t
 hipError_t launch_clear_flags(int32_t* flags, hipStream_t st) {
     hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, st, flags);
     return hipGetLastError();
+}
+
+hipError_t clear_increment(State& s, int64_t p0, int64_t n) {
+    if (n <= 0) return hipSuccess;
+    hipError_t e = hipMemsetAsync(s.dU + p0, 0, n * sizeof(D4), s.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s.dUf + p0, 0, n * sizeof(F4), s.stream);
+    return e;
 }
 
 }  // namespace lskum

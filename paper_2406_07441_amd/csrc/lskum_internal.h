@@ -106,6 +106,7 @@ struct Params {
     int sweep_lanes, residual_lanes;
     int limiter;
     double limiter_k;
+    int variant;  // 0 Anandhanarayanan et al., 1 Manish et al.
 };
 
 // Device work arrays of one flow state.
@@ -140,7 +141,8 @@ struct State {
     D4* qxl = nullptr;   // limited q-derivatives (limiter on)
     D4* qyl = nullptr;
     D4* R = nullptr;
-    D4* dU = nullptr;
+    D4* Rs = nullptr;    // forward-sweep right-hand side R - S (Manish variant)
+    D4* dU = nullptr;    // increment; kept between iterations (zero after a new U)
     D4* jv0 = nullptr;   // (rho, u1, u2, p) at the state the sweeps linearise about
     D4* jv1 = nullptr;   // (sqrt(beta), beta, 1/rho, 1/p)
     D4* jv2 = nullptr;   // (erf(Sx), exp(-Sx^2), erf(Sy), exp(-Sy^2))
@@ -186,6 +188,8 @@ hipError_t launch_soa_to_aos(const double* soa, D4* aos, int64_t n, hipStream_t 
 hipError_t launch_aos_to_soa(const D4* aos, double* soa, int64_t n, hipStream_t st);
 hipError_t launch_aosf_to_soa(const F4* aos, double* soa, int64_t n, hipStream_t st);
 hipError_t launch_clear_flags(int32_t* flags, hipStream_t st);
+// zero increment (both precisions) of points [p0, p0 + n): after a new U
+hipError_t clear_increment(State& s, int64_t p0, int64_t n);
 
 // Error reporting shared by the C-ABI source files: records msg for
 // lskum_last_error() and returns code.

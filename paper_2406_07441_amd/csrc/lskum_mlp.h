@@ -21,7 +21,7 @@ constexpr int kOffW4 = kOffB3 + kWidth;
 constexpr int kOffB4 = kOffW4 + kOut * kWidth;
 constexpr int kParams = kOffB4 + kOut;
 static_assert(kParams == 34308, "parameter count");
-constexpr int kChunk = 4096;  // rows per weight-gradient partial sum (multiple of 32)
+constexpr int kChunk = 256;   // rows per partial sum of the gradients (multiple of 32)
 constexpr int kRowAlign = 32; // workspace rows are padded to a multiple of this
 
 struct Net {
@@ -46,7 +46,7 @@ struct Net {
     float* se = nullptr;
     __bf16 *dZ3 = nullptr, *dZ2 = nullptr;
     float* dZ1 = nullptr;
-    float* part = nullptr;  // weight-gradient partials, [cap / kChunk][128][128]
+    float* part = nullptr;  // gradient partials, [cap / kChunk][128][128]
     double* d_loss = nullptr;
     int32_t* d_bad = nullptr;      // per component: 1 if the prediction is unusable
     double* d_res_fs = nullptr;    // per component free-stream residual (judge)

@@ -55,25 +55,154 @@ __device__ __forceinline__ f32x4 tile_mma(const __bf16* __restrict__ A, int64_t 
     return acc;
 }
 
-// Forward dense layer: Z = H W^T + b (H [M][128] bf16, W [128][128] bf16
-// [out][in]); writes Z (fp32) and bf16(GELU(Z)).  Grid: (M/16 * 8) waves.
-__global__ void __launch_bounds__(64) k_dense_fwd(int M, const __bf16* __restrict__ H,
-                                                  const __bf16* __restrict__ W,
-                                                  const float* __restrict__ bias,
-                                                  float* __restrict__ Z, __bf16* __restrict__ Hn) {
-    const int tile = blockIdx.x;
-    const int r0 = 16 * (tile >> 3), c0 = 16 * (tile & 7);
-    if (r0 >= M) return;
-    const f32x4 acc = tile_mma(H, kWidth, 1, W, 1, kWidth, r0, c0, 0, kWidth);
-    const int l = threadIdx.x;
-    const int c = c0 + (l & 15);
-    const float bc = bias[c];
+// Whole forward pass of 128 rows per workgroup (8 waves x 16 rows).  W2 and
+// W3 are staged in LDS with rows padded to kLdsW bf16 (a 16-byte operand read
+// by 16 lanes of different rows then hits distinct banks).  Layer 1 is
+// evaluated directly in the matrix-core operand layout (each lane computes the
+// 32 hidden units its A fragments hold); the 128 x 128 layers run on the
+// matrix cores, their outputs going back through a per-wave LDS tile to the
+// operand layout of the next layer; layer 4 sums each lane's 8 columns and
+// then across the 16 lanes of a row group with shuffles (fixed order).
+// TRAIN also writes what the backward pass reads (Xb, Z1-3, H1-3) and the
+// loss terms dY, se; otherwise Y.
+constexpr int kLdsW = kWidth + 8;
+constexpr int kFwdWaves = 8;
+
+template <bool TRAIN>
+__global__ void __launch_bounds__(64 * kFwdWaves) k_mlp_forward(
+    int M, int Mvalid, const float* __restrict__ X, const __bf16* __restrict__ W1,
+    const float* __restrict__ b1, const __bf16* __restrict__ W2, const float* __restrict__ b2,
+    const __bf16* __restrict__ W3, const float* __restrict__ b3, const __bf16* __restrict__ W4,
+    const float* __restrict__ b4, const float* __restrict__ T, float* __restrict__ Y,
+    __bf16* __restrict__ Xb, float* __restrict__ Z1, float* __restrict__ Z2,
+    float* __restrict__ Z3, __bf16* __restrict__ H1, __bf16* __restrict__ H2,
+    __bf16* __restrict__ H3, float* __restrict__ dY, float* __restrict__ se) {
+    __shared__ __attribute__((aligned(16))) __bf16 sW2[kWidth * kLdsW];
+    __shared__ __attribute__((aligned(16))) __bf16 sW3[kWidth * kLdsW];
+    __shared__ __attribute__((aligned(16))) __bf16 sH[kFwdWaves][16 * kLdsW];
+    // stage W2, W3 (16-byte chunks)
+    for (int ch = threadIdx.x; ch < kWidth * kWidth / 8; ch += blockDim.x) {
+        const int row = ch / (kWidth / 8), c8 = (ch % (kWidth / 8)) * 8;
+        *(bf16x8*)&sW2[row * kLdsW + c8] = *(const bf16x8*)&W2[row * kWidth + c8];
+        *(bf16x8*)&sW3[row * kLdsW + c8] = *(const bf16x8*)&W3[row * kWidth + c8];
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int row0 = (blockIdx.x * kFwdWaves + w) * 16;
+    if (row0 >= M) return;  // no barrier follows: the tile's work is wave-local
+    const int r = l & 15, g = l >> 4, kq = 8 * g;
+    const int64_t m = row0 + r;
+    __bf16* hs = sH[w];
+    // ---- layer 1 (5 -> 128) in the A-operand layout
+    float x[kIn];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int r = r0 + 4 * (l >> 4) + t;
-        const float z = acc[t] + bc;
-        Z[(int64_t)r * kWidth + c] = z;
-        Hn[(int64_t)r * kWidth + c] = (__bf16)gelu(z);
+    for (int f = 0; f < kIn; ++f) {
+        const __bf16 xb = (__bf16)(m < Mvalid ? X[m * kIn + f] : 0.0f);
+        x[f] = (float)xb;
+        if (TRAIN && g == 0) Xb[m * kIn + f] = xb;
+    }
+    bf16x8 a[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        float zz[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int n = 32 * s + kq + j;
+            float z = b1[n];
+#pragma unroll
+            for (int f = 0; f < kIn; ++f) z += x[f] * (float)W1[n * kIn + f];
+            zz[j] = z;
+            a[s][j] = (__bf16)gelu(z);
+        }
+        if (TRAIN) {
+            float* z1 = Z1 + m * kWidth + 32 * s + kq;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) z1[j] = zz[j];
+            *(bf16x8*)(H1 + m * kWidth + 32 * s + kq) = a[s];
+        }
+    }
+    // ---- layers 2 and 3 (128 -> 128) on the matrix cores
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+        const __bf16* sW = layer == 0 ? sW2 : sW3;
+        const float* bias = layer == 0 ? b2 : b3;
+        float* Zg = layer == 0 ? Z2 : Z3;
+        __bf16* Hg = layer == 0 ? H2 : H3;
+        f32x4 acc[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const bf16x8 b = *(const bf16x8*)&sW[(16 * c + r) * kLdsW + 32 * s + kq];
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[s], b, acc[c], 0, 0, 0);
+            }
+        }
+        // bias + GELU in the accumulator layout: lane holds rows 4g..4g+3 of column 16c + r
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int col = 16 * c + r;
+            const float bc = bias[col];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int rr = 4 * g + t;
+                const float z = acc[c][t] + bc;
+                const __bf16 h = (__bf16)gelu(z);
+                acc[c][t] = (float)h;  // keep the rounded activation for layer 4
+                hs[rr * kLdsW + col] = h;
+                if (TRAIN) {
+                    const int64_t mm = row0 + rr;
+                    Zg[mm * kWidth + col] = z;
+                    Hg[mm * kWidth + col] = h;
+                }
+            }
+        }
+        if (layer == 0) {
+            // back to the A-operand layout for layer 3 (wave-local tile; LDS
+            // operations of one wave complete in order)
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int s = 0; s < 4; ++s) a[s] = *(const bf16x8*)&hs[r * kLdsW + 32 * s + kq];
+        } else {
+            // ---- layer 4 (128 -> 4): lane partial sums over its 8 columns
+            float ysum[4][kOut];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int o = 0; o < kOut; ++o) {
+                    float sacc = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        sacc += acc[c][t] * (float)W4[o * kWidth + 16 * c + r];
+                    ysum[t][o] = sacc;
+                }
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int o = 0; o < kOut; ++o) ysum[t][o] += __shfl_xor(ysum[t][o], off, 64);
+            if (r < kOut) {
+                const int o = r;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int64_t mm = row0 + 4 * g + t;
+                    float yv = 0.0f;
+#pragma unroll
+                    for (int oo = 0; oo < kOut; ++oo)
+                        if (oo == o) yv = ysum[t][oo];
+                    yv += b4[o];
+                    if (TRAIN) {
+                        const float res = mm < Mvalid ? yv - T[mm * kOut + o] : 0.0f;
+                        dY[mm * kOut + o] = 2.0f * res / (4.0f * (float)Mvalid);
+                        se[mm * kOut + o] = res * res;
+                    } else if (mm < Mvalid) {
+                        Y[mm * kOut + o] = yv;
+                    }
+                }
+            }
+        }
     }
 }
 
@@ -119,47 +248,6 @@ __global__ void __launch_bounds__(64) k_dense_wgrad(int M, int mchunk, const __b
     for (int t = 0; t < 4; ++t) out[(r0 + 4 * (l >> 4) + t) * kWidth + c] = acc[t];
 }
 
-// Layer 1 (5 -> 128) on the vector units: Z1 = bf16(X) W1^T + b1.
-__global__ void __launch_bounds__(256) k_layer_in(int M, int Mvalid, const float* __restrict__ X,
-                                                  const __bf16* __restrict__ W1,
-                                                  const float* __restrict__ b1,
-                                                  __bf16* __restrict__ Xb, float* __restrict__ Z,
-                                                  __bf16* __restrict__ H) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (int64_t)M * kWidth) return;
-    const int m = (int)(g / kWidth), n = (int)(g % kWidth);
-    float z = b1[n];
-#pragma unroll
-    for (int k = 0; k < kIn; ++k) {
-        const __bf16 xb = (__bf16)(m < Mvalid ? X[(int64_t)m * kIn + k] : 0.0f);
-        if (n == 0) Xb[(int64_t)m * kIn + k] = xb;
-        z += (float)xb * (float)W1[n * kIn + k];
-    }
-    Z[g] = z;
-    H[g] = (__bf16)gelu(z);
-}
-
-// Layer 4 (128 -> 4): Y = H3 W4^T + b4; with targets, dY = 2 (Y - T) / (4 Mvalid)
-// (0 on padding rows) and per-row squared errors for the loss.
-__global__ void __launch_bounds__(256) k_layer_out(int M, int Mvalid, const __bf16* __restrict__ H,
-                                                   const __bf16* __restrict__ W4,
-                                                   const float* __restrict__ b4,
-                                                   const float* __restrict__ T,
-                                                   float* __restrict__ Y, float* __restrict__ dY,
-                                                   float* __restrict__ se) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (int64_t)M * kOut) return;
-    const int m = (int)(g / kOut), o = (int)(g % kOut);
-    float y = b4[o];
-    for (int k = 0; k < kWidth; ++k) y += (float)H[(int64_t)m * kWidth + k] * (float)W4[o * kWidth + k];
-    if (Y && m < Mvalid) Y[(int64_t)m * kOut + o] = y;
-    if (T) {
-        const float r = m < Mvalid ? y - T[(int64_t)m * kOut + o] : 0.0f;
-        dY[g] = 2.0f * r / (4.0f * (float)Mvalid);
-        se[g] = r * r;
-    }
-}
-
 // Layer 4 backward: dZ3 = bf16((dY W4) * GELU'(Z3)).
 __global__ void __launch_bounds__(256) k_layer_out_bwd(int M, const float* __restrict__ dY,
                                                        const __bf16* __restrict__ W4,
@@ -174,22 +262,24 @@ __global__ void __launch_bounds__(256) k_layer_out_bwd(int M, const float* __res
     dZ3[g] = (__bf16)(s * gelu_prime(Z3[g]));
 }
 
-// Sums of small products over the points, one thread per output, points in
-// fixed order: out[r][c] = sum_m P[m][r] Q[m][c] (Q == nullptr: sum_m P[m][r]).
-// P is fp32 or bf16 (template), Q bf16 or fp32 (template).
+// Partial sums of small products over one chunk of rows (grid.y = chunk),
+// one thread per output, rows in fixed order:
+// part[chunk][r][c] = sum_{m in chunk} P[m][r] Q[m][c] (Q == nullptr: P[m][r]).
 template <class TP, class TQ>
-__global__ void __launch_bounds__(256) k_colsum(int M, int R, int Cn, const TP* __restrict__ P,
-                                               int ldp, const TQ* __restrict__ Q, int ldq,
-                                               float* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_colsum(int M, int mchunk, int R, int Cn,
+                                               const TP* __restrict__ P, int ldp,
+                                               const TQ* __restrict__ Q, int ldq,
+                                               float* __restrict__ part) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= R * Cn) return;
     const int r = g / Cn, c = g % Cn;
+    const int m0 = blockIdx.y * mchunk, m1 = min(M, m0 + mchunk);
     float s = 0.0f;
-    for (int m = 0; m < M; ++m) {
+    for (int m = m0; m < m1; ++m) {
         const float pv = (float)P[(int64_t)m * ldp + r];
         s += Q ? pv * (float)Q[(int64_t)m * ldq + c] : pv;
     }
-    out[g] = s;
+    part[(int64_t)blockIdx.y * R * Cn + g] = s;
 }
 
 // out[k] = sum_ch P[ch][k] (fixed order).
@@ -202,15 +292,20 @@ __global__ void __launch_bounds__(256) k_sum_chunks(int n, int nch, const float*
     out[k] = s;
 }
 
-__global__ void __launch_bounds__(256) k_sum_all(int n, const float* __restrict__ v,
-                                                 double* __restrict__ out) {
-    __shared__ double red[4];
+// One block of 1024 threads; fixed-order partial sums then a fixed tree.
+__global__ void __launch_bounds__(1024) k_sum_all(int n, const float* __restrict__ v,
+                                                  double* __restrict__ out) {
+    __shared__ double red[16];
     double s = 0.0;
     for (int k = threadIdx.x; k < n; k += blockDim.x) s += v[k];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) out[0] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += red[w];
+        out[0] = t;
+    }
 }
 
 // bf16 copies of the weights (and the transposes are not needed: the MFMA
@@ -373,57 +468,68 @@ hipError_t refresh_weights(Net& net) {
 hipError_t forward(Net& net, const float* X, int M, int Mvalid, const float* T, float* Y) {
     hipStream_t st = net.stream;
     const float* th = net.theta;
-    hipLaunchKernelGGL(k_layer_in, dim3(nblk((int64_t)M * kWidth, 256)), dim3(256), 0, st, M,
-                       Mvalid, X, net.W1b, th + kOffB1, net.Xb, net.Z1, net.H1);
-    hipLaunchKernelGGL(k_dense_fwd, dim3((M / 16) * 8), dim3(64), 0, st, M, net.H1, net.W2b,
-                       th + kOffB2, net.Z2, net.H2);
-    hipLaunchKernelGGL(k_dense_fwd, dim3((M / 16) * 8), dim3(64), 0, st, M, net.H2, net.W3b,
-                       th + kOffB3, net.Z3, net.H3);
-    hipLaunchKernelGGL(k_layer_out, dim3(nblk((int64_t)M * kOut, 256)), dim3(256), 0, st, M,
-                       Mvalid, net.H3, net.W4b, th + kOffB4, T, Y, net.dY, net.se);
+    const dim3 grid(nblk(M, 16 * kFwdWaves)), block(64 * kFwdWaves);
+    if (T)
+        hipLaunchKernelGGL(k_mlp_forward<true>, grid, block, 0, st, M, Mvalid, X, net.W1b,
+                           th + kOffB1, net.W2b, th + kOffB2, net.W3b, th + kOffB3, net.W4b,
+                           th + kOffB4, T, (float*)nullptr, net.Xb, net.Z1, net.Z2, net.Z3,
+                           net.H1, net.H2, net.H3, net.dY, net.se);
+    else
+        hipLaunchKernelGGL(k_mlp_forward<false>, grid, block, 0, st, M, Mvalid, X, net.W1b,
+                           th + kOffB1, net.W2b, th + kOffB2, net.W3b, th + kOffB3, net.W4b,
+                           th + kOffB4, (const float*)nullptr, Y, net.Xb, net.Z1, net.Z2,
+                           net.Z3, net.H1, net.H2, net.H3, net.dY, net.se);
     return hipGetLastError();
 }
 
 // Backward after a forward with targets: gradient (flat, fp32) into net.grad.
+// Two-stage sum over rows: chunk partials, then a fixed-order sum of the chunks.
+template <class TP, class TQ>
+static void colsum(Net& net, int M, int R, int Cn, const TP* P, int ldp, const TQ* Q, int ldq,
+                   float* out) {
+    constexpr int kRows = 64;  // rows per thread in the first stage
+    const int nch = (M + kRows - 1) / kRows;
+    hipLaunchKernelGGL((k_colsum<TP, TQ>), dim3(nblk(R * Cn, 256), nch), dim3(256), 0, net.stream,
+                       M, kRows, R, Cn, P, ldp, Q, ldq, net.part);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(R * Cn, 256)), dim3(256), 0, net.stream, R * Cn,
+                       nch, net.part, out);
+}
+
+static void wgrad(Net& net, int M, const __bf16* dZ, const __bf16* H, float* out) {
+    const int nch = (M + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL(k_dense_wgrad, dim3(64, nch), dim3(64), 0, net.stream, M, kChunk, dZ, H,
+                       net.part);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(kWidth * kWidth, 256)), dim3(256), 0, net.stream,
+                       kWidth * kWidth, nch, net.part, out);
+}
+
 hipError_t backward(Net& net, int M) {
     hipStream_t st = net.stream;
     float* g = net.grad;
+    const float* none = nullptr;
     // layer 4
-    hipLaunchKernelGGL((k_colsum<float, __bf16>), dim3(nblk(kOut * kWidth, 256)), dim3(256), 0, st,
-                       M, kOut, kWidth, net.dY, kOut, net.H3, kWidth, g + kOffW4);
-    hipLaunchKernelGGL((k_colsum<float, float>), dim3(1), dim3(256), 0, st, M, kOut, 1, net.dY,
-                       kOut, (const float*)nullptr, 0, g + kOffB4);
+    colsum(net, M, kOut, kWidth, net.dY, kOut, net.H3, kWidth, g + kOffW4);
+    colsum(net, M, kOut, 1, net.dY, kOut, none, 0, g + kOffB4);
     hipLaunchKernelGGL(k_layer_out_bwd, dim3(nblk((int64_t)M * kWidth, 256)), dim3(256), 0, st, M,
                        net.dY, net.W4b, net.Z3, net.dZ3);
     // layer 3
-    const int nch = (M + kChunk - 1) / kChunk;
-    hipLaunchKernelGGL(k_dense_wgrad, dim3(64, nch), dim3(64), 0, st, M, kChunk, net.dZ3, net.H2,
-                       net.part);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(kWidth * kWidth, 256)), dim3(256), 0, st,
-                       kWidth * kWidth, nch, net.part, g + kOffW3);
-    hipLaunchKernelGGL((k_colsum<__bf16, float>), dim3(1), dim3(256), 0, st, M, kWidth, 1,
-                       net.dZ3, kWidth, (const float*)nullptr, 0, g + kOffB3);
+    wgrad(net, M, net.dZ3, net.H2, g + kOffW3);
+    colsum(net, M, kWidth, 1, net.dZ3, kWidth, none, 0, g + kOffB3);
     hipLaunchKernelGGL(k_dense_bwd_data<true>, dim3((M / 16) * 8), dim3(64), 0, st, M, net.dZ3,
                        net.W3b, net.Z2, net.dZ2, (float*)nullptr);
     // layer 2
-    hipLaunchKernelGGL(k_dense_wgrad, dim3(64, nch), dim3(64), 0, st, M, kChunk, net.dZ2, net.H1,
-                       net.part);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(kWidth * kWidth, 256)), dim3(256), 0, st,
-                       kWidth * kWidth, nch, net.part, g + kOffW2);
-    hipLaunchKernelGGL((k_colsum<__bf16, float>), dim3(1), dim3(256), 0, st, M, kWidth, 1,
-                       net.dZ2, kWidth, (const float*)nullptr, 0, g + kOffB2);
+    wgrad(net, M, net.dZ2, net.H1, g + kOffW2);
+    colsum(net, M, kWidth, 1, net.dZ2, kWidth, none, 0, g + kOffB2);
     hipLaunchKernelGGL(k_dense_bwd_data<false>, dim3((M / 16) * 8), dim3(64), 0, st, M, net.dZ2,
                        net.W2b, net.Z1, (__bf16*)nullptr, net.dZ1);
     // layer 1
-    hipLaunchKernelGGL((k_colsum<float, __bf16>), dim3(nblk(kWidth * kIn, 256)), dim3(256), 0, st,
-                       M, kWidth, kIn, net.dZ1, kWidth, net.Xb, kIn, g + kOffW1);
-    hipLaunchKernelGGL((k_colsum<float, float>), dim3(1), dim3(256), 0, st, M, kWidth, 1, net.dZ1,
-                       kWidth, (const float*)nullptr, 0, g + kOffB1);
+    colsum(net, M, kWidth, kIn, net.dZ1, kWidth, net.Xb, kIn, g + kOffW1);
+    colsum(net, M, kWidth, 1, net.dZ1, kWidth, none, 0, g + kOffB1);
     return hipGetLastError();
 }
 
 hipError_t loss(Net& net, int M, double* d_out) {
-    hipLaunchKernelGGL(k_sum_all, dim3(1), dim3(256), 0, net.stream, M * kOut, net.se, d_out);
+    hipLaunchKernelGGL(k_sum_all, dim3(1), dim3(1024), 0, net.stream, M * kOut, net.se, d_out);
     return hipGetLastError();
 }
 

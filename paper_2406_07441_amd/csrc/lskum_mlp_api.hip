@@ -153,6 +153,7 @@ int warm_start(M::Net& n, lskum::State& s, int32_t* fallback, double* res_warm) 
     HIPCHK(lskum::launch_reset_components(s));
     HIPCHK(lskum::launch_clear_flags(s.flags, s.stream));
     HIPCHK(lskum::launch_q_from_U(s));
+    HIPCHK(lskum::clear_increment(s, 0, c.n));
     std::vector<int32_t> bad(nc);
     std::vector<double> res(nc);
     HIPCHK(hipMemcpyAsync(bad.data(), n.d_bad, nc * sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -269,8 +270,11 @@ int lskum_mlp_set_params(lskum_mlp* h, const float* theta, int on_device) {
 int lskum_mlp_forward(lskum_mlp* h, int64_t m, const float* X, float* Y) {
     if (!h || m < 0 || (m > 0 && (!X || !Y))) return api_error(LSKUM_ERR_ARG, "invalid argument");
     M::Net& n = h->n;
-    for (int64_t r0 = 0; r0 < m; r0 += n.capacity) {
-        const int64_t k = std::min<int64_t>(n.capacity, m - r0);
+    // inference reads X and writes Y directly (no workspace): one launch per
+    // 2^30 rows
+    const int64_t step = (int64_t)1 << 30;
+    for (int64_t r0 = 0; r0 < m; r0 += step) {
+        const int64_t k = std::min<int64_t>(step, m - r0);
         if (int r = run_forward(n, X + r0 * M::kIn, k, nullptr, Y + r0 * M::kOut)) return r;
     }
     HIPCHK(hipStreamSynchronize(n.stream));

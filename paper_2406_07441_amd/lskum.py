@@ -22,6 +22,7 @@ OK, ERR_ARG, ERR_CONNECTIVITY, ERR_DEGENERATE, ERR_COLOURING = 0, -1, -2, -3, -4
 ERR_NONPHYSICAL, ERR_NOT_CONVERGED, ERR_HIP, ERR_OOM = -5, -6, -7, -8
 JVP_EXACT, JVP_FLUXDIFF = 0, 1
 FP64, MIXED = 0, 1
+ANANDH, MANISH = 0, 1
 
 
 class LskumError(RuntimeError):
@@ -34,7 +35,8 @@ class Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("inner_iters", C.c_int32),
                 ("jvp_mode", C.c_int32), ("precision", C.c_int32), ("check_every", C.c_int32),
                 ("tol_rel", C.c_double), ("max_iters", C.c_int32), ("sweep_lanes", C.c_int32),
-                ("residual_lanes", C.c_int32), ("limiter", C.c_int32), ("limiter_k", C.c_double)]
+                ("residual_lanes", C.c_int32), ("limiter", C.c_int32), ("limiter_k", C.c_double),
+                ("variant", C.c_int32)]
 
 
 class Report(C.Structure):

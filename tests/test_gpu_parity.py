@@ -229,3 +229,52 @@ def test_mixed_precision_error_against_fp64_oracle(lk, cfg1):
         e = rel(st.get_dU(), dUo)
         print(f"mixed dU it={it} rel err vs fp64 oracle {e:.3e}")
         assert e < 1e-4
+
+
+@pytest.mark.parametrize("jvp_mode", [0, 1])
+def test_manish_variant_iterations_parity(lk, cfg1, jvp_mode):
+    """Manish et al. variant: diagonal with rho(A)/2 and the lagged term S on
+    the forward right-hand side; the increment carried from one step to the
+    next on both sides (zero after a new U)."""
+    kw = dict(cfl=5.0, inner_iters=1, jvp_mode=jvp_mode)
+    o = O.Oracle(cfg1.cloud, mach=0.63, aoa_deg=2.0, variant=O.MANISH, **kw)
+    st = lk.State(cfg1.gc, 0.63, 2.0, lk.default_params(variant=lk.MANISH, **kw))
+    tol = TOL if jvp_mode == 0 else 1e-10
+    U, dU = o.free_stream(), None
+    for it in range(4):
+        U, R, dU, res = o.iteration(U, dU)
+        res_gpu = st.step()
+        e = rel(st.get_dU(), dU)
+        print(f"manish mode={jvp_mode} it={it}: dU rel err {e:.3e}")
+        assert e < tol and abs(res_gpu - res) <= TOL * res
+    assert rel(st.get_U(), U) < 1e-13
+    # a new state restarts the lag: S = 0 on its first step
+    st.set_U(U)
+    st.step()
+    _, _, dU0, _ = o.iteration(U)
+    assert rel(st.get_dU(), dU0) < tol
+    st.close()
+
+
+def test_manish_variant_mixed_and_batch(lk, cfg1):
+    kw = dict(cfl=5.0, inner_iters=1)
+    o = O.Oracle(cfg1.cloud, mach=0.63, aoa_deg=2.0, variant=O.MANISH, **kw)
+    U, dU = o.free_stream(), None
+    for _ in range(3):
+        U, _, dU, _ = o.iteration(U, dU)
+    st = lk.State(cfg1.gc, 0.63, 2.0, lk.default_params(variant=lk.MANISH, precision=lk.MIXED,
+                                                         **kw))
+    for _ in range(3):
+        st.step()
+    assert rel(st.get_dU(), dU) < 1e-4
+    st.close()
+    # a batch of two conditions equals the single-condition steps bitwise
+    prm = lk.default_params(variant=lk.MANISH, check_every=3, max_iters=3, tol_rel=0.0, **kw)
+    b = lk.Batch([cfg1.gc], [0, 0], [0.63, 0.5], [2.0, -1.0], prm)
+    b.solve()
+    for k, (m, a) in enumerate(((0.63, 2.0), (0.5, -1.0))):
+        s1 = lk.State(cfg1.gc, m, a, prm)
+        s1.solve()
+        assert np.array_equal(b.get_U(k), s1.get_U())
+        s1.close()
+    b.close()
