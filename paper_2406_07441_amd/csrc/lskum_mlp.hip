@@ -282,14 +282,20 @@ __global__ void __launch_bounds__(256) k_colsum(int M, int mchunk, int R, int Cn
     part[(int64_t)blockIdx.y * R * Cn + g] = s;
 }
 
-// out[k] = sum_ch P[ch][k] (fixed order).
+// out[k] = sum_ch P[ch][k]: a block covers 64 outputs with 4 thread groups,
+// group g summing chunks g, g + 4, ... in order; the four group sums are then
+// added in group order (a fixed order throughout).
 __global__ void __launch_bounds__(256) k_sum_chunks(int n, int nch, const float* __restrict__ P,
                                                     float* __restrict__ out) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+    __shared__ float part[4][64];
+    const int j = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + j;
     float s = 0.0f;
-    for (int c = 0; c < nch; ++c) s += P[(int64_t)c * n + k];
-    out[k] = s;
+    if (k < n)
+        for (int c = g; c < nch; c += 4) s += P[(int64_t)c * n + k];
+    part[g][j] = s;
+    __syncthreads();
+    if (g == 0 && k < n) out[k] = ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j];
 }
 
 // One block of 1024 threads; fixed-order partial sums then a fixed tree.
@@ -491,7 +497,7 @@ static void colsum(Net& net, int M, int R, int Cn, const TP* P, int ldp, const T
     const int nch = (M + kRows - 1) / kRows;
     hipLaunchKernelGGL((k_colsum<TP, TQ>), dim3(nblk(R * Cn, 256), nch), dim3(256), 0, net.stream,
                        M, kRows, R, Cn, P, ldp, Q, ldq, net.part);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(R * Cn, 256)), dim3(256), 0, net.stream, R * Cn,
+    hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(R * Cn, 64)), dim3(256), 0, net.stream, R * Cn,
                        nch, net.part, out);
 }
 
@@ -499,7 +505,7 @@ static void wgrad(Net& net, int M, const __bf16* dZ, const __bf16* H, float* out
     const int nch = (M + kChunk - 1) / kChunk;
     hipLaunchKernelGGL(k_dense_wgrad, dim3(64, nch), dim3(64), 0, net.stream, M, kChunk, dZ, H,
                        net.part);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(kWidth * kWidth, 256)), dim3(256), 0, net.stream,
+    hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(kWidth * kWidth, 64)), dim3(256), 0, net.stream,
                        kWidth * kWidth, nch, net.part, out);
 }
 
