@@ -84,3 +84,33 @@ def test_batch_set_U_and_failed_condition_retires(lk, setup):
     reps, _ = bat.solve()
     assert reps[0]["status"] == lk.ERR_NOT_CONVERGED and reps[0]["iters"] == 20
     assert reps[1]["status"] == lk.ERR_NONPHYSICAL and reps[1]["iters"] < 20
+
+
+def test_batch_benchmark_workload_sampled_conditions(lk):
+    """The 64-condition benchmark batch (8 clouds of 149k-592k points, 26.5 M
+    points, limiter on): one iteration of the two conditions on the two
+    smallest clouds against the oracle, FP64 (1e-11) and in the benchmark's
+    mixed precision (1e-4)."""
+    import oracle as O
+    clouds = cg.batch_clouds()
+    mach, aoa = cg.batch_conditions()
+    gcs = [lk.Cloud(c) for c in clouds]
+    order = np.argsort([c.n for c in clouds])[:2]
+    picks = [int(c) for c in order]            # condition k uses cloud k % 8: k = c for k < 8
+    kw = dict(cfl=100.0, inner_iters=1, limiter=1, limiter_k=5.0)
+    ref = {}
+    for k in picks:
+        o = O.Oracle(clouds[k], mach=float(mach[k]), aoa_deg=float(aoa[k]), **kw)
+        U0 = o.free_stream()
+        _, _, dU, _ = o.iteration(U0)
+        ref[k] = (U0, dU)
+    for prec, tol in ((lk.FP64, 1e-11), (lk.MIXED, 1e-4)):
+        b = lk.Batch(gcs, np.arange(64) % 8, mach, aoa, lk.default_params(precision=prec, **kw))
+        b.step_timed()
+        for k in picks:
+            U0, dU = ref[k]
+            got = b.get_U(k) - U0
+            e = float(np.abs(got - dU).max() / np.abs(dU).max())
+            print(f"batch condition {k} (cloud {clouds[k].n} points) precision={prec}: {e:.3e}")
+            assert e < tol
+        b.close()
