@@ -73,6 +73,7 @@ def lib():
             "ora_residual_norm": (D, [P, P]),
             "ora_iteration": (I32, [P, P, P, P, P, P]),
             "ora_unsplit_jvp": (None, [P, P, D, D, P, P]),
+            "ora_explicit_iteration": (I32, [P, P, P, P, P]),
             "ora_manish_source": (None, [P, P, P, P, P]),
             "ora_solve": (I32, [P, P, P, I32, D, P]),
             "ora_forces": (I32, [P, P, P, P, P]),
@@ -252,6 +253,17 @@ class Oracle:
         if st:
             raise RuntimeError(f"iteration status {st}")
         return U, R, dU, float(res.value)
+
+    def explicit_iteration(self, U):
+        """One explicit iteration U - dt R; returns (U_new, R, res)."""
+        U = _f64(U).copy()
+        R = np.empty((4, self.n))
+        res = C.c_double(0.0)
+        st = lib().ora_explicit_iteration(C.byref(self.c), C.byref(self.prm), _p(U), _p(R),
+                                          C.byref(res))
+        if st:
+            raise RuntimeError(f"explicit iteration status {st}")
+        return U, R, float(res.value)
 
     def solve(self, U, max_iters, tol_abs=0.0):
         """Iterate in place; returns (U, iterations, residual history)."""

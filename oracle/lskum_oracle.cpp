@@ -854,6 +854,28 @@ int32_t ora_iteration(const ora_cloud* oc, const ora_params* prm, double* U, dou
     return st;
 }
 
+// One explicit iteration (the paper's explicit LSKUM solver, Section 5): the
+// semi-discrete equation dU/dt = -R (eq. 19 without the implicit operator) with
+// the first-order forward difference in time, U <- U - dt R, dt the same local
+// time step as the implicit scheme (the CFL number is the caller's).  Outer
+// points keep the free stream (R = 0); wall points keep tangency (R has no
+// normal-momentum component).  Returns 0, ERR_NONPHYS or ERR_DEGEN.
+int32_t ora_explicit_iteration(const ora_cloud* oc, const ora_params* prm, double* U,
+                               double* R_out, double* res) {
+    Cloud c = to_cloud(oc);
+    Params P = to_params(prm);
+    std::vector<double> R(4 * c.n), dt(c.n), D(c.n);
+    int st = ora_residual(oc, prm, U, R.data(), res, nullptr);
+    if (st) return st;
+    timestep_diag(c, P, U, dt.data(), D.data());
+    std::vector<double> dU(4 * c.n);
+    for (int64_t p = 0; p < c.n; ++p)
+        for (int v = 0; v < 4; ++v) dU[v * c.n + p] = -dt[p] * R[v * c.n + p];
+    st = state_update(c, P, U, dU.data());
+    if (R_out) std::memcpy(R_out, R.data(), sizeof(double) * 4 * c.n);
+    return st;
+}
+
 // Runs up to max_iters iterations from U, stopping when res <= tol_abs.
 // history (optional, max_iters entries) receives res per iteration.
 // Returns the number of iterations run, or a negative status.
