@@ -41,7 +41,8 @@ class _Cloud(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("mach", C.c_double),
                 ("aoa_deg", C.c_double), ("inner_iters", C.c_int32), ("jvp_mode", C.c_int32),
-                ("limiter", C.c_int32), ("variant", C.c_int32), ("limiter_k", C.c_double)]
+                ("limiter", C.c_int32), ("variant", C.c_int32), ("limiter_k", C.c_double),
+                ("order", C.c_int32), ("pad2", C.c_int32)]
 
 
 _lib = None
@@ -109,11 +110,13 @@ def split_flux(U, d, s, gamma=GAMMA):
 
 
 ANANDH, MANISH = 0, 1
+COLOUR_ORDER, WALL_FIRST = 0, 1
 
 
 def params(mach=0.63, aoa_deg=2.0, cfl=100.0, inner_iters=1, jvp_mode=0, gamma=GAMMA, limiter=0,
-           limiter_k=5.0, variant=ANANDH):
-    return _Params(gamma, cfl, mach, aoa_deg, inner_iters, jvp_mode, limiter, variant, limiter_k)
+           limiter_k=5.0, variant=ANANDH, order=COLOUR_ORDER):
+    return _Params(gamma, cfl, mach, aoa_deg, inner_iters, jvp_mode, limiter, variant, limiter_k,
+                   order, 0)
 
 
 def unsplit_jvp(U, dU, d, jvp_mode=0, gamma=GAMMA):
@@ -153,7 +156,8 @@ class Oracle:
     """Oracle bound to one cloud and one flow condition."""
 
     def __init__(self, cloud, mach=0.63, aoa_deg=2.0, cfl=100.0, inner_iters=1, jvp_mode=0,
-                 gamma=GAMMA, colours=None, limiter=0, limiter_k=5.0, variant=ANANDH):
+                 gamma=GAMMA, colours=None, limiter=0, limiter_k=5.0, variant=ANANDH,
+                 order=COLOUR_ORDER):
         self.cloud = cloud
         self._keep = [_f64(cloud.x), _f64(cloud.y), _f64(cloud.tx), _f64(cloud.ty),
                       np.ascontiguousarray(cloud.type, dtype=np.int8),
@@ -169,7 +173,7 @@ class Oracle:
         self.c = _Cloud(cloud.n, _p(k[0]), _p(k[1]), _p(k[2]), _p(k[3]), _p(k[4]), _p(k[5]),
                         _p(k[6]), _p(col), nc)
         self.prm = params(mach, aoa_deg, cfl, inner_iters, jvp_mode, gamma, limiter, limiter_k,
-                          variant)
+                          variant, order)
         self.n = cloud.n
 
     # -- state -------------------------------------------------------------

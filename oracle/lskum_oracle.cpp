@@ -172,6 +172,7 @@ struct Params {
     int32_t limiter;                // 0 none (the paper), 1 Venkatakrishnan on q~
     double limiter_k;
     int32_t variant;                // 0 Anandhanarayanan et al., 1 Manish et al.
+    int32_t order;                  // 0 colour order (Algorithm 6), 1 wall first (Algorithm 5)
 };
 
 enum { OK = 0, ERR_ARG = -1, ERR_CONN = -2, ERR_DEGEN = -3, ERR_COLOUR = -4, ERR_NONPHYS = -5 };
@@ -556,7 +557,8 @@ void manish_source(const Cloud& c, const Params& P, const double* U, const doubl
 
 // LUSGS(): forward and backward sweeps of eq. (27) in colour order
 // (Algorithm 6): colours ascending for the forward sweep, descending for the
-// backward sweep; within a colour the points are independent.
+// backward sweep; within a colour the points are independent.  Order 1 is
+// Algorithm 5 (wall points first; see the end of the function).
 //   forward:  dU*_0 = -( R_0 + sum_k sum_{i in N_k, col(i) < col(0)} w_i A_k(U_i) dU*_i ) / D_0
 //   backward: dU_0  = dU*_0 - ( sum_k sum_{i in N_k, col(i) > col(0)} w_i A_k(U_i) dU_i ) / D_0
 // The products A_k(U_i) dU_i are the split-flux Jacobian products at the
@@ -602,10 +604,27 @@ void lusgs(const Cloud& c, const Params& P, const double* U, const double* R, co
         if (c.type[p] == 0) project_out_normal(c, p, out);
         for (int v = 0; v < 4; ++v) dU[v * c.n + p] = out[v];
     };
-    for (int col = 0; col < c.ncolour; ++col)
-        for (int64_t p : by_colour[col]) sweep_point(p, true);
-    for (int col = c.ncolour - 1; col >= 0; --col)
-        for (int64_t p : by_colour[col]) sweep_point(p, false);
+    if (P.order == 0) {
+        for (int col = 0; col < c.ncolour; ++col)
+            for (int64_t p : by_colour[col]) sweep_point(p, true);
+        for (int col = c.ncolour - 1; col >= 0; --col)
+            for (int64_t p : by_colour[col]) sweep_point(p, false);
+        return;
+    }
+    // Algorithm 5: the same per-point sweeps, grouped into wall, interior and
+    // outer points; each sweep visits the groups in that order, the colours
+    // ascending (forward) or descending (backward) within a group.  A point
+    // still sums over its lower- (upper-) colour neighbours and reads whatever
+    // the shared increment array holds for them at that moment.
+    const int8_t groups[3] = {0, 1, 2};
+    for (int8_t g : groups)
+        for (int col = 0; col < c.ncolour; ++col)
+            for (int64_t p : by_colour[col])
+                if (c.type[p] == g) sweep_point(p, true);
+    for (int8_t g : groups)
+        for (int col = c.ncolour - 1; col >= 0; --col)
+            for (int64_t p : by_colour[col])
+                if (c.type[p] == g) sweep_point(p, false);
 }
 
 // state_update(): U <- U + dU (Section 3, definition of dU).
@@ -654,14 +673,15 @@ typedef struct {
     int32_t inner_iters, jvp_mode;
     int32_t limiter, variant;
     double limiter_k;
+    int32_t order, pad2;
 } ora_params;
 
 static Cloud to_cloud(const ora_cloud* c) {
     return Cloud{c->n, c->x, c->y, c->tx, c->ty, c->type, c->off, c->idx, c->colour, c->ncolour};
 }
 static Params to_params(const ora_params* p) {
-    return Params{p->gamma,       p->cfl,      p->mach,    p->aoa_deg, p->inner_iters,
-                  p->jvp_mode,    p->limiter,  p->limiter_k, p->variant};
+    return Params{p->gamma,    p->cfl,     p->mach,      p->aoa_deg, p->inner_iters,
+                  p->jvp_mode, p->limiter, p->limiter_k, p->variant, p->order};
 }
 
 // Point colouring, Algorithm 4: colour(first point) = first colour; then for

@@ -278,3 +278,83 @@ def test_limiter_keeps_linear_fields_and_clips_extrema():
         lo = min(q[0, nb].min(), q[0, p])
         hi = max(q[0, nb].max(), q[0, p])
         assert np.all(rec <= hi + 1e-9) and np.all(rec >= lo - 1e-9)
+
+
+def _dense_wall_first(o, U, R, D):
+    """Algorithm 5 as a dense solve.  Forward: Gauss-Seidel over the
+    processing order (groups wall, interior, outer; colours ascending) with
+    only lower-colour neighbours already processed contributing (the others
+    still hold the zero of the sweep's start): (D + P L') dU* = -P R.
+    Backward (same group order, colours descending): an upper-colour
+    neighbour contributes its final dU if processed before, else its dU*:
+    (D + P U1) dU = (D - P U2) dU*."""
+    c = o.cloud
+    n = c.n
+    act = np.where(c.type != cg.OUTER)[0]
+    pos = -np.ones(n, dtype=int)
+    pos[act] = np.arange(len(act))
+    m = len(act)
+    col = o.colours
+    fwd = {p: (int(c.type[p]), int(col[p])) for p in range(n)}
+    bwd = {p: (int(c.type[p]), -int(col[p])) for p in range(n)}
+    L, U1, U2 = (np.zeros((4 * m, 4 * m)) for _ in range(3))
+    eye = np.eye(4)
+    for p in act:
+        for k, (d, s) in enumerate(o.split_dirs(p)):
+            nb, w, _ = o.split_stencil(p, k)
+            for i, wi in zip(nb, w):
+                if c.type[i] == cg.OUTER:
+                    continue
+                A = np.stack([O.flux_jvp(U[:, i], eye[j], d, s) for j in range(4)], axis=1)
+                if col[i] < col[p]:
+                    if fwd[i] < fwd[p]:
+                        blk = L
+                    else:
+                        continue
+                else:
+                    blk = U1 if bwd[i] < bwd[p] else U2
+                blk[4 * pos[p]:4 * pos[p] + 4, 4 * pos[i]:4 * pos[i] + 4] += wi * A
+    Pi = np.eye(4 * m)
+    for p in act:
+        if c.type[p] == cg.WALL:
+            nvec = np.array([0.0, -c.ty[p], c.tx[p], 0.0])
+            Pi[4 * pos[p]:4 * pos[p] + 4, 4 * pos[p]:4 * pos[p] + 4] = eye - np.outer(nvec, nvec)
+    Dm = np.kron(np.diag(D[act]), eye)
+    r = R[:, act].T.reshape(-1)
+    star = np.linalg.solve(Dm + Pi @ L, -(Pi @ r))
+    dU = np.linalg.solve(Dm + Pi @ U1, (Dm - Pi @ U2) @ star)
+    out = np.zeros((4, n))
+    out[:, act] = dU.reshape(m, 4).T
+    return out
+
+
+def test_wall_first_sweeps_equal_dense_solve():
+    c = cg.box(7, 6, h=0.2, wall_bottom=True)
+    o = O.Oracle(c, mach=0.6, aoa_deg=0.0, cfl=20.0, order=O.WALL_FIRST)
+    U = o.free_stream()
+    rng = np.random.default_rng(1)
+    U = U * (1 + 0.05 * rng.standard_normal(U.shape) * (c.type != cg.OUTER))
+    U[2, c.type == cg.WALL] = 0.0
+    R, _ = o.residual(U)
+    dt, D = o.timestep_diag(U)
+    dU = o.lusgs(U, R, D)
+    ref = _dense_wall_first(o, U, R, D)
+    assert np.abs(dU - ref).max() < 1e-12 * np.abs(ref).max()
+    # and it differs from the colour order (the wall points see stale neighbours)
+    o0 = O.Oracle(c, mach=0.6, aoa_deg=0.0, cfl=20.0)
+    assert np.abs(o0.lusgs(U, R, D) - dU).max() > 1e-6 * np.abs(dU).max()
+
+
+def test_wall_first_without_walls_is_colour_order():
+    # interior before outer points, whose increment is always 0: the same result
+    c = cg.box(9, 8, h=0.13)
+    rng = np.random.default_rng(4)
+    for order in (O.COLOUR_ORDER, O.WALL_FIRST):
+        o = O.Oracle(c, mach=0.5, aoa_deg=20.0, cfl=20.0, order=order)
+        U = o.free_stream() * (1 + 0.03 * rng.standard_normal((4, c.n)) * (c.type != cg.OUTER))
+        rng = np.random.default_rng(4)
+        if order == O.COLOUR_ORDER:
+            ref = o.iteration(U)
+        else:
+            got = o.iteration(U)
+    assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[2], got[2])
