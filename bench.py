@@ -110,6 +110,23 @@ def time_to_tol(lk, gc, max_iters, **kw):
     return out
 
 
+def explicit_vs_implicit(lk, gc, iters):
+    """The paper's explicit solver (U - dt R, CFL 0.4) against the implicit one
+    (CFL 100) on the benchmark workload: time per iteration and residual drop
+    after the same number of iterations."""
+    out = {}
+    for name, kw in (("implicit_fp64", dict()), ("explicit_fp64", dict(scheme=lk.EXPLICIT,
+                                                                        cfl=0.4))):
+        prm = params(lk, check_every=100, tol_rel=0.0, max_iters=iters, **kw)
+        st = lk.State(gc, MACH, AOA, prm)
+        rep = st.solve()
+        out[name] = {"iters": rep.iters, "status": rep.status, "seconds": rep.seconds,
+                     "ms_per_iter": 1e3 * rep.seconds / max(1, rep.iters),
+                     "res_drop": rep.res_final / rep.res_fs}
+        st.close()
+    return out
+
+
 def batch_run(lk, cloudgen, iters):
     """64 conditions on 8 uneven clouds, FP32 sweeps / FP64 residual, autotuned."""
     import numpy as np
@@ -446,6 +463,10 @@ def main():
             "exact_mixed": time_to_tol(lk, gc, args.tol_iters, precision=lk.MIXED),
         }
         print(f"# time to tol: {json.dumps(extra['time_to_1e-8'])}", file=sys.stderr, flush=True)
+    if args.tol_iters > 0:
+        extra["explicit_vs_implicit_2000_iters"] = explicit_vs_implicit(lk, gc, 2000)
+        print(f"# explicit vs implicit: {json.dumps(extra['explicit_vs_implicit_2000_iters'])}",
+              file=sys.stderr, flush=True)
     if args.batch_iters > 0:
         extra["batch_64_conditions"] = batch_run(lk, cloudgen, args.batch_iters)
         print(f"# batch: {json.dumps(extra['batch_64_conditions'])}", file=sys.stderr, flush=True)

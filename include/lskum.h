@@ -61,6 +61,8 @@ enum {
 enum { LSKUM_JVP_EXACT = 0, LSKUM_JVP_FLUXDIFF = 1 };
 enum { LSKUM_FP64 = 0, LSKUM_MIXED = 1 };
 enum { LSKUM_ANANDH = 0, LSKUM_MANISH = 1 };
+enum { LSKUM_IMPLICIT = 0, LSKUM_EXPLICIT = 1 };
+enum { LSKUM_ORDER_COLOUR = 0, LSKUM_ORDER_WALL_FIRST = 1 };
 
 typedef struct lskum_cloud lskum_cloud; /* device geometry, CSR, colours */
 typedef struct lskum_state lskum_state; /* device flow state and work arrays */
@@ -93,6 +95,19 @@ typedef struct {
                                the term S on the forward right-hand side R - S,
                                S from the previous iteration's increment (zero
                                after state creation or a new U) */
+    int32_t scheme;         /* LSKUM_IMPLICIT: the LU-SGS iteration above;
+                               LSKUM_EXPLICIT: the paper's explicit solver,
+                               U <- U - dt R with the same local time step
+                               (the CFL number must suit an explicit scheme,
+                               e.g. 0.4); no sweeps, no increment kept */
+    int32_t order;          /* LSKUM_ORDER_COLOUR: each sweep visits the colours
+                               in turn (Algorithm 6); LSKUM_ORDER_WALL_FIRST:
+                               wall, interior and outer points in turn, colours
+                               ascending (forward) / descending (backward)
+                               within each (Algorithm 5); a point still sums
+                               over its lower-/upper-colour neighbours, reading
+                               what the increment array holds (zero at the
+                               start of the forward sweep) */
 } lskum_params;
 
 typedef struct {
@@ -107,7 +122,8 @@ typedef struct {
 
 /* Fills p with the defaults: gamma 1.4, cfl 100, inner_iters 1, exact JVP,
  * fp64, check_every 10, tol_rel 1e-8, max_iters 20000, lanes 0 (library
- * choice), no limiter (limiter_k 5), Anandhanarayanan variant. */
+ * choice), no limiter (limiter_k 5), Anandhanarayanan variant, implicit
+ * scheme, colour order. */
 void lskum_default_params(lskum_params* p);
 
 /* Creates a cloud on the current HIP device from host arrays of n points.
@@ -162,8 +178,9 @@ int lskum_residual(lskum_state* s, double* R, int on_device, double* res);
  * inner_iters inner iterations (eq. 16): qx, qy ([4][n]). */
 int lskum_q_derivatives(lskum_state* s, double* qx, double* qy, int on_device);
 
-/* One implicit iteration: residual, local time step and diagonal, forward
- * and backward colour sweeps (eq. 27), U += dU.  *res (may be NULL) receives
+/* One iteration of the state's scheme.  Implicit: residual, local time step
+ * and diagonal, forward and backward colour sweeps (eq. 27), U += dU.
+ * Explicit: residual, U -= dt R.  *res (may be NULL) receives
  * the norm of the residual of the state the step started from; passing NULL
  * keeps the step free of host synchronisation.
  * Errors: NONPHYSICAL (the state then holds the non-physical result). */
@@ -172,7 +189,8 @@ int lskum_lusgs_step(lskum_state* s, double* res);
 /* One lskum_lusgs_step launched eagerly with HIP events between its
  * phases on the state's stream; ms[6] receives the GPU milliseconds of
  * (0) q-derivatives, (1) residual kernel, (2) residual norm, (3) forward
- * sweep, (4) backward sweep, (5) state update.  Synchronises the stream. */
+ * sweep, (4) backward sweep, (5) state update (0 for the sweeps of the
+ * explicit scheme).  Synchronises the stream. */
 int lskum_step_timed(lskum_state* s, double* ms);
 
 /* Iterates lusgs steps until res <= tol_rel * res_fs or max_iters; the

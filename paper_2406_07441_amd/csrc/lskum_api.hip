@@ -145,11 +145,16 @@ int upload_cloud(lskum::Cloud& c) {
     const int64_t n = c.n, nnz = c.nnz;
     c.ncolour = 0;
     for (int64_t p = 0; p < n; ++p) c.ncolour = std::max(c.ncolour, c.h_colour[p] + 1);
+    // colour-sorted points, by point type (wall, interior, outer) within a
+    // colour and by index within that: colour c, type g occupies
+    // [h_grp_off[3c + g], h_grp_off[3c + g + 1])
+    c.h_grp_off.assign(3 * (size_t)c.ncolour + 1, 0);
+    for (int64_t p = 0; p < n; ++p) ++c.h_grp_off[3 * c.h_colour[p] + c.h_type[p] + 1];
+    for (size_t k = 0; k + 1 < c.h_grp_off.size(); ++k) c.h_grp_off[k + 1] += c.h_grp_off[k];
     c.h_col_off.assign(c.ncolour + 1, 0);
-    for (int64_t p = 0; p < n; ++p) ++c.h_col_off[c.h_colour[p] + 1];
-    for (int32_t k = 0; k < c.ncolour; ++k) c.h_col_off[k + 1] += c.h_col_off[k];
-    std::vector<int32_t> perm(n), fill(c.h_col_off.begin(), c.h_col_off.end() - 1);
-    for (int64_t p = 0; p < n; ++p) perm[fill[c.h_colour[p]]++] = (int32_t)p;
+    for (int32_t k = 0; k <= c.ncolour; ++k) c.h_col_off[k] = c.h_grp_off[3 * k];
+    std::vector<int32_t> perm(n), fill(c.h_grp_off.begin(), c.h_grp_off.end() - 1);
+    for (int64_t p = 0; p < n; ++p) perm[fill[3 * c.h_colour[p] + c.h_type[p]]++] = (int32_t)p;
 
     // sweep lists in colour-sorted point order
     std::vector<int32_t> lo_off(n + 1, 0), up_off(n + 1, 0), lo_idx, up_idx;
@@ -314,6 +319,10 @@ int check_params(const lskum_params* p) {
         return fail(LSKUM_ERR_ARG, "lanes must be 0, 1, 2, 4 or 8 (16 for the sweeps)");
     if ((p->limiter != 0 && p->limiter != 1) || !(p->limiter_k > 0.0))
         return fail(LSKUM_ERR_ARG, "limiter must be 0 or 1 with limiter_k > 0");
+    if (p->order != 0 && p->order != 1)
+        return fail(LSKUM_ERR_ARG, "order must be LSKUM_ORDER_COLOUR or LSKUM_ORDER_WALL_FIRST");
+    if (p->scheme != 0 && p->scheme != 1)
+        return fail(LSKUM_ERR_ARG, "scheme must be LSKUM_IMPLICIT or LSKUM_EXPLICIT");
     if (p->variant != 0 && p->variant != 1)
         return fail(LSKUM_ERR_ARG, "variant must be LSKUM_ANANDH or LSKUM_MANISH");
     if (p->precision == 1 && p->jvp_mode == 1)
@@ -325,7 +334,7 @@ lskum::Params to_params(const lskum_params* p) {
     return lskum::Params{p->gamma,       p->cfl,            p->inner_iters, p->jvp_mode,
                          p->precision,   p->check_every,    p->tol_rel,     p->max_iters,
                          p->sweep_lanes, p->residual_lanes, p->limiter,     p->limiter_k,
-                         p->variant};
+                         p->variant,     p->scheme,         p->order};
 }
 
 // Lanes per point: the caller's choice, else 8 for the latency-bound sweeps
@@ -347,6 +356,11 @@ int enqueue_step(lskum::State& s, int slot) {
     HIPCHK(lskum::launch_q_derivatives(s));
     HIPCHK(lskum::launch_residual(s, slot));
     HIPCHK(lskum::launch_norm(s, slot));
+    if (s.prm.scheme == 1) {
+        HIPCHK(lskum::launch_explicit_update(s));
+        s.have_dU = false;
+        return LSKUM_OK;
+    }
     HIPCHK(lskum::launch_sweeps(s));
     HIPCHK(lskum::launch_update(s));
     s.have_dU = true;
@@ -604,6 +618,8 @@ void lskum_default_params(lskum_params* p) {
     p->limiter = 0;
     p->limiter_k = 5.0;
     p->variant = LSKUM_ANANDH;
+    p->scheme = LSKUM_IMPLICIT;
+    p->order = LSKUM_ORDER_COLOUR;
 }
 
 int lskum_cloud_create(int64_t n, const double* x, const double* y, const int8_t* type,
@@ -735,7 +751,8 @@ int lskum_state_set_params(lskum_state* so, const lskum_params* prm) {
                               np.limiter == s.prm.limiter && np.limiter_k == s.prm.limiter_k &&
                               np.sweep_lanes == s.prm.sweep_lanes &&
                               np.residual_lanes == s.prm.residual_lanes &&
-                              np.variant == s.prm.variant;
+                              np.variant == s.prm.variant && np.scheme == s.prm.scheme &&
+                              np.order == s.prm.order;
     if (s.graph && !same_kernels) {
         (void)hipGraphExecDestroy(s.graph);
         s.graph = nullptr;
@@ -863,14 +880,15 @@ int lskum_step_timed(lskum_state* so, double* ms) {
     HIPCHK(hipEventRecord(s.ev[2], s.stream));
     HIPCHK(lskum::launch_norm(s, 0));
     HIPCHK(hipEventRecord(s.ev[3], s.stream));
-    HIPCHK(lskum::launch_sweep_dir(s, true));
+    const bool expl = s.prm.scheme == 1;
+    if (!expl) HIPCHK(lskum::launch_sweep_dir(s, true));
     HIPCHK(hipEventRecord(s.ev[4], s.stream));
-    HIPCHK(lskum::launch_sweep_dir(s, false));
+    if (!expl) HIPCHK(lskum::launch_sweep_dir(s, false));
     HIPCHK(hipEventRecord(s.ev[5], s.stream));
-    HIPCHK(lskum::launch_update(s));
+    HIPCHK(expl ? lskum::launch_explicit_update(s) : lskum::launch_update(s));
     HIPCHK(hipEventRecord(s.ev[6], s.stream));
     HIPCHK(hipEventSynchronize(s.ev[6]));
-    s.have_dU = true;
+    s.have_dU = !expl;
     for (int k = 0; k < 6; ++k) {
         float t = 0.f;
         HIPCHK(hipEventElapsedTime(&t, s.ev[k], s.ev[k + 1]));

@@ -980,6 +980,34 @@ __global__ void __launch_bounds__(kBlock) k_update(int64_t n, double gamma, D4* 
     if (bad) flags[0] = 1;
 }
 
+// Explicit iteration (the paper's explicit LSKUM solver): U <- U - dt R with
+// the implicit scheme's local time step dt = CFL rmin / (|u| + a) at the
+// current state, then the next q-variables.  Outer points keep their state.
+__global__ void __launch_bounds__(kBlock) k_explicit_update(
+    int64_t n, double gamma, double cfl, const int8_t* __restrict__ type,
+    const PointGeom* __restrict__ geom, const int32_t* __restrict__ comp,
+    const int32_t* __restrict__ active, const D4* __restrict__ R, D4* __restrict__ U,
+    D4* __restrict__ q, int32_t* __restrict__ flags) {
+    const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (p >= n || !live(comp, active, p) || type[p] == kOuter) return;
+    D4 u = U[p];
+    const double rho = u.x, irho = 1.0 / rho;
+    const double u1 = u.y * irho, u2 = u.z * irho;
+    const double usq = u1 * u1 + u2 * u2;
+    const double pr = (gamma - 1.0) * (u.w - 0.5 * rho * usq);
+    const double a = sqrt(gamma * pr / rho);
+    const double dt = cfl * geom[p].lsq.w / (sqrt(usq) + a);
+    const D4 r = R[p];
+    u.x -= dt * r.x;
+    u.y -= dt * r.y;
+    u.z -= dt * r.z;
+    u.w -= dt * r.w;
+    U[p] = u;
+    bool bad;
+    q[p] = q_of_U(u, gamma, 1.0 / (gamma - 1.0), bad);
+    if (bad) flags[0] = 1;
+}
+
 // Pressure force on the closed wall polygon of each component (one block per
 // component): sum over edges (a, b) of -(p_mid - p_inf) * |e| * (edge normal
 // pointing out of the body), orient = +1 for a counter-clockwise polygon.
@@ -1190,13 +1218,35 @@ hipError_t launch_reset_components(State& s) {
     return hipGetLastError();
 }
 
+// The phases of a sweep as ranges of the colour-sorted points: one per
+// colour (Algorithm 6), or per (point type, colour) with wall, interior and
+// outer points in turn (Algorithm 5); colours ascending forward, descending
+// backward.
+static std::vector<std::pair<int32_t, int32_t>> sweep_phases(const State& s, bool forward) {
+    const Cloud& c = *s.cloud;
+    std::vector<std::pair<int32_t, int32_t>> ph;
+    const int C = c.ncolour;
+    if (s.prm.order == 0) {
+        for (int k = 0; k < C; ++k) {
+            const int col = forward ? k : C - 1 - k;
+            ph.emplace_back(c.h_col_off[col], c.h_col_off[col + 1] - c.h_col_off[col]);
+        }
+        return ph;
+    }
+    for (int g = 0; g < 3; ++g)
+        for (int k = 0; k < C; ++k) {
+            const int col = forward ? k : C - 1 - k;
+            const int32_t a = c.h_grp_off[3 * col + g], b = c.h_grp_off[3 * col + g + 1];
+            ph.emplace_back(a, b - a);
+        }
+    return ph;
+}
+
 template <class T, int MODE, int LANES>
 static void sweep_lanes(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv1,
                         const Vec4<T>* jv2, const T* Dg, Vec4<T>* dU) {
     const Cloud& c = *s.cloud;
-    for (int k = 0; k < c.ncolour; ++k) {
-        const int col = forward ? k : c.ncolour - 1 - k;
-        const int32_t start = c.h_col_off[col], cnt = c.h_col_off[col + 1] - start;
+    for (const auto& [start, cnt] : sweep_phases(s, forward)) {
         if (!cnt) continue;
         const dim3 g(grid_for((int64_t)cnt * LANES)), b(kBlock);
         if (forward)
@@ -1224,7 +1274,24 @@ static void sweep_t(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* j
     }
 }
 
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_zero4(int64_t n, Vec4<T>* __restrict__ v) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) v[p] = {T(0), T(0), T(0), T(0)};
+}
+
 hipError_t launch_sweep_dir(State& s, bool forward) {
+    const Cloud& c = *s.cloud;
+    // Algorithm 5 reads increments of points not yet visited in the forward
+    // sweep: they start the sweep at zero (a kernel, so that graphs replay it)
+    if (forward && s.prm.order == 1) {
+        if (s.prm.precision == 1)
+            hipLaunchKernelGGL(k_zero4<float>, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream, c.n,
+                               s.dUf);
+        else
+            hipLaunchKernelGGL(k_zero4<double>, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream,
+                               c.n, s.dU);
+    }
     if (s.prm.precision == 1)
         sweep_t<float, 0>(s, forward, s.jv0f, s.jv1f, s.jv2f, s.Df, s.dUf);
     else if (s.prm.jvp_mode == 1)
@@ -1238,6 +1305,14 @@ hipError_t launch_sweeps(State& s) {
     hipError_t e = launch_sweep_dir(s, true);
     if (e != hipSuccess) return e;
     return launch_sweep_dir(s, false);
+}
+
+hipError_t launch_explicit_update(State& s) {
+    const Cloud& c = *s.cloud;
+    hipLaunchKernelGGL(k_explicit_update, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream, c.n,
+                       s.prm.gamma, s.prm.cfl, c.type, c.geom, c.comp, s.active, s.R, s.U, s.q,
+                       s.flags);
+    return hipGetLastError();
 }
 
 hipError_t launch_update(State& s) {

@@ -96,6 +96,7 @@ struct Cloud {
     // host
     std::vector<int32_t> h_colour;
     std::vector<int32_t> h_col_off;  // ncolour + 1
+    std::vector<int32_t> h_grp_off;  // 3 ncolour + 1: (colour, point type) ranges
 };
 
 struct Params {
@@ -107,6 +108,8 @@ struct Params {
     int limiter;
     double limiter_k;
     int variant;  // 0 Anandhanarayanan et al., 1 Manish et al.
+    int scheme;   // 0 implicit (LU-SGS), 1 explicit
+    int order;    // 0 colour order (Algorithm 6), 1 wall points first (Algorithm 5)
 };
 
 // Device work arrays of one flow state.
@@ -183,6 +186,7 @@ hipError_t launch_reset_components(State& s);
 hipError_t launch_sweeps(State& s);
 hipError_t launch_sweep_dir(State& s, bool forward);
 hipError_t launch_update(State& s);
+hipError_t launch_explicit_update(State& s);  // U -= dt R (explicit scheme)
 hipError_t launch_forces(State& s);  // fsum[2k..2k+1] = force of component k
 hipError_t launch_soa_to_aos(const double* soa, D4* aos, int64_t n, hipStream_t st);
 hipError_t launch_aos_to_soa(const D4* aos, double* soa, int64_t n, hipStream_t st);

@@ -23,6 +23,8 @@ ERR_NONPHYSICAL, ERR_NOT_CONVERGED, ERR_HIP, ERR_OOM = -5, -6, -7, -8
 JVP_EXACT, JVP_FLUXDIFF = 0, 1
 FP64, MIXED = 0, 1
 ANANDH, MANISH = 0, 1
+IMPLICIT, EXPLICIT = 0, 1
+ORDER_COLOUR, ORDER_WALL_FIRST = 0, 1
 
 
 class LskumError(RuntimeError):
@@ -36,7 +38,7 @@ class Params(C.Structure):
                 ("jvp_mode", C.c_int32), ("precision", C.c_int32), ("check_every", C.c_int32),
                 ("tol_rel", C.c_double), ("max_iters", C.c_int32), ("sweep_lanes", C.c_int32),
                 ("residual_lanes", C.c_int32), ("limiter", C.c_int32), ("limiter_k", C.c_double),
-                ("variant", C.c_int32)]
+                ("variant", C.c_int32), ("scheme", C.c_int32), ("order", C.c_int32)]
 
 
 class Report(C.Structure):

@@ -278,3 +278,44 @@ def test_manish_variant_mixed_and_batch(lk, cfg1):
         assert np.array_equal(b.get_U(k), s1.get_U())
         s1.close()
     b.close()
+
+
+def test_explicit_scheme_parity(lk, cfg1):
+    """The explicit solver (U - dt R) over five iterations, and its residual
+    norm at each, against the oracle."""
+    o = O.Oracle(cfg1.cloud, mach=0.63, aoa_deg=2.0, cfl=0.4, inner_iters=1)
+    st = lk.State(cfg1.gc, 0.63, 2.0, lk.default_params(cfl=0.4, scheme=lk.EXPLICIT))
+    U = o.free_stream()
+    for it in range(5):
+        U, R, res = o.explicit_iteration(U)
+        res_gpu = st.step()
+        assert abs(res_gpu - res) <= TOL * res
+    dU_rel = rel(st.get_U() - cfg1.states[0], U - cfg1.states[0])
+    print(f"explicit: U change rel err {dU_rel:.3e}")
+    assert dU_rel < TOL
+    with pytest.raises(lk.LskumError):
+        st.get_dU()
+    ph = st.step_timed()
+    assert ph["forward_sweep"] < 0.05 and ph["backward_sweep"] < 0.05
+    st.close()
+
+
+def test_wall_first_order_parity(lk, cfg1, jit):
+    """Algorithm 5 (wall, interior, outer points in turn) against the oracle,
+    FP64 at 1e-11 and mixed at 1e-4, and different from the colour order."""
+    for case, mach, aoa, it in ((cfg1, 0.63, 2.0, 10), (jit, 0.85, 1.0, 3)):
+        o = O.Oracle(case.cloud, mach=mach, aoa_deg=aoa, cfl=100.0, inner_iters=1,
+                     order=O.WALL_FIRST)
+        U = case.states[it]
+        _, _, dUo, _ = o.iteration(U)
+        for prec, tol in ((lk.FP64, TOL), (lk.MIXED, 1e-4)):
+            st = lk.State(case.gc, mach, aoa,
+                          lk.default_params(order=lk.ORDER_WALL_FIRST, precision=prec))
+            st.set_U(U)
+            st.step()
+            e = rel(st.get_dU(), dUo)
+            print(f"wall-first precision={prec}: dU rel err {e:.3e}")
+            assert e < tol
+            st.close()
+        _, _, dUc, _ = case.o.iteration(U)
+        assert rel(dUc, dUo) > 1e-8
