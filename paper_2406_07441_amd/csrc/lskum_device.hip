@@ -1087,20 +1087,20 @@ hipError_t launch_precompute(Cloud& c, hipStream_t st) {
     unsigned long long* d_cnt = nullptr;
     hipError_t e = hipMalloc((void**)&d_cnt, 2 * sizeof(unsigned long long));
     if (e != hipSuccess) return e;
+    unsigned long long h[2] = {0, 0};
     e = hipMemsetAsync(d_cnt, 0, 2 * sizeof(unsigned long long), st);
-    if (e != hipSuccess) return e;
-    if (c.n > 0)
+    if (e == hipSuccess && c.n > 0) {
         hipLaunchKernelGGL(k_precompute, dim3(grid_for(c.n)), dim3(kBlock), 0, st, c.n, c.xy,
                            c.frame, c.type, c.off, c.idx, c.geom, d_cnt);
-    unsigned long long h[2] = {0, 0};
-    e = hipMemcpyAsync(h, d_cnt, sizeof(h), hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return e;
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d_cnt, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(d_cnt);
+    if (e != hipSuccess) return e;
     c.n_degenerate = (int64_t)h[1];
     if (h[0]) return hipErrorInvalidValue;  // singular full stencil, reported by the caller
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 hipError_t launch_sweep_weights(Cloud& c, hipStream_t st) {
