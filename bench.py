@@ -204,6 +204,7 @@ def batch_converge(lk, cloudgen, max_iters):
            "seconds_until_all_retired": max(d["seconds"] for d in done),
            "point_iters_per_s": pts / tot, "lanes": {"sweep": lanes[0], "residual": lanes[1]},
            "iters": [d["iters"] for d in done],
+           "res_drop": [float(f"{d['res_drop']:.3e}") for d in done],
            "not_converged": [k for k, d in enumerate(done) if d["status"] != 0]}
     b.close()
     return out

@@ -354,7 +354,7 @@ int read_flags(lskum::State& s, int32_t* h) {
 // Enqueues one iteration; component residual norms go to res_hist[slot][k].
 int enqueue_step(lskum::State& s, int slot) {
     HIPCHK(lskum::launch_q_derivatives(s));
-    HIPCHK(lskum::launch_residual(s, slot));
+    HIPCHK(lskum::launch_residual(s, slot, true));
     HIPCHK(lskum::launch_norm(s, slot));
     if (s.prm.scheme == 1) {
         HIPCHK(lskum::launch_explicit_update(s));
@@ -876,7 +876,7 @@ int lskum_step_timed(lskum_state* so, double* ms) {
     HIPCHK(hipEventRecord(s.ev[0], s.stream));
     HIPCHK(lskum::launch_q_derivatives(s));
     HIPCHK(hipEventRecord(s.ev[1], s.stream));
-    HIPCHK(lskum::launch_residual(s, 0));
+    HIPCHK(lskum::launch_residual(s, 0, true));
     HIPCHK(hipEventRecord(s.ev[2], s.stream));
     HIPCHK(lskum::launch_norm(s, 0));
     HIPCHK(hipEventRecord(s.ev[3], s.stream));

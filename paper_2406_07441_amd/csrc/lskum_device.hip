@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(
     D4* __restrict__ jv0, D4* __restrict__ jv1, D4* __restrict__ jv2, F4* __restrict__ jv0f,
     F4* __restrict__ jv1f, F4* __restrict__ jv2f, float* __restrict__ Df,
     double* __restrict__ rr_out, int32_t* __restrict__ flags, int variant, int fd,
-    const D4* __restrict__ dUprev, const F4* __restrict__ dUprevf, D4* __restrict__ Rs) {
+    D4* dUio, F4* dUfio, D4* __restrict__ Rs, const int32_t* __restrict__ colour, int sweep0) {
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t gt = (int64_t)lb * blockDim.x + threadIdx.x;
     const int64_t p = gt / LANES;
@@ -564,10 +564,10 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                 // iteration's increment onto the forward right-hand side R - S (eq. 36-38)
                 double dv[4] = {0, 0, 0, 0};
                 if (MIXED) {
-                    const F4 d = dUprevf[p];
+                    const F4 d = dUfio[p];
                     dv[0] = d.x; dv[1] = d.y; dv[2] = d.z; dv[3] = d.w;
                 } else {
-                    const D4 d = dUprev[p];
+                    const D4 d = dUio[p];
                     dv[0] = d.x; dv[1] = d.y; dv[2] = d.z; dv[3] = d.w;
                 }
                 double Sv[4] = {0, 0, 0, 0}, Ja[4], Jb[4];
@@ -602,6 +602,9 @@ __global__ void __launch_bounds__(kBlock) k_residual(
 #pragma unroll
                     for (int v = 0; v < 4; ++v) Sv[v] = -0.5 * (ca * Ja[v] + cb * Jb[v]);
                 Rs[p] = {Rp[0] - Sv[0], Rp[1] - Sv[1], Rp[2] - Sv[2], Rp[3] - Sv[3]};
+                if (sweep0)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) Sv[v] = Rp[v] - Sv[v];
             }
             if (MIXED) {
                 jv0f[p] = {(float)j0.x, (float)j0.y, (float)j0.z, (float)j0.w};
@@ -613,6 +616,45 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                 jv1[p] = j1;
                 jv2[p] = j2;
                 Dg[p] = Dp;
+            }
+            // the forward sweep's first colour phase: its points have no lower
+            // neighbours, dU* = -R / D (R - S for the Manish variant), in the
+            // sweep precision and with the sweep kernel's arithmetic
+            if (sweep0 && colour[p] == 0) {
+                double rs[4] = {Rp[0], Rp[1], Rp[2], Rp[3]};
+                if (variant != 0) {
+                    const D4 r2 = Rs[p];
+                    rs[0] = r2.x; rs[1] = r2.y; rs[2] = r2.z; rs[3] = r2.w;
+                }
+                if (MIXED) {
+                    float o[4] = {0.f, 0.f, 0.f, 0.f};
+                    if (ty != kOuter) {
+                        const float iD = 1.0f / (float)Dp;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) o[v] = -((float)rs[v] + 0.0f) * iD;
+                        if (ty == kWall) {
+                            const float nx = (float)(-t.y), ny = (float)t.x;
+                            const float mn = o[1] * nx + o[2] * ny;
+                            o[1] -= mn * nx;
+                            o[2] -= mn * ny;
+                        }
+                    }
+                    dUfio[p] = {o[0], o[1], o[2], o[3]};
+                } else {
+                    double o[4] = {0, 0, 0, 0};
+                    if (ty != kOuter) {
+                        const double iD = 1.0 / Dp;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) o[v] = -(rs[v] + 0.0) * iD;
+                        if (ty == kWall) {
+                            const double nx = -t.y, ny = t.x;
+                            const double mn = o[1] * nx + o[2] * ny;
+                            o[1] -= mn * nx;
+                            o[2] -= mn * ny;
+                        }
+                    }
+                    dUio[p] = {o[0], o[1], o[2], o[3]};
+                }
             }
             if (bad || !(rho > 0.0) || !(pr > 0.0)) flags[0] = 1;
         }
@@ -1170,8 +1212,13 @@ hipError_t launch_q_derivatives(State& s) {
     return hipGetLastError();
 }
 
+// In colour order the first forward phase (no lower neighbours) is done by the
+// residual kernel and the first backward phase (no upper neighbours: dU = dU*)
+// is skipped.
+static int fused_first_colour(const State& s) { return s.prm.order == 0 && s.prm.scheme == 0; }
+
 template <bool MIXED, int LANES>
-static void residual_lanes(State& s) {
+static void residual_lanes(State& s, bool in_step) {
     const Cloud& c = *s.cloud;
     const unsigned nb = grid_for(c.n * LANES);
     hipLaunchKernelGGL((k_residual<MIXED, LANES>), dim3(nb), dim3(kBlock), 0, s.stream, c.n,
@@ -1179,25 +1226,26 @@ static void residual_lanes(State& s) {
                        s.active, s.U, s.q, s.prm.limiter ? s.qxl : s.qx[s.qsel],
                        s.prm.limiter ? s.qyl : s.qy[s.qsel], s.R, s.D, s.jv0, s.jv1, s.jv2,
                        s.jv0f, s.jv1f, s.jv2f, s.Df, s.rr, s.flags, s.prm.variant,
-                       s.prm.jvp_mode, s.dU, s.dUf, s.Rs);
+                       s.prm.jvp_mode, s.dU, s.dUf, s.Rs, c.colour,
+                       in_step && fused_first_colour(s));
 }
 
 template <bool MIXED>
-static void residual_t(State& s) {
+static void residual_t(State& s, bool in_step) {
     switch (s.residual_lanes) {
-        case 1: residual_lanes<MIXED, 1>(s); break;
-        case 2: residual_lanes<MIXED, 2>(s); break;
-        case 8: residual_lanes<MIXED, 8>(s); break;
-        default: residual_lanes<MIXED, 4>(s); break;
+        case 1: residual_lanes<MIXED, 1>(s, in_step); break;
+        case 2: residual_lanes<MIXED, 2>(s, in_step); break;
+        case 8: residual_lanes<MIXED, 8>(s, in_step); break;
+        default: residual_lanes<MIXED, 4>(s, in_step); break;
     }
 }
 
-hipError_t launch_residual(State& s, int slot) {
+hipError_t launch_residual(State& s, int slot, bool in_step) {
     (void)slot;
     if (s.prm.precision == 1)
-        residual_t<true>(s);
+        residual_t<true>(s, in_step);
     else
-        residual_t<false>(s);
+        residual_t<false>(s, in_step);
     return hipGetLastError();
 }
 
@@ -1227,7 +1275,7 @@ static std::vector<std::pair<int32_t, int32_t>> sweep_phases(const State& s, boo
     std::vector<std::pair<int32_t, int32_t>> ph;
     const int C = c.ncolour;
     if (s.prm.order == 0) {
-        for (int k = 0; k < C; ++k) {
+        for (int k = fused_first_colour(s) ? 1 : 0; k < C; ++k) {
             const int col = forward ? k : C - 1 - k;
             ph.emplace_back(c.h_col_off[col], c.h_col_off[col + 1] - c.h_col_off[col]);
         }

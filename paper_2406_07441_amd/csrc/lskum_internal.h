@@ -179,7 +179,9 @@ hipError_t launch_free_stream(State& s);
 hipError_t launch_q_from_U(State& s);
 hipError_t launch_q_derivatives(State& s);  // includes the limiter when on
 // residual + time step/diagonal + sweep intermediates (per-point R_rho^2)
-hipError_t launch_residual(State& s, int slot);
+// in_step: part of an implicit step (the kernel then also does the forward
+// sweep's first colour phase); false for a residual evaluation alone
+hipError_t launch_residual(State& s, int slot, bool in_step = false);
 // per-component residual norms into res_hist[slot][k]; retires components
 hipError_t launch_norm(State& s, int slot);
 hipError_t launch_reset_components(State& s);
