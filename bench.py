@@ -43,12 +43,13 @@ NB_OPS = 2 + 40 + 2 * (11 + COST["exp"] + COST["sqrt"] + 2 * COST["div"])
 # + div each), difference, scale and accumulate (12)
 SPLIT_OPS = 3 + 2 * (25 + COST["erf"] + COST["exp"] + COST["div"]) + 12
 
-# Algorithmic bytes of one sweep (all colour phases) per point, each array
-# read or written once: own R 32 (forward) or dU* 32 (backward), D 8,
-# list offsets 8, coordinates 16, geometry split coefficients 64, type 1,
-# result 32; the point's linearisation data (96) and increment (32) read by
-# its neighbours; 4 bytes per list entry.
-SWEEP_POINT_BYTES = 32 + 8 + 8 + 16 + 64 + 1 + 32 + 96 + 32
+# Algorithmic bytes of the sweep, each array read or written once. Per swept
+# point: colour-sorted index 4, list offset 4, component 4, type 1, wall
+# frame 16, D 8, own R (forward) or dU* (backward) 32, result 32, and its
+# linearisation data (96) and increment (32) as read by its neighbours; per
+# list entry: neighbour index 4, split weights 16, split code 1.
+SWEEP_POINT_BYTES = 4 + 4 + 4 + 1 + 16 + 8 + 32 + 32 + 96 + 32
+SWEEP_ENTRY_BYTES = 4 + 16 + 1
 
 
 def residual_flops(cloud) -> float:
@@ -63,9 +64,16 @@ def residual_flops(cloud) -> float:
     return float(np.sum(deg[active] * (NB_OPS + splits[active] * SPLIT_OPS)))
 
 
-def sweep_bytes(cloud) -> float:
-    """Algorithmic HBM bytes of one sweep direction over the whole cloud."""
-    return float(cloud.n * SWEEP_POINT_BYTES + 4 * cloud.nnz / 2)
+def forward_sweep_bytes(cloud, colours) -> tuple[float, int]:
+    """Algorithmic bytes of the forward sweep's colour-phase launches and their
+    number: colours 1 and up (the colour-0 phase has no lower neighbours and is
+    formed inside the residual kernel), with every lower-list entry."""
+    import numpy as np
+    deg = np.diff(cloud.nbr_off)
+    src = np.repeat(np.arange(cloud.n), deg)
+    lower = int(np.count_nonzero(colours[cloud.nbr_idx] < colours[src]))
+    swept = int(np.count_nonzero(colours > 0))
+    return float(swept * SWEEP_POINT_BYTES + lower * SWEEP_ENTRY_BYTES), int(colours.max())
 
 
 def device_source_hash() -> str:
@@ -340,6 +348,37 @@ def warm_start_run(lk, cloudgen, train_steps: int, held_out: int):
     }
 
 
+def mlp_profile_run(lk) -> dict:
+    """The warm-start network alone on random rows: 20 + 200 minibatch Adam
+    steps of 8192 rows, then 11 forward passes over 655,360 rows and 11 over
+    1,000,000 rows (one launch each)."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(0)
+    n = 1_000_000
+    X = torch.from_numpy(rng.uniform(-1, 1, (n, 5)).astype(np.float32)).cuda()
+    T = torch.from_numpy((0.1 * rng.standard_normal((n, 4))).astype(np.float32)).cuda()
+    net = lk.MLP(seed=1, max_rows=8192)
+    net.train(X, T, steps=20, batch=8192, lr=1e-3)
+    _, train_s = net.train(X, T, steps=200, batch=8192, lr=1e-3)
+    out = {"train_steps": 200, "batch": 8192, "train_s": train_s,
+           "train_tflops": 3 * MLP_FLOP_PER_ROW * 8192 * 200 / train_s / 1e12}
+    net.close()
+    big = lk.MLP(seed=1, max_rows=n)
+    for rows in (655_360, n):
+        big.forward(X[:rows])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            big.forward(X[:rows])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 10
+        out[f"forward_{rows}_ms"] = 1e3 * dt
+        out[f"forward_{rows}_tflops"] = MLP_FLOP_PER_ROW * rows / dt / 1e12
+    big.close()
+    return out
+
+
 def cpu_baseline(cloud, iters: int):
     import oracle
     o = oracle.Oracle(cloud, mach=MACH, aoa_deg=AOA, cfl=CFL, inner_iters=INNER,
@@ -374,6 +413,9 @@ def main():
                     help="2,621,440-point FP64 vs mixed run to 1e-8 with this cap (0 skips)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the timed steps (for profiler runs)")
+    ap.add_argument("--profile-mlp", action="store_true",
+                    help="run only the warm-start network's training and inference "
+                         "timing (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -390,6 +432,9 @@ def main():
     from paper_2406_07441_amd import lskum as lk
 
     torch.cuda.set_device(0)
+    if args.profile_mlp:
+        print(json.dumps(mlp_profile_run(lk)))
+        return
     if args.calibrate_copy:
         src = torch.ones(32 * 2 ** 20, dtype=torch.float64, device="cuda")   # 256 MiB
         dst = torch.empty_like(src)
@@ -433,15 +478,16 @@ def main():
     flops = residual_flops(cloud)
     res_ms = phases["residual"]
     res_tf = flops / (res_ms * 1e-3) / 1e12
-    sweep_ms = phases["forward_sweep"] / ncol          # average launch of a colour phase
-    sweep_b = sweep_bytes(cloud) / ncol                # algorithmic bytes per launch
+    fwd_b, fwd_launches = forward_sweep_bytes(cloud, gc.colours())
+    sweep_ms = phases["forward_sweep"] / fwd_launches  # average launch of a colour phase
+    sweep_b = fwd_b / fwd_launches                     # algorithmic bytes per launch
     sweep_gbs = sweep_b / (sweep_ms * 1e-3) / 1e9
     kernels = {
         "k_sweep_forward": {"bound": "hbm", "achieved": sweep_gbs, "peak": PEAK_HBM_GBS,
                             "unit": "GB/s", "frac": sweep_gbs / PEAK_HBM_GBS,
                             "traffic": (traffic or {}).get("k_sweep_forward"),
                             "bytes_per_launch": sweep_b, "avg_ms": sweep_ms,
-                            "launches_per_step": ncol,
+                            "launches_per_step": fwd_launches,
                             "ms_per_step": phases["forward_sweep"]},
         "k_residual": {"bound": "alu", "achieved": res_tf, "peak": PEAK_FP64_TFLOPS,
                        "unit": "TFLOP/s", "frac": res_tf / PEAK_FP64_TFLOPS,
