@@ -883,6 +883,7 @@ __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const D2&
     const Vec4<T> di = dU[i];
     const T dv[4] = {di.x, di.y, di.z, di.w};
     const Lin<T> L = load_lin(jv0, jv1, i);
+    const Vec4<T> k2 = jv2[i];  // interior entries only; loaded with the rest
     T J[4];
     if (cd & kSwWall) {
         // wall-frame directions: erf/exp at the neighbour state are formed here
@@ -915,7 +916,6 @@ __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const D2&
         }
         return;
     }
-    const Vec4<T> k2 = jv2[i];
     if (cd & kSwA) {
         const T sg = (cd & kSwNegA) ? T(1) : T(-1);
         if constexpr (MODE == 1)
@@ -959,38 +959,75 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
     const int gt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int pt = gt / LANES, lane = gt % LANES;
     if (pt >= count) return;  // uniform over the lanes of a point
+    // A phase is short and latency-bound, so its loads are ordered to form as
+    // few dependent levels as possible: q-indexed offsets and permutation;
+    // then the point's own record and the list entries together; then the
+    // neighbours' data.  Nothing waits on the point type before the list walk
+    // (an outer point's products are formed and discarded).
     const int32_t q = start + pt;
     const int32_t p = col_perm[q];
     const int32_t e0 = loff[q], e1 = loff[q + 1];
-    if (!live(comp, active, p)) return;
+    if (comp && !active[comp[p]]) return;  // retired component of a batch (uniform per point)
+    if (!comp && !active[0]) return;
+    // the lane's first list entry, requested before the point's own record
+    int32_t e = e0 + lane;
+    uint8_t cd = 0;
+    D2 w = {0.0, 0.0};
+    int32_t i = 0;
+    if (e < e1) {
+        cd = lcode[e];
+        w = lw[e];
+        i = lidx[e];
+    }
     const int8_t ty = type[p];
-    if (ty == kOuter) {
-        if (FWD && lane == 0) dU[p] = {T(0), T(0), T(0), T(0)};
-        return;
+    const D2 t = frame[p];
+    T dg = T(1);
+    Vec4<T> own = {T(0), T(0), T(0), T(0)};
+    if (lane == 0) {  // used after the list walk; the division waits until then
+        dg = Dg[p];
+        if (FWD) {
+            const D4 r = R[p];
+            own = {T(r.x), T(r.y), T(r.z), T(r.w)};
+        } else {
+            own = dU[p];
+        }
     }
     T acc[4] = {T(0), T(0), T(0), T(0)};
-    const D2 t = frame[p];
-    for (int32_t e = e0 + lane; e < e1; e += LANES)
-        sweep_contrib<T, MODE>(lcode[e], t, lw[e], lidx[e], jv0, jv1, jv2, U, dU, gamma, acc);
+    while (e < e1) {
+        // the next entry is requested before this one's neighbour data is used;
+        // past the end the last entry is re-read (in bounds) and not used
+        const int32_t en = e + LANES;
+        const int32_t ec = en < e1 ? en : e1 - 1;
+        const uint8_t cdn = lcode[ec];
+        const D2 wn = lw[ec];
+        const int32_t in = lidx[ec];
+        sweep_contrib<T, MODE>(cd, t, w, i, jv0, jv1, jv2, U, dU, gamma, acc);
+        cd = cdn;
+        w = wn;
+        i = in;
+        e = en;
+    }
 #pragma unroll
     for (int o = LANES / 2; o > 0; o >>= 1)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] += __shfl_xor(acc[v], o, 64);
     if (lane != 0) return;
-    const T iD = T(1) / Dg[p];
+    if (ty == kOuter) {
+        if (FWD) dU[p] = {T(0), T(0), T(0), T(0)};
+        return;
+    }
+    const T iD = T(1) / dg;
     T out[4];
     if (FWD) {
-        const D4 r = R[p];
-        out[0] = -(T(r.x) + acc[0]) * iD;
-        out[1] = -(T(r.y) + acc[1]) * iD;
-        out[2] = -(T(r.z) + acc[2]) * iD;
-        out[3] = -(T(r.w) + acc[3]) * iD;
+        out[0] = -(own.x + acc[0]) * iD;
+        out[1] = -(own.y + acc[1]) * iD;
+        out[2] = -(own.z + acc[2]) * iD;
+        out[3] = -(own.w + acc[3]) * iD;
     } else {
-        const Vec4<T> d0 = dU[p];
-        out[0] = d0.x - acc[0] * iD;
-        out[1] = d0.y - acc[1] * iD;
-        out[2] = d0.z - acc[2] * iD;
-        out[3] = d0.w - acc[3] * iD;
+        out[0] = own.x - acc[0] * iD;
+        out[1] = own.y - acc[1] * iD;
+        out[2] = own.z - acc[2] * iD;
+        out[3] = own.w - acc[3] * iD;
     }
     if (ty == kWall) {
         const T nx = T(-t.y), ny = T(t.x);
