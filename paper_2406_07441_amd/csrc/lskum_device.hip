@@ -287,6 +287,25 @@ __device__ __forceinline__ double lane_sum(double v) {
     return v;
 }
 
+// Neighbour data of the q-derivative sums: position, q and (defect
+// correction passes) the current derivatives.
+struct QNbr {
+    D2 r;
+    D4 q, gx, gy;
+};
+
+template <bool INNER>
+__device__ __forceinline__ QNbr load_qnbr(int32_t i, const D2* __restrict__ xy,
+                                          const D4* __restrict__ q, const D4* __restrict__ qx,
+                                          const D4* __restrict__ qy) {
+    QNbr nb{xy[i], q[i], {}, {}};
+    if (INNER) {
+        nb.gx = qx[i];
+        nb.gy = qy[i];
+    }
+    return nb;
+}
+
 template <bool INNER, bool LIMIT, int LANES>
 __global__ void __launch_bounds__(kBlock) k_qgrad(
     int64_t n, double K, const D2* __restrict__ xy, const int32_t* __restrict__ off,
@@ -309,31 +328,41 @@ __global__ void __launch_bounds__(kBlock) k_qgrad(
     }
     double bx[4] = {0, 0, 0, 0}, by[4] = {0, 0, 0, 0};
     double dmax[4] = {0, 0, 0, 0}, dmin[4] = {0, 0, 0, 0};
-    const int32_t e0 = off[p], e1 = off[p + 1];
-    for (int32_t e = e0 + lane; e < e1; e += LANES) {
-        const int32_t i = idx[e];
-        const D2 ri = xy[i];
-        const double dx = ri.x - r0.x, dy = ri.y - r0.y;
-        const D4 qi = q[i];
-        double dq[4] = {qi.x - qv[0], qi.y - qv[1], qi.z - qv[2], qi.w - qv[3]};
-        if (LIMIT) {
+    // both neighbour walks are software-pipelined: indices two entries ahead,
+    // neighbour data one entry ahead of the one being used; past the end the
+    // last entry is re-read (in bounds) and not used
+    const int32_t e0 = off[p], e1 = off[p + 1], last = e1 - 1;
+    if (e0 + lane < e1) {
+        int32_t e = e0 + lane;
+        int32_t i_next = idx[min(e + LANES, last)];
+        QNbr cur = load_qnbr<INNER>(idx[e], xy, q, qx_in, qy_in);
+        for (; e < e1; e += LANES) {
+            const int32_t i_after = idx[min(e + 2 * LANES, last)];
+            const QNbr nxt = load_qnbr<INNER>(i_next, xy, q, qx_in, qy_in);
+            const double dx = cur.r.x - r0.x, dy = cur.r.y - r0.y;
+            const D4 qi = cur.q;
+            double dq[4] = {qi.x - qv[0], qi.y - qv[1], qi.z - qv[2], qi.w - qv[3]};
+            if (LIMIT) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    dmax[v] = fmax(dmax[v], dq[v]);
+                    dmin[v] = fmin(dmin[v], dq[v]);
+                }
+            }
+            if (INNER) {
+                const D4 gxi = cur.gx, gyi = cur.gy;
+                dq[0] -= 0.5 * (dx * (gxi.x - gx0.x) + dy * (gyi.x - gy0.x));
+                dq[1] -= 0.5 * (dx * (gxi.y - gx0.y) + dy * (gyi.y - gy0.y));
+                dq[2] -= 0.5 * (dx * (gxi.z - gx0.z) + dy * (gyi.z - gy0.z));
+                dq[3] -= 0.5 * (dx * (gxi.w - gx0.w) + dy * (gyi.w - gy0.w));
+            }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                dmax[v] = fmax(dmax[v], dq[v]);
-                dmin[v] = fmin(dmin[v], dq[v]);
+                bx[v] += dx * dq[v];
+                by[v] += dy * dq[v];
             }
-        }
-        if (INNER) {
-            const D4 gxi = qx_in[i], gyi = qy_in[i];
-            dq[0] -= 0.5 * (dx * (gxi.x - gx0.x) + dy * (gyi.x - gy0.x));
-            dq[1] -= 0.5 * (dx * (gxi.y - gx0.y) + dy * (gyi.y - gy0.y));
-            dq[2] -= 0.5 * (dx * (gxi.z - gx0.z) + dy * (gyi.z - gy0.z));
-            dq[3] -= 0.5 * (dx * (gxi.w - gx0.w) + dy * (gyi.w - gy0.w));
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            bx[v] += dx * dq[v];
-            by[v] += dy * dq[v];
+            cur = nxt;
+            i_next = i_after;
         }
     }
 #pragma unroll
@@ -364,20 +393,28 @@ __global__ void __launch_bounds__(kBlock) k_qgrad(
     const double kh = K * L.w;
     const double eps2 = kh * kh * kh;
     double fn[4] = {1, 1, 1, 1}, fd[4] = {1, 1, 1, 1};  // running minimum fn/fd
-    for (int32_t e = e0 + lane; e < e1; e += LANES) {
-        const D2 ri = xy[idx[e]];
-        const double dx = ri.x - r0.x, dy = ri.y - r0.y;
+    if (e0 + lane < e1) {
+        int32_t e = e0 + lane;
+        int32_t i_next = idx[min(e + LANES, last)];
+        D2 ri = xy[idx[e]];
+        for (; e < e1; e += LANES) {
+            const int32_t i_after = idx[min(e + 2 * LANES, last)];
+            const D2 rn = xy[i_next];
+            const double dx = ri.x - r0.x, dy = ri.y - r0.y;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const double d2 = -0.5 * (dx * gx[v] + dy * gy[v]);
-            if (d2 == 0.0) continue;
-            const double d1 = d2 > 0.0 ? dmax[v] : dmin[v];
-            const double nu = d1 * d1 + eps2 + 2.0 * d1 * d2;
-            const double de = d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2;
-            if (nu * fd[v] < fn[v] * de) {
-                fn[v] = nu;
-                fd[v] = de;
+            for (int v = 0; v < 4; ++v) {
+                const double d2 = -0.5 * (dx * gx[v] + dy * gy[v]);
+                if (d2 == 0.0) continue;
+                const double d1 = d2 > 0.0 ? dmax[v] : dmin[v];
+                const double nu = d1 * d1 + eps2 + 2.0 * d1 * d2;
+                const double de = d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2;
+                if (nu * fd[v] < fn[v] * de) {
+                    fn[v] = nu;
+                    fd[v] = de;
+                }
             }
+            ri = rn;
+            i_next = i_after;
         }
     }
 #pragma unroll
@@ -430,6 +467,66 @@ __device__ __forceinline__ void unsplit_jvp(const D4& u, const double dv[4], dou
     J[3] = (dv[3] + pd) * ud + (u.w + p) * udd;
 }
 
+// Neighbour data of one stencil pair of the residual.
+struct Nbr {
+    D2 r;
+    D4 q, gx, gy;
+};
+
+__device__ __forceinline__ Nbr load_nbr(int32_t i, const D2* __restrict__ xy,
+                                        const D4* __restrict__ q, const D4* __restrict__ qx,
+                                        const D4* __restrict__ qy) {
+    return {xy[i], q[i], qx[i], qy[i]};
+}
+
+// One (point, neighbour) pair of the residual sum (eq. 11): the q~
+// reconstructions at both ends (eq. 15), their primitive states and the split
+// flux differences of every split the neighbour lies in (x+-/y+- at interior
+// points, t+-/n- at a wall), weighted by the point's split coefficients.
+__device__ __forceinline__ void residual_pair(int8_t ty, const D2& t, const D2& r0, const D4& q0,
+                                              const D4& gx0, const D4& gy0, const D2& c0,
+                                              const D2& c1, const D2& c2, const D2& c3,
+                                              const Nbr& nb, double inv_gm1, bool g14,
+                                              double Rp[4], int& bad) {
+    const double dx = nb.r.x - r0.x, dy = nb.r.y - r0.y;
+    const D4 qi = nb.q, gxi = nb.gx, gyi = nb.gy;
+    const D4 qti = {qi.x - 0.5 * (dx * gxi.x + dy * gyi.x), qi.y - 0.5 * (dx * gxi.y + dy * gyi.y),
+                    qi.z - 0.5 * (dx * gxi.z + dy * gyi.z), qi.w - 0.5 * (dx * gxi.w + dy * gyi.w)};
+    const D4 qt0 = {q0.x - 0.5 * (dx * gx0.x + dy * gy0.x), q0.y - 0.5 * (dx * gx0.y + dy * gy0.y),
+                    q0.z - 0.5 * (dx * gx0.z + dy * gy0.z), q0.w - 0.5 * (dx * gx0.w + dy * gy0.w)};
+    if (ty == kWall) {
+        const double ds = dot_nc(dx, dy, t.x, t.y);
+        const double dn = dot_nc(dx, dy, -t.y, t.x);
+        const bool in_t = ds != 0.0, in_n = dn > 0.0;
+        if (!in_t && !in_n) return;
+        bad |= !(qti.w < 0.0) || !(qt0.w < 0.0);
+        const Prim wi = prim_from_q(qti, inv_gm1, g14);
+        const Prim w0 = prim_from_q(qt0, inv_gm1, g14);
+        if (in_t) {
+            const D2 c = ds < 0.0 ? c0 : c1;
+            const double sg = ds < 0.0 ? 1.0 : -1.0;
+            acc_split_diff<2>(wi, w0, t.x, t.y, sg, c.x * ds + c.y * dn, inv_gm1, Rp);
+        }
+        if (in_n) acc_split_diff<2>(wi, w0, -t.y, t.x, -1.0, c2.x * dn + c2.y * ds, inv_gm1, Rp);
+        return;
+    }
+    const bool in_x = dx != 0.0, in_y = dy != 0.0;
+    if (!in_x && !in_y) return;
+    bad |= !(qti.w < 0.0) || !(qt0.w < 0.0);
+    const Prim wi = prim_from_q(qti, inv_gm1, g14);
+    const Prim w0 = prim_from_q(qt0, inv_gm1, g14);
+    if (in_x) {
+        const D2 c = dx < 0.0 ? c0 : c1;
+        const double sg = dx < 0.0 ? 1.0 : -1.0;
+        acc_split_diff<0>(wi, w0, 1.0, 0.0, sg, c.x * dx + c.y * dy, inv_gm1, Rp);
+    }
+    if (in_y) {
+        const D2 c = dy < 0.0 ? c2 : c3;
+        const double sg = dy < 0.0 ? 1.0 : -1.0;
+        acc_split_diff<1>(wi, w0, 0.0, 1.0, sg, c.x * dy + c.y * dx, inv_gm1, Rp);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Residual (eq. 11 with the q~ reconstruction of eq. 15), local time step,
 // scalar diagonal (eq. 25, 34-35) and the sweep linearisation data.
@@ -466,50 +563,21 @@ __global__ void __launch_bounds__(kBlock) k_residual(
             const PointGeom& G = geom[p];
             const D2 c0 = G.split[0], c1 = G.split[1], c2 = G.split[2], c3 = G.split[3];
             const int32_t e1 = off[p + 1];
-            for (int32_t e = off[p] + lane; e < e1; e += LANES) {
-                const int32_t i = idx[e];
-                const D2 ri = xy[i];
-                const double dx = ri.x - r0.x, dy = ri.y - r0.y;
-                const D4 qi = q[i], gxi = qx[i], gyi = qy[i];
-                const D4 qti = {qi.x - 0.5 * (dx * gxi.x + dy * gyi.x),
-                                qi.y - 0.5 * (dx * gxi.y + dy * gyi.y),
-                                qi.z - 0.5 * (dx * gxi.z + dy * gyi.z),
-                                qi.w - 0.5 * (dx * gxi.w + dy * gyi.w)};
-                const D4 qt0 = {q0.x - 0.5 * (dx * gx0.x + dy * gy0.x),
-                                q0.y - 0.5 * (dx * gx0.y + dy * gy0.y),
-                                q0.z - 0.5 * (dx * gx0.z + dy * gy0.z),
-                                q0.w - 0.5 * (dx * gx0.w + dy * gy0.w)};
-                if (ty == kWall) {
-                    const double ds = dot_nc(dx, dy, t.x, t.y);
-                    const double dn = dot_nc(dx, dy, -t.y, t.x);
-                    const bool in_t = ds != 0.0, in_n = dn > 0.0;
-                    if (!in_t && !in_n) continue;
-                    bad |= !(qti.w < 0.0) || !(qt0.w < 0.0);
-                    const Prim wi = prim_from_q(qti, inv_gm1, g14);
-                    const Prim w0 = prim_from_q(qt0, inv_gm1, g14);
-                    if (in_t) {
-                        const D2 c = ds < 0.0 ? c0 : c1;
-                        const double sg = ds < 0.0 ? 1.0 : -1.0;
-                        acc_split_diff<2>(wi, w0, t.x, t.y, sg, c.x * ds + c.y * dn, inv_gm1, Rp);
-                    }
-                    if (in_n)
-                        acc_split_diff<2>(wi, w0, -t.y, t.x, -1.0, c2.x * dn + c2.y * ds, inv_gm1, Rp);
-                } else {
-                    const bool in_x = dx != 0.0, in_y = dy != 0.0;
-                    if (!in_x && !in_y) continue;
-                    bad |= !(qti.w < 0.0) || !(qt0.w < 0.0);
-                    const Prim wi = prim_from_q(qti, inv_gm1, g14);
-                    const Prim w0 = prim_from_q(qt0, inv_gm1, g14);
-                    if (in_x) {
-                        const D2 c = dx < 0.0 ? c0 : c1;
-                        const double sg = dx < 0.0 ? 1.0 : -1.0;
-                        acc_split_diff<0>(wi, w0, 1.0, 0.0, sg, c.x * dx + c.y * dy, inv_gm1, Rp);
-                    }
-                    if (in_y) {
-                        const D2 c = dy < 0.0 ? c2 : c3;
-                        const double sg = dy < 0.0 ? 1.0 : -1.0;
-                        acc_split_diff<1>(wi, w0, 0.0, 1.0, sg, c.x * dy + c.y * dx, inv_gm1, Rp);
-                    }
+            int32_t e = off[p] + lane;
+            if (e < e1) {
+                // software pipeline: neighbour indices two entries ahead and
+                // neighbour data one entry ahead of the pair being computed;
+                // past the end the last entry is re-read (in bounds), unused
+                const int32_t last = e1 - 1;
+                int32_t i_next = idx[min(e + LANES, last)];
+                Nbr cur = load_nbr(idx[e], xy, q, qx, qy);
+                for (; e < e1; e += LANES) {
+                    const int32_t i_after = idx[min(e + 2 * LANES, last)];
+                    const Nbr nxt = load_nbr(i_next, xy, q, qx, qy);
+                    residual_pair(ty, t, r0, q0, gx0, gy0, c0, c1, c2, c3, cur, inv_gm1, g14, Rp,
+                                  bad);
+                    cur = nxt;
+                    i_next = i_after;
                 }
             }
         }
