@@ -76,6 +76,67 @@ def forward_sweep_bytes(cloud, colours) -> tuple[float, int]:
     return float(swept * SWEEP_POINT_BYTES + lower * SWEEP_ENTRY_BYTES), int(colours.max())
 
 
+def iteration_bytes(cloud, colours) -> float:
+    """Algorithmic bytes of one whole iteration (m = 1 with the limiter), each
+    array read or written once, neighbour data counted once per pass:
+    q-derivative pass 0 (q 32, xy 16, offsets 8, LS matrix 32, 4 per stencil
+    entry, q_x/q_y write 64), the limited inner pass (q, q_x, q_y 96, xy 16,
+    offsets 8, LS matrix 32, 4 per entry, four derivative writes 128), the
+    residual (q, limited q_x, q_y 96, xy 16, frame 16, type 1, offsets 8,
+    split and diagonal coefficients 128, U 32, 4 per entry; R 32, R_rho^2 8,
+    linearisation data 96, D 8 written), the norm (8), both sweeps as above
+    and the update (U read and written 64, dU 32, q written 32)."""
+    import numpy as np
+    deg = np.diff(cloud.nbr_off).astype(np.int64)
+    src = np.repeat(np.arange(cloud.n), deg)
+    lower = int(np.count_nonzero(colours[cloud.nbr_idx] < colours[src]))
+    upper = cloud.nnz - lower
+    per_point = (152 + 280 + 441 + 8 + 2 * SWEEP_POINT_BYTES + 128)
+    return float(cloud.n * per_point + 3 * 4 * cloud.nnz + SWEEP_ENTRY_BYTES * (lower + upper))
+
+
+def large_cloud_run(lk, cloudgen, steps: int):
+    """The 2,621,440-point cloud (M 0.5, AoA 3 deg, the benchmark's solver
+    settings), FP64 and mixed precision: graph-replayed iterations from the
+    free stream, HIP-event phase times and the bandwidth figures; its working
+    set is larger than the 256 MB Infinity Cache."""
+    cloud = cloudgen.cloud_2621440()
+    gc = lk.Cloud(cloud)
+    colours = gc.colours()
+    it_bytes = iteration_bytes(cloud, colours)
+    fwd_b, fwd_launches = forward_sweep_bytes(cloud, colours)
+    flops = residual_flops(cloud)
+    out = {"points": cloud.n, "edges": cloud.nnz, "colours": gc.n_colours,
+           "iteration_bytes": it_bytes}
+    for name, prec in (("fp64", lk.FP64), ("mixed", lk.MIXED)):
+        prm = lk.default_params(cfl=CFL, inner_iters=INNER, precision=prec, check_every=10,
+                                tol_rel=0.0, max_iters=10, limiter=LIMITER, limiter_k=LIMITER_K)
+        st = lk.State(gc, 0.5, 3.0, prm)
+        st.solve()
+        prm.max_iters = steps
+        st.set_params(prm)
+        rep = st.solve()
+        ms = 1e3 * rep.seconds / rep.iters
+        acc = None
+        for _ in range(10):
+            ph = st.step_timed()
+            acc = ph if acc is None else {k: acc[k] + ph[k] for k in acc}
+        phases = {k: v / 10 for k, v in acc.items()}
+        st.close()
+        sweep_gbs = fwd_b / (phases["forward_sweep"] * 1e-3) / 1e9
+        it_gbs = it_bytes / (ms * 1e-3) / 1e9
+        out[name] = {
+            "iters": rep.iters, "ms_per_iter": ms,
+            "point_iters_per_s": cloud.n / (ms * 1e-3), "phases_ms": phases,
+            "iteration_gbs": it_gbs, "iteration_frac_hbm": it_gbs / PEAK_HBM_GBS,
+            "forward_sweep_gbs": sweep_gbs, "forward_sweep_frac_hbm": sweep_gbs / PEAK_HBM_GBS,
+            "forward_sweep_launches": fwd_launches,
+            "residual_tflops": flops / (phases["residual"] * 1e-3) / 1e12}
+        print(f"# 2.6M {name}: {ms:.3f} ms/iteration, whole iteration {it_gbs:.0f} GB/s, "
+              f"forward sweep {sweep_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    return out
+
+
 def device_source_hash() -> str:
     src = os.path.join(ROOT, "paper_2406_07441_amd", "csrc", "lskum_device.hip")
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
@@ -409,6 +470,8 @@ def main():
                     help="held-out conditions of the warm-start leg")
     ap.add_argument("--batch-converge-iters", type=int, default=0,
                     help="solve the 64-condition batch to 1e-8 with this cap (0 skips)")
+    ap.add_argument("--large-steps", type=int, default=200,
+                    help="graph-replayed iterations of the 2,621,440-point bandwidth leg (0 skips)")
     ap.add_argument("--config3-iters", type=int, default=0,
                     help="2,621,440-point FP64 vs mixed run to 1e-8 with this cap (0 skips)")
     ap.add_argument("--profile-only", action="store_true",
@@ -496,6 +559,10 @@ def main():
                        "ms_per_step": res_ms},
     }
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    it_bytes = iteration_bytes(cloud, gc.colours())
+    it_gbs = it_bytes / (ms_per_step * 1e-3) / 1e9
+    iteration_bw = {"bytes_per_iteration": it_bytes, "achieved_gbs": it_gbs,
+                    "peak_gbs": PEAK_HBM_GBS, "frac": it_gbs / PEAK_HBM_GBS}
     roofline = {"kernel": dom, **{k: v for k, v in kernels[dom].items()
                                   if k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}}
     if args.profile_only:
@@ -521,6 +588,8 @@ def main():
         extra["batch_64_to_1e-8"] = batch_converge(lk, cloudgen, args.batch_converge_iters)
         print(f"# batch to 1e-8: {json.dumps(extra['batch_64_to_1e-8'])}", file=sys.stderr,
               flush=True)
+    if args.large_steps > 0:
+        extra["cloud_2621440_bandwidth"] = large_cloud_run(lk, cloudgen, args.large_steps)
     if args.config3_iters > 0:
         extra["cloud_2621440_to_1e-8"] = config3_run(lk, cloudgen, args.config3_iters)
         print(f"# 2.6M: {json.dumps(extra['cloud_2621440_to_1e-8'])}", file=sys.stderr, flush=True)
@@ -539,7 +608,7 @@ def main():
                                "limiter K5",
                    "points": cloud.n, "edges": cloud.nnz, "colours": ncol},
         "roofline": roofline, "roofline_kernels": kernels, "cpu_baseline": cpu,
-        "phases_ms": phases, **extra,
+        "iteration_bandwidth": iteration_bw, "phases_ms": phases, **extra,
     }
     print(json.dumps(line))
 

@@ -306,8 +306,12 @@ __device__ __forceinline__ QNbr load_qnbr(int32_t i, const D2* __restrict__ xy,
     return nb;
 }
 
+constexpr int kDxyCache = 8;  // limiter: LDS slots per thread for neighbour offsets
+
+// Four workgroups per CU: the limited pass fits 128 VGPRs (four wavefronts
+// per SIMD), which measured faster than three wavefronts without the bound.
 template <bool INNER, bool LIMIT, int LANES>
-__global__ void __launch_bounds__(kBlock) k_qgrad(
+__global__ void __launch_bounds__(kBlock, 4) k_qgrad(
     int64_t n, double K, const D2* __restrict__ xy, const int32_t* __restrict__ off,
     const int32_t* __restrict__ idx, const PointGeom* __restrict__ geom,
     const int32_t* __restrict__ comp, const int32_t* __restrict__ active,
@@ -331,15 +335,19 @@ __global__ void __launch_bounds__(kBlock) k_qgrad(
     // both neighbour walks are software-pipelined: indices two entries ahead,
     // neighbour data one entry ahead of the one being used; past the end the
     // last entry is re-read (in bounds) and not used
+    // with the limiter, a lane keeps the offsets of its first kDxyCache
+    // entries in LDS for the second walk
+    __shared__ D2 dxy_cache[LIMIT ? kDxyCache * kBlock : 1];
     const int32_t e0 = off[p], e1 = off[p + 1], last = e1 - 1;
     if (e0 + lane < e1) {
         int32_t e = e0 + lane;
         int32_t i_next = idx[min(e + LANES, last)];
         QNbr cur = load_qnbr<INNER>(idx[e], xy, q, qx_in, qy_in);
-        for (; e < e1; e += LANES) {
+        for (int k = 0; e < e1; e += LANES, ++k) {
             const int32_t i_after = idx[min(e + 2 * LANES, last)];
             const QNbr nxt = load_qnbr<INNER>(i_next, xy, q, qx_in, qy_in);
             const double dx = cur.r.x - r0.x, dy = cur.r.y - r0.y;
+            if (LIMIT && k < kDxyCache) dxy_cache[k * kBlock + threadIdx.x] = {dx, dy};
             const D4 qi = cur.q;
             double dq[4] = {qi.x - qv[0], qi.y - qv[1], qi.z - qv[2], qi.w - qv[3]};
             if (LIMIT) {
@@ -393,28 +401,29 @@ __global__ void __launch_bounds__(kBlock) k_qgrad(
     const double kh = K * L.w;
     const double eps2 = kh * kh * kh;
     double fn[4] = {1, 1, 1, 1}, fd[4] = {1, 1, 1, 1};  // running minimum fn/fd
-    if (e0 + lane < e1) {
-        int32_t e = e0 + lane;
-        int32_t i_next = idx[min(e + LANES, last)];
-        D2 ri = xy[idx[e]];
-        for (; e < e1; e += LANES) {
-            const int32_t i_after = idx[min(e + 2 * LANES, last)];
-            const D2 rn = xy[i_next];
-            const double dx = ri.x - r0.x, dy = ri.y - r0.y;
+    int k = 0;
+    for (int32_t e = e0 + lane; e < e1; e += LANES, ++k) {
+        double dx, dy;
+        if (k < kDxyCache) {  // written by this thread in the first walk
+            const D2 d = dxy_cache[k * kBlock + threadIdx.x];
+            dx = d.x;
+            dy = d.y;
+        } else {
+            const D2 ri = xy[idx[e]];
+            dx = ri.x - r0.x;
+            dy = ri.y - r0.y;
+        }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const double d2 = -0.5 * (dx * gx[v] + dy * gy[v]);
-                if (d2 == 0.0) continue;
-                const double d1 = d2 > 0.0 ? dmax[v] : dmin[v];
-                const double nu = d1 * d1 + eps2 + 2.0 * d1 * d2;
-                const double de = d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2;
-                if (nu * fd[v] < fn[v] * de) {
-                    fn[v] = nu;
-                    fd[v] = de;
-                }
+        for (int v = 0; v < 4; ++v) {
+            const double d2 = -0.5 * (dx * gx[v] + dy * gy[v]);
+            if (d2 == 0.0) continue;
+            const double d1 = d2 > 0.0 ? dmax[v] : dmin[v];
+            const double nu = d1 * d1 + eps2 + 2.0 * d1 * d2;
+            const double de = d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2;
+            if (nu * fd[v] < fn[v] * de) {
+                fn[v] = nu;
+                fd[v] = de;
             }
-            ri = rn;
-            i_next = i_after;
         }
     }
 #pragma unroll
