@@ -59,6 +59,7 @@ void free_cloud(lskum::Cloud& c) {
     void* ptrs[] = {c.xy,     c.frame,     c.type,   c.off,      c.idx,      c.colour,
                     c.col_perm, c.wall_list, c.geom, c.lo_off,   c.lo_idx,   c.up_off,
                     c.up_idx, c.lo_w,      c.up_w,     c.lo_code,  c.up_code,  c.comp,
+                    c.lo_wf, c.up_wf,
                     c.comp_off, c.wall_off, c.comp_inv_active,
                     c.comp_orient, c.chunk_start, c.chunk_comp, c.comp_chunk_off};
     for (void* p : ptrs) (void)hipFree(p);
@@ -230,6 +231,8 @@ int upload_cloud(lskum::Cloud& c) {
     chk(dalloc(&c.up_idx, up_idx.size()));
     chk(dalloc(&c.lo_w, lo_idx.size()));
     chk(dalloc(&c.up_w, up_idx.size()));
+    chk(dalloc(&c.lo_wf, lo_idx.size()));
+    chk(dalloc(&c.up_wf, up_idx.size()));
     chk(dalloc(&c.lo_code, lo_idx.size()));
     chk(dalloc(&c.up_code, up_idx.size()));
     chk(dalloc(&c.comp_off, c.ncomp + 1));

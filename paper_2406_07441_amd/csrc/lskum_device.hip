@@ -902,6 +902,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_weights(int64_t n,
                                                           const int32_t* __restrict__ off,
                                                           const int32_t* __restrict__ idx,
                                                           D2* __restrict__ w,
+                                                          F2* __restrict__ wf,
                                                           uint8_t* __restrict__ code) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
@@ -940,6 +941,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_weights(int64_t n,
             }
         }
         w[e] = {wa, wb};
+        wf[e] = {(float)wa, (float)wb};
         code[e] = cd;
     }
 }
@@ -949,7 +951,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_weights(int64_t n,
 // use the x and y split the neighbour falls in, wall points the t split and,
 // on the fluid side, the n- split (wall frame t of point p).
 template <class T, int MODE>
-__device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const D2& w, int32_t i,
+__device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<T>& w, int32_t i,
                                               const Vec4<T>* __restrict__ jv0,
                                               const Vec4<T>* __restrict__ jv1,
                                               const Vec4<T>* __restrict__ jv2,
@@ -1028,7 +1030,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
     int32_t start, int32_t count, const int32_t* __restrict__ col_perm,
     const D2* __restrict__ frame, const int8_t* __restrict__ type,
     const int32_t* __restrict__ loff, const int32_t* __restrict__ lidx,
-    const D2* __restrict__ lw, const uint8_t* __restrict__ lcode,
+    const W2<T>* __restrict__ lw, const uint8_t* __restrict__ lcode,
     const int32_t* __restrict__ comp, const int32_t* __restrict__ active,
     const Vec4<T>* __restrict__ jv0, const Vec4<T>* __restrict__ jv1,
     const Vec4<T>* __restrict__ jv2, const D4* __restrict__ U, const D4* __restrict__ R,
@@ -1049,7 +1051,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
     // the lane's first list entry, requested before the point's own record
     int32_t e = e0 + lane;
     uint8_t cd = 0;
-    D2 w = {0.0, 0.0};
+    W2<T> w = {T(0), T(0)};
     int32_t i = 0;
     if (e < e1) {
         cd = lcode[e];
@@ -1076,7 +1078,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
         const int32_t en = e + LANES;
         const int32_t ec = en < e1 ? en : e1 - 1;
         const uint8_t cdn = lcode[ec];
-        const D2 wn = lw[ec];
+        const W2<T> wn = lw[ec];
         const int32_t in = lidx[ec];
         sweep_contrib<T, MODE>(cd, t, w, i, jv0, jv1, jv2, U, dU, gamma, acc);
         cd = cdn;
@@ -1263,10 +1265,10 @@ hipError_t launch_sweep_weights(Cloud& c, hipStream_t st) {
     if (c.n > 0) {
         hipLaunchKernelGGL(k_sweep_weights, dim3(grid_for(c.n)), dim3(kBlock), 0, st, c.n,
                            c.col_perm, c.xy, c.frame, c.type, c.geom, c.lo_off, c.lo_idx, c.lo_w,
-                           c.lo_code);
+                           c.lo_wf, c.lo_code);
         hipLaunchKernelGGL(k_sweep_weights, dim3(grid_for(c.n)), dim3(kBlock), 0, st, c.n,
                            c.col_perm, c.xy, c.frame, c.type, c.geom, c.up_off, c.up_idx, c.up_w,
-                           c.up_code);
+                           c.up_wf, c.up_code);
     }
     return hipGetLastError();
 }
@@ -1404,6 +1406,13 @@ static std::vector<std::pair<int32_t, int32_t>> sweep_phases(const State& s, boo
     return ph;
 }
 
+// The sweep-list weights in the sweep arithmetic's precision.
+template <class T>
+static const W2<T>* list_weights(const D2* w, const F2* wf) {
+    if constexpr (std::is_same_v<T, float>) return wf;
+    else return w;
+}
+
 template <class T, int MODE, int LANES>
 static void sweep_lanes(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv1,
                         const Vec4<T>* jv2, const T* Dg, Vec4<T>* dU) {
@@ -1413,14 +1422,15 @@ static void sweep_lanes(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T
         const dim3 g(grid_for((int64_t)cnt * LANES)), b(kBlock);
         if (forward)
             hipLaunchKernelGGL((k_sweep<T, true, MODE, LANES>), g, b, 0, s.stream, start, cnt,
-                               c.col_perm, c.frame, c.type, c.lo_off, c.lo_idx, c.lo_w,
-                               c.lo_code, c.comp, s.active, jv0, jv1, jv2, s.U,
-                               s.prm.variant ? s.Rs : s.R, Dg, dU, s.prm.gamma);
+                               c.col_perm, c.frame, c.type, c.lo_off, c.lo_idx,
+                               list_weights<T>(c.lo_w, c.lo_wf), c.lo_code, c.comp, s.active,
+                               jv0, jv1, jv2, s.U, s.prm.variant ? s.Rs : s.R, Dg, dU,
+                               s.prm.gamma);
         else
             hipLaunchKernelGGL((k_sweep<T, false, MODE, LANES>), g, b, 0, s.stream, start, cnt,
-                               c.col_perm, c.frame, c.type, c.up_off, c.up_idx, c.up_w,
-                               c.up_code, c.comp, s.active, jv0, jv1, jv2, s.U, s.R, Dg, dU,
-                               s.prm.gamma);
+                               c.col_perm, c.frame, c.type, c.up_off, c.up_idx,
+                               list_weights<T>(c.up_w, c.up_wf), c.up_code, c.comp, s.active,
+                               jv0, jv1, jv2, s.U, s.R, Dg, dU, s.prm.gamma);
     }
 }
 

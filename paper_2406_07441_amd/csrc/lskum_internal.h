@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 namespace lskum {
@@ -21,6 +22,12 @@ using F4 = Vec4<float>;
 struct alignas(16) D2 {
     double x, y;
 };
+struct alignas(8) F2 {
+    float x, y;
+};
+// sweep-list weights in the sweep arithmetic
+template <class T>
+using W2 = std::conditional_t<std::is_same_v<T, float>, F2, D2>;
 
 // Geometry precomputed once per cloud (one record per point).
 //   lsq:   inverse of the full-stencil LS normal matrix, (a11, a12, a22, rmin)
@@ -64,10 +71,12 @@ struct Cloud {
     int32_t* lo_off = nullptr;
     int32_t* lo_idx = nullptr;
     D2* lo_w = nullptr;
+    F2* lo_wf = nullptr;  // the weights rounded to fp32 (mixed-precision sweeps)
     uint8_t* lo_code = nullptr;
     int32_t* up_off = nullptr;
     int32_t* up_idx = nullptr;
     D2* up_w = nullptr;
+    F2* up_wf = nullptr;
     uint8_t* up_code = nullptr;
     // Components: a batch cloud is the disjoint union of one copy of a cloud
     // per flow condition.  Component k owns points [comp_off[k], comp_off[k+1])
