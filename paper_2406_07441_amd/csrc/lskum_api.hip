@@ -302,8 +302,8 @@ void free_state(lskum::State& s) {
     if (s.have_events)
         for (hipEvent_t ev : s.ev) (void)hipEventDestroy(ev);
     void* ptrs[] = {s.U,    s.q,      s.qx[0], s.qx[1],  s.qy[0],   s.qy[1],    s.qxl, s.Rs,
-                    s.qyl,  s.R,      s.dU,    s.jv0,    s.jv1,     s.jv2,      s.D,
-                    s.jv0f, s.jv1f,   s.jv2f,  s.dUf,    s.Df,      s.rr,       s.fsum, s.partial,
+                    s.qyl,  s.R,      s.dU,    s.jv0,    s.jv2,      s.D,
+                    s.jv0f, s.jv2f,  s.dUf,    s.Df,      s.rr,       s.fsum, s.partial,
                     s.res_hist, s.flags, s.active, s.status, s.iters, s.res_last, s.tol_abs,
                     s.vinf};
     for (void* p : ptrs) (void)hipFree(p);
@@ -439,11 +439,9 @@ int init_state(lskum::State& s, const lskum::Cloud& c, const lskum_params* prm,
     chk(dalloc(&s.Rs, n));
     chk(dalloc(&s.dU, n));
     chk(dalloc(&s.jv0, n));
-    chk(dalloc(&s.jv1, n));
     chk(dalloc(&s.jv2, n));
     chk(dalloc(&s.D, n));
     chk(dalloc(&s.jv0f, n));
-    chk(dalloc(&s.jv1f, n));
     chk(dalloc(&s.jv2f, n));
     chk(dalloc(&s.dUf, n));
     chk(dalloc(&s.Df, n));

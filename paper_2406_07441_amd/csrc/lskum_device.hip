@@ -551,8 +551,8 @@ __global__ void __launch_bounds__(kBlock) k_residual(
     const int32_t* __restrict__ comp, const int32_t* __restrict__ active,
     const D4* __restrict__ U, const D4* __restrict__ q, const D4* __restrict__ qx,
     const D4* __restrict__ qy, D4* __restrict__ R, double* __restrict__ Dg,
-    D4* __restrict__ jv0, D4* __restrict__ jv1, D4* __restrict__ jv2, F4* __restrict__ jv0f,
-    F4* __restrict__ jv1f, F4* __restrict__ jv2f, float* __restrict__ Df,
+    D4* __restrict__ jv0, D4* __restrict__ jv2, F4* __restrict__ jv0f, F4* __restrict__ jv2f,
+    float* __restrict__ Df,
     double* __restrict__ rr_out, int32_t* __restrict__ flags, int variant, int fd,
     D4* dUio, F4* dUfio, D4* __restrict__ Rs, const int32_t* __restrict__ colour, int sweep0) {
     const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -616,7 +616,6 @@ __global__ void __launch_bounds__(kBlock) k_residual(
             const double sb = sqrt(beta);
             const double sx = u1 * sb, sy = u2 * sb;
             const D4 j0 = {rho, u1, u2, pr};
-            const D4 j1 = {sb, beta, irho, 1.0 / pr};
             const D4 j2 = {erf(sx), exp(-(sx * sx)), erf(sy), exp(-(sy * sy))};
             const double a = sqrt(gamma * pr / rho);
             const PointGeom& G = geom[p];
@@ -685,12 +684,10 @@ __global__ void __launch_bounds__(kBlock) k_residual(
             }
             if (MIXED) {
                 jv0f[p] = {(float)j0.x, (float)j0.y, (float)j0.z, (float)j0.w};
-                jv1f[p] = {(float)j1.x, (float)j1.y, (float)j1.z, (float)j1.w};
                 jv2f[p] = {(float)j2.x, (float)j2.y, (float)j2.z, (float)j2.w};
                 Df[p] = (float)Dp;
             } else {
                 jv0[p] = j0;
-                jv1[p] = j1;
                 jv2[p] = j2;
                 Dg[p] = Dp;
             }
@@ -883,10 +880,28 @@ __device__ __forceinline__ void jvp_fluxdiff(const Lin<double>& L, double er, do
     for (int v = 0; v < 4; ++v) J[v] = Ga[v] - Gb[v];
 }
 
+// The linearisation data of neighbour i from its (rho, u1, u2, p) record: the
+// derived quantities are formed here rather than read, which halves the bytes
+// a sweep gathers per neighbour for them.
+// One reciprocal, of rho p, gives both 1/rho and 1/p; the fp32 sweeps use
+// the hardware reciprocal and square root (about 1 ulp).
 template <class T>
-__device__ __forceinline__ Lin<T> load_lin(const Vec4<T>* jv0, const Vec4<T>* jv1, int32_t i) {
-    const Vec4<T> a = jv0[i], b = jv1[i];
-    return Lin<T>{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+__device__ __forceinline__ Lin<T> load_lin(const Vec4<T>* jv0, int32_t i) {
+    const Vec4<T> a = jv0[i];
+    T r, sb;
+    if constexpr (std::is_same_v<T, float>) {
+        r = __builtin_amdgcn_rcpf(a.x * a.w);
+    } else {
+        r = T(1) / (a.x * a.w);
+    }
+    const T irho = a.w * r, ip = a.x * r;
+    const T beta = T(0.5) * a.x * ip;
+    if constexpr (std::is_same_v<T, float>) {
+        sb = __builtin_amdgcn_sqrtf(beta);
+    } else {
+        sb = sqrt(beta);
+    }
+    return Lin<T>{a.x, a.y, a.z, a.w, sb, beta, irho, ip};
 }
 
 // Split weights and bits of the sweep-list entries of the colour-sorted point
@@ -953,7 +968,6 @@ __global__ void __launch_bounds__(kBlock) k_sweep_weights(int64_t n,
 template <class T, int MODE>
 __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<T>& w, int32_t i,
                                               const Vec4<T>* __restrict__ jv0,
-                                              const Vec4<T>* __restrict__ jv1,
                                               const Vec4<T>* __restrict__ jv2,
                                               const D4* __restrict__ U,
                                               const Vec4<T>* __restrict__ dU, double gamma,
@@ -961,7 +975,7 @@ __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<
     const T gm1 = T(gamma - 1.0), inv_gm1 = T(1.0 / (gamma - 1.0));
     const Vec4<T> di = dU[i];
     const T dv[4] = {di.x, di.y, di.z, di.w};
-    const Lin<T> L = load_lin(jv0, jv1, i);
+    const Lin<T> L = load_lin(jv0, i);
     const Vec4<T> k2 = jv2[i];  // interior entries only; loaded with the rest
     T J[4];
     if (cd & kSwWall) {
@@ -1032,8 +1046,8 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
     const int32_t* __restrict__ loff, const int32_t* __restrict__ lidx,
     const W2<T>* __restrict__ lw, const uint8_t* __restrict__ lcode,
     const int32_t* __restrict__ comp, const int32_t* __restrict__ active,
-    const Vec4<T>* __restrict__ jv0, const Vec4<T>* __restrict__ jv1,
-    const Vec4<T>* __restrict__ jv2, const D4* __restrict__ U, const D4* __restrict__ R,
+    const Vec4<T>* __restrict__ jv0, const Vec4<T>* __restrict__ jv2,
+    const D4* __restrict__ U, const D4* __restrict__ R,
     const T* __restrict__ Dg, Vec4<T>* __restrict__ dU, double gamma) {
     const int gt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int pt = gt / LANES, lane = gt % LANES;
@@ -1080,7 +1094,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
         const uint8_t cdn = lcode[ec];
         const W2<T> wn = lw[ec];
         const int32_t in = lidx[ec];
-        sweep_contrib<T, MODE>(cd, t, w, i, jv0, jv1, jv2, U, dU, gamma, acc);
+        sweep_contrib<T, MODE>(cd, t, w, i, jv0, jv2, U, dU, gamma, acc);
         cd = cdn;
         w = wn;
         i = in;
@@ -1340,8 +1354,8 @@ static void residual_lanes(State& s, bool in_step) {
     hipLaunchKernelGGL((k_residual<MIXED, LANES>), dim3(nb), dim3(kBlock), 0, s.stream, c.n,
                        s.prm.gamma, s.prm.cfl, c.xy, c.frame, c.type, c.off, c.idx, c.geom, c.comp,
                        s.active, s.U, s.q, s.prm.limiter ? s.qxl : s.qx[s.qsel],
-                       s.prm.limiter ? s.qyl : s.qy[s.qsel], s.R, s.D, s.jv0, s.jv1, s.jv2,
-                       s.jv0f, s.jv1f, s.jv2f, s.Df, s.rr, s.flags, s.prm.variant,
+                       s.prm.limiter ? s.qyl : s.qy[s.qsel], s.R, s.D, s.jv0, s.jv2, s.jv0f,
+                       s.jv2f, s.Df, s.rr, s.flags, s.prm.variant,
                        s.prm.jvp_mode, s.dU, s.dUf, s.Rs, c.colour,
                        in_step && fused_first_colour(s));
 }
@@ -1414,8 +1428,8 @@ static const W2<T>* list_weights(const D2* w, const F2* wf) {
 }
 
 template <class T, int MODE, int LANES>
-static void sweep_lanes(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv1,
-                        const Vec4<T>* jv2, const T* Dg, Vec4<T>* dU) {
+static void sweep_lanes(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv2,
+                        const T* Dg, Vec4<T>* dU) {
     const Cloud& c = *s.cloud;
     for (const auto& [start, cnt] : sweep_phases(s, forward)) {
         if (!cnt) continue;
@@ -1424,25 +1438,25 @@ static void sweep_lanes(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T
             hipLaunchKernelGGL((k_sweep<T, true, MODE, LANES>), g, b, 0, s.stream, start, cnt,
                                c.col_perm, c.frame, c.type, c.lo_off, c.lo_idx,
                                list_weights<T>(c.lo_w, c.lo_wf), c.lo_code, c.comp, s.active,
-                               jv0, jv1, jv2, s.U, s.prm.variant ? s.Rs : s.R, Dg, dU,
+                               jv0, jv2, s.U, s.prm.variant ? s.Rs : s.R, Dg, dU,
                                s.prm.gamma);
         else
             hipLaunchKernelGGL((k_sweep<T, false, MODE, LANES>), g, b, 0, s.stream, start, cnt,
                                c.col_perm, c.frame, c.type, c.up_off, c.up_idx,
                                list_weights<T>(c.up_w, c.up_wf), c.up_code, c.comp, s.active,
-                               jv0, jv1, jv2, s.U, s.R, Dg, dU, s.prm.gamma);
+                               jv0, jv2, s.U, s.R, Dg, dU, s.prm.gamma);
     }
 }
 
 template <class T, int MODE>
-static void sweep_t(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv1,
-                    const Vec4<T>* jv2, const T* Dg, Vec4<T>* dU) {
+static void sweep_t(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv2,
+                    const T* Dg, Vec4<T>* dU) {
     switch (s.sweep_lanes) {
-        case 1: sweep_lanes<T, MODE, 1>(s, forward, jv0, jv1, jv2, Dg, dU); break;
-        case 2: sweep_lanes<T, MODE, 2>(s, forward, jv0, jv1, jv2, Dg, dU); break;
-        case 8: sweep_lanes<T, MODE, 8>(s, forward, jv0, jv1, jv2, Dg, dU); break;
-        case 16: sweep_lanes<T, MODE, 16>(s, forward, jv0, jv1, jv2, Dg, dU); break;
-        default: sweep_lanes<T, MODE, 4>(s, forward, jv0, jv1, jv2, Dg, dU); break;
+        case 1: sweep_lanes<T, MODE, 1>(s, forward, jv0, jv2, Dg, dU); break;
+        case 2: sweep_lanes<T, MODE, 2>(s, forward, jv0, jv2, Dg, dU); break;
+        case 8: sweep_lanes<T, MODE, 8>(s, forward, jv0, jv2, Dg, dU); break;
+        case 16: sweep_lanes<T, MODE, 16>(s, forward, jv0, jv2, Dg, dU); break;
+        default: sweep_lanes<T, MODE, 4>(s, forward, jv0, jv2, Dg, dU); break;
     }
 }
 
@@ -1465,11 +1479,11 @@ hipError_t launch_sweep_dir(State& s, bool forward) {
                                c.n, s.dU);
     }
     if (s.prm.precision == 1)
-        sweep_t<float, 0>(s, forward, s.jv0f, s.jv1f, s.jv2f, s.Df, s.dUf);
+        sweep_t<float, 0>(s, forward, s.jv0f, s.jv2f, s.Df, s.dUf);
     else if (s.prm.jvp_mode == 1)
-        sweep_t<double, 1>(s, forward, s.jv0, s.jv1, s.jv2, s.D, s.dU);
+        sweep_t<double, 1>(s, forward, s.jv0, s.jv2, s.D, s.dU);
     else
-        sweep_t<double, 0>(s, forward, s.jv0, s.jv1, s.jv2, s.D, s.dU);
+        sweep_t<double, 0>(s, forward, s.jv0, s.jv2, s.D, s.dU);
     return hipGetLastError();
 }
 

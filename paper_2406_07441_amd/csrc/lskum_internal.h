@@ -156,12 +156,10 @@ struct State {
     D4* Rs = nullptr;    // forward-sweep right-hand side R - S (Manish variant)
     D4* dU = nullptr;    // increment; kept between iterations (zero after a new U)
     D4* jv0 = nullptr;   // (rho, u1, u2, p) at the state the sweeps linearise about
-    D4* jv1 = nullptr;   // (sqrt(beta), beta, 1/rho, 1/p)
     D4* jv2 = nullptr;   // (erf(Sx), exp(-Sx^2), erf(Sy), exp(-Sy^2))
     double* D = nullptr; // scalar diagonal
     // fp32 copies for the mixed-precision sweeps
     F4* jv0f = nullptr;
-    F4* jv1f = nullptr;
     F4* jv2f = nullptr;
     F4* dUf = nullptr;
     float* Df = nullptr;
