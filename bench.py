@@ -46,10 +46,14 @@ SPLIT_OPS = 3 + 2 * (25 + COST["erf"] + COST["exp"] + COST["div"]) + 12
 # Algorithmic bytes of the sweep, each array read or written once. Per swept
 # point: colour-sorted index 4, list offset 4, component 4, type 1, wall
 # frame 16, D 8, own R (forward) or dU* (backward) 32, result 32, and its
-# linearisation data (96) and increment (32) as read by its neighbours; per
-# list entry: neighbour index 4, split weights 16, split code 1.
-SWEEP_POINT_BYTES = 4 + 4 + 4 + 1 + 16 + 8 + 32 + 32 + 96 + 32
+# linearisation records ((rho, u1, u2, p) 32 and the erf/exp pairs 32) and
+# increment (32) as read by its neighbours; per list entry: neighbour index
+# 4, split weights 16, split code 1.
+SWEEP_POINT_BYTES = 4 + 4 + 4 + 1 + 16 + 8 + 32 + 32 + 64 + 32
 SWEEP_ENTRY_BYTES = 4 + 16 + 1
+# the same in mixed precision (fp32 D, increments, records and weights; R stays fp64)
+SWEEP_POINT_BYTES_F32 = 4 + 4 + 4 + 1 + 16 + 4 + 32 + 16 + 32 + 16
+SWEEP_ENTRY_BYTES_F32 = 4 + 8 + 1
 
 
 def residual_flops(cloud) -> float:
@@ -64,7 +68,7 @@ def residual_flops(cloud) -> float:
     return float(np.sum(deg[active] * (NB_OPS + splits[active] * SPLIT_OPS)))
 
 
-def forward_sweep_bytes(cloud, colours) -> tuple[float, int]:
+def forward_sweep_bytes(cloud, colours, mixed: bool = False) -> tuple[float, int]:
     """Algorithmic bytes of the forward sweep's colour-phase launches and their
     number: colours 1 and up (the colour-0 phase has no lower neighbours and is
     formed inside the residual kernel), with every lower-list entry."""
@@ -73,10 +77,12 @@ def forward_sweep_bytes(cloud, colours) -> tuple[float, int]:
     src = np.repeat(np.arange(cloud.n), deg)
     lower = int(np.count_nonzero(colours[cloud.nbr_idx] < colours[src]))
     swept = int(np.count_nonzero(colours > 0))
-    return float(swept * SWEEP_POINT_BYTES + lower * SWEEP_ENTRY_BYTES), int(colours.max())
+    pb, eb = ((SWEEP_POINT_BYTES_F32, SWEEP_ENTRY_BYTES_F32) if mixed
+              else (SWEEP_POINT_BYTES, SWEEP_ENTRY_BYTES))
+    return float(swept * pb + lower * eb), int(colours.max())
 
 
-def iteration_bytes(cloud, colours) -> float:
+def iteration_bytes(cloud, colours, mixed: bool = False) -> float:
     """Algorithmic bytes of one whole iteration (m = 1 with the limiter), each
     array read or written once, neighbour data counted once per pass:
     q-derivative pass 0 (q 32, xy 16, offsets 8, LS matrix 32, 4 per stencil
@@ -84,15 +90,21 @@ def iteration_bytes(cloud, colours) -> float:
     offsets 8, LS matrix 32, 4 per entry, four derivative writes 128), the
     residual (q, limited q_x, q_y 96, xy 16, frame 16, type 1, offsets 8,
     split and diagonal coefficients 128, U 32, 4 per entry; R 32, R_rho^2 8,
-    linearisation data 96, D 8 written), the norm (8), both sweeps as above
-    and the update (U read and written 64, dU 32, q written 32)."""
+    linearisation records 64 and D 8 written, or 32 and 4 in mixed precision),
+    the norm (8), both sweeps as above and the update (U read and written 64,
+    dU 32 or 16, q written 32)."""
     import numpy as np
     deg = np.diff(cloud.nbr_off).astype(np.int64)
     src = np.repeat(np.arange(cloud.n), deg)
     lower = int(np.count_nonzero(colours[cloud.nbr_idx] < colours[src]))
     upper = cloud.nnz - lower
-    per_point = (152 + 280 + 441 + 8 + 2 * SWEEP_POINT_BYTES + 128)
-    return float(cloud.n * per_point + 3 * 4 * cloud.nnz + SWEEP_ENTRY_BYTES * (lower + upper))
+    if mixed:
+        per_point = 152 + 280 + 373 + 8 + 2 * SWEEP_POINT_BYTES_F32 + 112
+        entry = SWEEP_ENTRY_BYTES_F32
+    else:
+        per_point = 152 + 280 + 409 + 8 + 2 * SWEEP_POINT_BYTES + 128
+        entry = SWEEP_ENTRY_BYTES
+    return float(cloud.n * per_point + 3 * 4 * cloud.nnz + entry * (lower + upper))
 
 
 def large_cloud_run(lk, cloudgen, steps: int):
@@ -103,12 +115,11 @@ def large_cloud_run(lk, cloudgen, steps: int):
     cloud = cloudgen.cloud_2621440()
     gc = lk.Cloud(cloud)
     colours = gc.colours()
-    it_bytes = iteration_bytes(cloud, colours)
-    fwd_b, fwd_launches = forward_sweep_bytes(cloud, colours)
     flops = residual_flops(cloud)
-    out = {"points": cloud.n, "edges": cloud.nnz, "colours": gc.n_colours,
-           "iteration_bytes": it_bytes}
+    out = {"points": cloud.n, "edges": cloud.nnz, "colours": gc.n_colours}
     for name, prec in (("fp64", lk.FP64), ("mixed", lk.MIXED)):
+        it_bytes = iteration_bytes(cloud, colours, mixed=prec == lk.MIXED)
+        fwd_b, fwd_launches = forward_sweep_bytes(cloud, colours, mixed=prec == lk.MIXED)
         prm = lk.default_params(cfl=CFL, inner_iters=INNER, precision=prec, check_every=10,
                                 tol_rel=0.0, max_iters=10, limiter=LIMITER, limiter_k=LIMITER_K)
         st = lk.State(gc, 0.5, 3.0, prm)
@@ -126,7 +137,7 @@ def large_cloud_run(lk, cloudgen, steps: int):
         sweep_gbs = fwd_b / (phases["forward_sweep"] * 1e-3) / 1e9
         it_gbs = it_bytes / (ms * 1e-3) / 1e9
         out[name] = {
-            "iters": rep.iters, "ms_per_iter": ms,
+            "iters": rep.iters, "ms_per_iter": ms, "iteration_bytes": it_bytes,
             "point_iters_per_s": cloud.n / (ms * 1e-3), "phases_ms": phases,
             "iteration_gbs": it_gbs, "iteration_frac_hbm": it_gbs / PEAK_HBM_GBS,
             "forward_sweep_gbs": sweep_gbs, "forward_sweep_frac_hbm": sweep_gbs / PEAK_HBM_GBS,
