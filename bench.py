@@ -219,9 +219,14 @@ def batch_run(lk, cloudgen, iters):
     lanes = b.autotune(2)
     reps, tot = b.solve()
     pts = sum(r["iters"] * b.sizes[k] for k, r in enumerate(reps))
+    # algorithmic bytes: each condition's iterations on its own cloud (mixed precision)
+    cb = [iteration_bytes(c, g.colours(), mixed=True) for c, g in zip(clouds, gcs)]
+    moved = sum(r["iters"] * cb[k % 8] for k, r in enumerate(reps))
     out = {"conditions": 64, "clouds": [c.n for c in clouds], "points": b.n_points,
            "colour_phases": b.n_colours, "iters": iters, "seconds": tot,
-           "point_iters_per_s": pts / tot, "lanes": {"sweep": lanes[0], "residual": lanes[1]},
+           "point_iters_per_s": pts / tot, "iteration_gbs": moved / tot / 1e9,
+           "iteration_frac_hbm": moved / tot / 1e9 / PEAK_HBM_GBS,
+           "lanes": {"sweep": lanes[0], "residual": lanes[1]},
            "failed": int(sum(r["status"] == lk.ERR_NONPHYSICAL for r in reps)),
            "median_res_drop": float(np.median([r["res_final"] / r["res_fs"] for r in reps]))}
     b.close()
@@ -290,7 +295,7 @@ def batch_converge(lk, cloudgen, max_iters):
     return out
 
 
-def config3_run(lk, cloudgen, max_iters):
+def config3_run(lk, cloudgen, max_iters, precisions=("fp64", "mixed")):
     """2560 x 1024 cloud, M 0.5, AoA 3 deg: FP64 against mixed precision to 1e-8
     (limiter on: without it the impulsive start goes non-physical on this cloud
     within 2,000 iterations)."""
@@ -299,6 +304,8 @@ def config3_run(lk, cloudgen, max_iters):
     gc = lk.Cloud(cloud)
     out, U = {}, {}
     for name, prec in (("fp64", lk.FP64), ("mixed", lk.MIXED)):
+        if name not in precisions:
+            continue
         prm = lk.default_params(cfl=CFL, inner_iters=INNER, precision=prec, check_every=100,
                                 tol_rel=1e-8, limiter=LIMITER, limiter_k=LIMITER_K)
         st = lk.State(gc, 0.5, 3.0, prm)
@@ -308,9 +315,10 @@ def config3_run(lk, cloudgen, max_iters):
                      "point_iters_per_s": cloud.n * d["iters"] / d["seconds"],
                      "res_drop": d["res_drop"], "cl": d["cl"], "cd": d["cd"]}
         st.close()
-    out["max_abs_dU_mixed_vs_fp64"] = float(np.abs(U["mixed"] - U["fp64"]).max())
-    out["dcl"] = out["mixed"]["cl"] - out["fp64"]["cl"]
-    out["dcd"] = out["mixed"]["cd"] - out["fp64"]["cd"]
+    if len(U) == 2:
+        out["max_abs_dU_mixed_vs_fp64"] = float(np.abs(U["mixed"] - U["fp64"]).max())
+        out["dcl"] = out["mixed"]["cl"] - out["fp64"]["cl"]
+        out["dcd"] = out["mixed"]["cd"] - out["fp64"]["cd"]
     out["points"] = cloud.n
     return out
 
@@ -485,6 +493,8 @@ def main():
                     help="graph-replayed iterations of the 2,621,440-point bandwidth leg (0 skips)")
     ap.add_argument("--config3-iters", type=int, default=0,
                     help="2,621,440-point FP64 vs mixed run to 1e-8 with this cap (0 skips)")
+    ap.add_argument("--config3-precisions", default="fp64,mixed",
+                    help="precisions of the --config3-iters leg (comma separated)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the timed steps (for profiler runs)")
     ap.add_argument("--profile-mlp", action="store_true",
@@ -602,7 +612,8 @@ def main():
     if args.large_steps > 0:
         extra["cloud_2621440_bandwidth"] = large_cloud_run(lk, cloudgen, args.large_steps)
     if args.config3_iters > 0:
-        extra["cloud_2621440_to_1e-8"] = config3_run(lk, cloudgen, args.config3_iters)
+        extra["cloud_2621440_to_1e-8"] = config3_run(lk, cloudgen, args.config3_iters,
+                                                     args.config3_precisions.split(","))
         print(f"# 2.6M: {json.dumps(extra['cloud_2621440_to_1e-8'])}", file=sys.stderr, flush=True)
     if args.warm_steps > 0:
         extra["warm_start"] = warm_start_run(lk, cloudgen, args.warm_steps, args.warm_held_out)

@@ -319,3 +319,56 @@ def test_wall_first_order_parity(lk, cfg1, jit):
             st.close()
         _, _, dUc, _ = case.o.iteration(U)
         assert rel(dUc, dUo) > 1e-8
+
+
+def wide_stencil_box(n=16, h=0.1, radius=3):
+    """A box cloud whose stencils are all (j', k') within `radius` rows and columns
+    (48 neighbours at interior points for radius 3), with a wall along the bottom."""
+    base = cg.box(n, n, h=h, wall_bottom=True)
+    j, k = np.arange(n * n) % n, np.arange(n * n) // n
+    cols = []
+    for dk in range(-radius, radius + 1):
+        for dj in range(-radius, radius + 1):
+            if dk == 0 and dj == 0:
+                continue
+            kn, jn = k + dk, j + dj
+            ok = (kn >= 0) & (kn < n) & (jn >= 0) & (jn < n)
+            cols.append(np.where(ok, kn * n + jn, -1))
+    nb = np.stack(cols, axis=1)
+    mask = nb >= 0
+    off = np.zeros(n * n + 1, dtype=np.int32)
+    np.cumsum(mask.sum(axis=1), out=off[1:])
+    return cg.Cloud(x=base.x, y=base.y, type=base.type, tx=base.tx, ty=base.ty, nbr_off=off,
+                    nbr_idx=nb[mask].astype(np.int32), name=f"box{n}x{n}r{radius}")
+
+
+def test_limiter_parity_wide_stencils(lk):
+    # 48-neighbour stencils: every lane of the limited q-derivative pass walks
+    # more entries than it keeps in LDS, so the second walk also re-gathers
+    cloud = wide_stencil_box()
+    assert np.diff(cloud.nbr_off).max() == 48
+    o = O.Oracle(cloud, mach=0.5, aoa_deg=10.0, cfl=20.0, inner_iters=1, limiter=1,
+                 limiter_k=5.0)
+    x, y = cloud.x, cloud.y
+    rho = 1.0 + 0.1 * np.sin(3 * x) * np.cos(2 * y)
+    u = 0.5 * np.cos(np.radians(10.0)) + 0.05 * np.sin(2 * y)
+    v = 0.5 * np.sin(np.radians(10.0)) + 0.04 * np.cos(3 * x)
+    v = np.where(cloud.type == cg.WALL, 0.0, v)  # tangency at the flat wall
+    p = (1.0 + 0.1 * np.cos(3 * x + y)) / 1.4
+    U0 = np.stack([rho, rho * u, rho * v, p / 0.4 + 0.5 * rho * (u * u + v * v)])
+    gc = lk.Cloud(cloud)
+    st = lk.State(gc, 0.5, 10.0, lk.default_params(cfl=20.0, inner_iters=1, limiter=1,
+                                                   limiter_k=5.0))
+    U1, _, _, _ = o.iteration(U0)
+    for U in (U0, U1):
+        st.set_U(U)
+        R, _ = st.residual()
+        Ro, _ = o.residual(U)
+        assert rel(R, Ro) < TOL
+        st.set_U(U)
+        st.step()
+        _, _, dUo, _ = o.iteration(U)
+        e = rel(st.get_dU(), dUo)
+        print(f"wide stencils, limiter: dU rel err {e:.3e}")
+        assert e < TOL
+    st.close()
