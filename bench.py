@@ -579,7 +579,24 @@ def main():
                        "flops_per_launch": flops, "avg_ms": res_ms, "launches_per_step": 1,
                        "ms_per_step": res_ms},
     }
+    # the two q-derivative passes together (algorithmic bytes as in iteration_bytes)
+    # and the update, both against HBM
+    qg_b = float(cloud.n * (152 + 280) + 2 * 4 * cloud.nnz)
+    qg_gbs = qg_b / (phases["q_derivatives"] * 1e-3) / 1e9
+    up_b = float(cloud.n * 128)
+    up_gbs = up_b / (phases["update"] * 1e-3) / 1e9
+    others = {
+        "k_qgrad (both passes)": {"bound": "hbm", "achieved": qg_gbs, "peak": PEAK_HBM_GBS,
+                                  "unit": "GB/s", "frac": qg_gbs / PEAK_HBM_GBS,
+                                  "bytes_per_step": qg_b, "launches_per_step": 2,
+                                  "ms_per_step": phases["q_derivatives"]},
+        "k_update": {"bound": "hbm", "achieved": up_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": up_gbs / PEAK_HBM_GBS, "traffic": (traffic or {}).get("k_update"),
+                     "bytes_per_launch": up_b, "launches_per_step": 1,
+                     "ms_per_step": phases["update"]},
+    }
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    kernels.update(others)
     it_bytes = iteration_bytes(cloud, gc.colours())
     it_gbs = it_bytes / (ms_per_step * 1e-3) / 1e9
     iteration_bw = {"bytes_per_iteration": it_bytes, "achieved_gbs": it_gbs,
