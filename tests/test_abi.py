@@ -78,3 +78,27 @@ def test_wall_points_need_a_frame(lib):
     code, msg = _create(lib, 2, off, np.array([1, 0], dtype=np.int32),
                         typ=np.array([0, 1], dtype=np.int8))
     assert code == -1 and "frame" in msg
+
+
+def test_empty_and_malformed_inputs_are_rejected(lib):
+    off = np.array([0], dtype=np.int32)
+    code, msg = _create(lib, 0, off, np.zeros(0, dtype=np.int32))
+    assert code == -1 and "range" in msg
+    # offsets that do not start at zero, or decrease
+    code, msg = _create(lib, 2, np.array([1, 1, 1], dtype=np.int32), np.zeros(1, dtype=np.int32))
+    assert code == -2 and "nbr_off[0]" in msg
+    code, msg = _create(lib, 3, np.array([0, 2, 1, 2], dtype=np.int32),
+                        np.array([1, 2], dtype=np.int32))
+    assert code == -2 and "monotone" in msg
+    # an invalid point type and a non-finite coordinate
+    off = np.array([0, 1, 2], dtype=np.int32)
+    code, msg = _create(lib, 2, off, np.array([1, 0], dtype=np.int32),
+                        typ=np.array([1, 7], dtype=np.int8))
+    assert code == -1 and "type" in msg
+    h = C.c_void_p()
+    x = np.array([0.0, np.nan])
+    code = lib.lskum_cloud_create(2, x.ctypes.data, np.zeros(2).ctypes.data,
+                                  np.ones(2, dtype=np.int8).ctypes.data, None, None,
+                                  off.ctypes.data, np.array([1, 0], dtype=np.int32).ctypes.data,
+                                  None, C.byref(h))
+    assert code == -1 and "finite" in lib.lskum_last_error().decode()

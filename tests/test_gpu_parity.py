@@ -372,3 +372,35 @@ def test_limiter_parity_wide_stencils(lk):
         print(f"wide stencils, limiter: dU rel err {e:.3e}")
         assert e < TOL
     st.close()
+
+
+@pytest.mark.parametrize("n", [5, 6, 9])
+def test_tiny_clouds_parity(lk, n):
+    # boxes of 25-81 points (most of them outer, a wall along the bottom):
+    # colour phases of a handful of points, empty phases of a point type, a
+    # single partial block per launch
+    cloud = cg.box(n, n, h=0.1, wall_bottom=True)
+    o = O.Oracle(cloud, mach=0.5, aoa_deg=5.0, cfl=20.0, inner_iters=1)
+    x, y = cloud.x, cloud.y
+    rho = 1.0 + 0.05 * np.sin(7 * x + 3 * y)
+    u = 0.5 * np.cos(np.radians(5.0)) + 0.03 * np.cos(5 * y)
+    v = np.where(cloud.type == cg.WALL, 0.0, 0.5 * np.sin(np.radians(5.0)) + 0.02 * np.sin(4 * x))
+    p = (1.0 + 0.05 * np.cos(6 * x - 2 * y)) / 1.4
+    U0 = np.stack([rho, rho * u, rho * v, p / 0.4 + 0.5 * rho * (u * u + v * v)])
+    gc = lk.Cloud(cloud)
+    assert np.array_equal(gc.colours(), o.colours)
+    for prm in (lk.default_params(cfl=20.0, inner_iters=1),
+                lk.default_params(cfl=20.0, inner_iters=1, order=lk.ORDER_WALL_FIRST)):
+        st = lk.State(gc, 0.5, 5.0, prm)
+        st.set_U(U0)
+        R, _ = st.residual()
+        Ro, _ = o.residual(U0)
+        assert rel(R, Ro) < TOL
+        st.set_U(U0)
+        st.step()
+        _, _, dUo, _ = O.Oracle(cloud, mach=0.5, aoa_deg=5.0, cfl=20.0, inner_iters=1,
+                                order=prm.order).iteration(U0)
+        e = rel(st.get_dU(), dUo)
+        print(f"box {n}x{n} order {prm.order}: dU rel err {e:.3e}")
+        assert e < TOL
+        st.close()
