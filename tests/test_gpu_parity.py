@@ -3,9 +3,11 @@
 Bar (FP64): max |X_gpu - X_oracle| / max |X_oracle| <= 1e-11 for the
 residual R, the q-derivatives and the increment dU of one iteration, on the
 same input state; colours bit-exact.  Inputs: the free-stream start and
-oracle states after 1 and 10 iterations of the 160 x 40 O-grid
+oracle states after 1, 10, 50 and 200 iterations of the 160 x 40 O-grid
 (M 0.63, 2 deg) -- several colours, wall/interior/outer points and ragged
-neighbour counts (14/19/24) -- plus a jittered 320 x 96 cloud at M 0.85.
+neighbour counts (14/19/24) -- plus a jittered 320 x 96 cloud at M 0.85,
+tiny boxes and wide-stencil boxes; and 200 graph-replayed iterations of the
+160 x 40 case against 200 oracle iterations.
 """
 import numpy as np
 import pytest
@@ -50,7 +52,8 @@ class Case:
 
 @pytest.fixture(scope="module")
 def cfg1(lk):
-    return Case(lk, cg.cloud_6400(), 0.63, 2.0)
+    # oracle states after 0, 1, 10, 50 and 200 iterations (about 40 s of oracle work)
+    return Case(lk, cg.cloud_6400(), 0.63, 2.0, states=(0, 1, 10, 50, 200))
 
 
 @pytest.fixture(scope="module")
@@ -72,7 +75,7 @@ def test_free_stream_state_and_anchor(cfg1):
     assert abs(res_gpu - res) <= TOL * res
 
 
-@pytest.mark.parametrize("it", [0, 1, 10])
+@pytest.mark.parametrize("it", [0, 1, 10, 50, 200])
 def test_q_derivatives_parity(cfg1, it):
     U = cfg1.states[it]
     cfg1.st.set_U(U)
@@ -82,7 +85,7 @@ def test_q_derivatives_parity(cfg1, it):
     assert rel(qx, ox) < TOL and rel(qy, oy) < TOL
 
 
-@pytest.mark.parametrize("it", [0, 1, 10])
+@pytest.mark.parametrize("it", [0, 1, 10, 50, 200])
 def test_residual_parity(cfg1, it):
     U = cfg1.states[it]
     cfg1.st.set_U(U)
@@ -94,7 +97,7 @@ def test_residual_parity(cfg1, it):
     assert abs(res - reso) <= TOL * reso
 
 
-@pytest.mark.parametrize("it", [0, 1, 10])
+@pytest.mark.parametrize("it", [0, 1, 10, 50, 200])
 def test_iteration_parity_exact_jvp(cfg1, it):
     U = cfg1.states[it]
     cfg1.st.set_U(U)
@@ -159,6 +162,19 @@ def test_multi_step_matches_oracle_iterations(cfg1):
     for _ in range(10):
         cfg1.st.step(want_res=False)
     assert rel(cfg1.st.get_U(), cfg1.states[10]) < 1e-12
+
+
+def test_two_hundred_graph_replayed_iterations_match_the_oracle(lk, cfg1):
+    # the 6,400-point case's full run: 200 iterations from the free stream
+    # through lskum_solve against 200 oracle iterations
+    prm = lk.default_params(cfl=100.0, inner_iters=1, check_every=10, max_iters=200, tol_rel=0.0)
+    st = lk.State(cfg1.gc, 0.63, 2.0, prm)
+    rep = st.solve()
+    assert rep.iters == 200
+    e = rel(st.get_U(), cfg1.states[200])
+    print(f"200 solve iterations: U rel err {e:.3e}")
+    assert e < 1e-11
+    st.close()
 
 
 def test_solve_graph_replay_matches_eager_steps(lk, cfg1):
