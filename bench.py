@@ -470,7 +470,20 @@ def cpu_baseline(cloud, iters: int):
     dt = time.perf_counter() - t0
     return {"value": cloud.n * iters / dt, "unit": "point-iters/s", "cores": 1, "kind": "oracle",
             "sample": f"{iters} serial FP64 oracle iterations of the {cloud.n}-point workload "
-                      f"from the free-stream start ({dt:.1f} s)"}
+                      f"from the free-stream start ({dt:.1f} s) on one core of {host_cpu()}"}
+
+
+def host_cpu() -> str:
+    """The host processor model and its logical CPU count."""
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return f"{model} ({os.cpu_count()} logical CPUs)"
 
 
 def main():
