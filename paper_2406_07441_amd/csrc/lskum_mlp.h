@@ -23,6 +23,7 @@ constexpr int kParams = kOffB4 + kOut;
 static_assert(kParams == 34308, "parameter count");
 constexpr int kChunk = 256;   // rows per partial sum of the gradients (multiple of 32)
 constexpr int kRowAlign = 32; // workspace rows are padded to a multiple of this
+constexpr int kMaxSumJobs = 8; // sums over rows in one backward pass
 
 struct Net {
     int device = 0;
@@ -46,7 +47,7 @@ struct Net {
     float* se = nullptr;
     __bf16 *dZ3 = nullptr, *dZ2 = nullptr;
     float* dZ1 = nullptr;
-    float* part = nullptr;  // gradient partials, [cap / kChunk][128][128]
+    float* part = nullptr;  // gradient partials of one backward pass, part_floats(capacity)
     double* d_loss = nullptr;
     int32_t* d_bad = nullptr;      // per component: 1 if the prediction is unusable
     double* d_res_fs = nullptr;    // per component free-stream residual (judge)
@@ -59,6 +60,8 @@ struct Net {
 // with Y ([Mvalid][4]) the predictions.
 hipError_t forward(Net& net, const float* X, int M, int Mvalid, const float* T, float* Y);
 hipError_t backward(Net& net, int M);
+// Floats of gradient partials a workspace of cap rows needs (Net::part).
+int64_t part_floats(int64_t cap);
 hipError_t loss(Net& net, int M, double* d_out);
 hipError_t adam_step(Net& net, float lr);
 hipError_t refresh_weights(Net& net);

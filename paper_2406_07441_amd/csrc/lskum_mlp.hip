@@ -282,20 +282,32 @@ __global__ void __launch_bounds__(256) k_colsum(int M, int mchunk, int R, int Cn
     part[(int64_t)blockIdx.y * R * Cn + g] = s;
 }
 
-// out[k] = sum_ch P[ch][k]: a block covers 64 outputs with 4 thread groups,
-// group g summing chunks g, g + 4, ... in order; the four group sums are then
-// added in group order (a fixed order throughout).
-__global__ void __launch_bounds__(256) k_sum_chunks(int n, int nch, const float* __restrict__ P,
-                                                    float* __restrict__ out) {
+// All second-stage sums of one backward pass in one launch: out_y[k] =
+// sum_ch P_y[ch][k], where the partials of sum y start at P + off[y] (nch[y]
+// chunks of n[y] values).  Block (x, y) covers outputs [64 x, 64 x + 64) of
+// sum y with 4 thread groups, group g adding chunks g, g + 4, ... in order;
+// the four group sums are then added in group order (a fixed order throughout).
+struct SumJobs {
+    int32_t n[kMaxSumJobs];
+    int32_t nch[kMaxSumJobs];
+    int64_t off[kMaxSumJobs];
+    float* out[kMaxSumJobs];
+};
+
+__global__ void __launch_bounds__(256) k_sum_jobs(SumJobs J, const float* __restrict__ P) {
     __shared__ float part[4][64];
+    const int y = blockIdx.y;
+    const int n = J.n[y], nch = J.nch[y];
+    if ((int)blockIdx.x * 64 >= n) return;  // uniform over the block
+    const float* Py = P + J.off[y];
     const int j = threadIdx.x & 63, g = threadIdx.x >> 6;
     const int k = blockIdx.x * 64 + j;
     float s = 0.0f;
     if (k < n)
-        for (int c = g; c < nch; c += 4) s += P[(int64_t)c * n + k];
+        for (int c = g; c < nch; c += 4) s += Py[(int64_t)c * n + k];
     part[g][j] = s;
     __syncthreads();
-    if (g == 0 && k < n) out[k] = ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j];
+    if (g == 0 && k < n) J.out[y][k] = ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j];
 }
 
 // One block of 1024 threads; fixed-order partial sums then a fixed tree.
@@ -490,47 +502,79 @@ hipError_t forward(Net& net, const float* X, int M, int Mvalid, const float* T, 
 
 // Backward after a forward with targets: gradient (flat, fp32) into net.grad.
 // Two-stage sum over rows: chunk partials, then a fixed-order sum of the chunks.
+// The sums over rows of one backward pass: each first stage writes its chunk
+// partials to its own region of net.part (sized by part_floats for the
+// workspace), and one launch adds them all at the end.
+struct SumPlan {
+    SumJobs jobs{};
+    int njobs = 0;
+    int nmax = 0;
+    int64_t off = 0;
+    // registers a sum of nch chunk partials of n values; returns where its
+    // partials start in net.part
+    int64_t add(int n, int nch, float* out) {
+        jobs.n[njobs] = n;
+        jobs.nch[njobs] = nch;
+        jobs.off[njobs] = off;
+        jobs.out[njobs] = out;
+        nmax = std::max(nmax, n);
+        const int64_t at = off;
+        off += (int64_t)nch * n;
+        ++njobs;
+        return at;
+    }
+};
+
+constexpr int kColRows = 64;  // rows per thread in a column-sum first stage
+
 template <class TP, class TQ>
-static void colsum(Net& net, int M, int R, int Cn, const TP* P, int ldp, const TQ* Q, int ldq,
-                   float* out) {
-    constexpr int kRows = 64;  // rows per thread in the first stage
-    const int nch = (M + kRows - 1) / kRows;
+static void colsum(Net& net, SumPlan& plan, int M, int R, int Cn, const TP* P, int ldp,
+                   const TQ* Q, int ldq, float* out) {
+    const int nch = (M + kColRows - 1) / kColRows;
+    float* dst = net.part + plan.add(R * Cn, nch, out);
     hipLaunchKernelGGL((k_colsum<TP, TQ>), dim3(nblk(R * Cn, 256), nch), dim3(256), 0, net.stream,
-                       M, kRows, R, Cn, P, ldp, Q, ldq, net.part);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(R * Cn, 64)), dim3(256), 0, net.stream, R * Cn,
-                       nch, net.part, out);
+                       M, kColRows, R, Cn, P, ldp, Q, ldq, dst);
 }
 
-static void wgrad(Net& net, int M, const __bf16* dZ, const __bf16* H, float* out) {
+static void wgrad(Net& net, SumPlan& plan, int M, const __bf16* dZ, const __bf16* H, float* out) {
     const int nch = (M + kChunk - 1) / kChunk;
+    float* dst = net.part + plan.add(kWidth * kWidth, nch, out);
     hipLaunchKernelGGL(k_dense_wgrad, dim3(64, nch), dim3(64), 0, net.stream, M, kChunk, dZ, H,
-                       net.part);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(nblk(kWidth * kWidth, 64)), dim3(256), 0, net.stream,
-                       kWidth * kWidth, nch, net.part, out);
+                       dst);
+}
+
+int64_t part_floats(int64_t cap) {
+    const int64_t nw = (cap + kChunk - 1) / kChunk, nc = (cap + kColRows - 1) / kColRows;
+    return 2 * nw * kWidth * kWidth +
+           nc * (kOut * kWidth + kOut + kWidth + kWidth + kWidth * kIn + kWidth);
 }
 
 hipError_t backward(Net& net, int M) {
     hipStream_t st = net.stream;
     float* g = net.grad;
     const float* none = nullptr;
+    SumPlan plan;
     // layer 4
-    colsum(net, M, kOut, kWidth, net.dY, kOut, net.H3, kWidth, g + kOffW4);
-    colsum(net, M, kOut, 1, net.dY, kOut, none, 0, g + kOffB4);
+    colsum(net, plan, M, kOut, kWidth, net.dY, kOut, net.H3, kWidth, g + kOffW4);
+    colsum(net, plan, M, kOut, 1, net.dY, kOut, none, 0, g + kOffB4);
     hipLaunchKernelGGL(k_layer_out_bwd, dim3(nblk((int64_t)M * kWidth, 256)), dim3(256), 0, st, M,
                        net.dY, net.W4b, net.Z3, net.dZ3);
     // layer 3
-    wgrad(net, M, net.dZ3, net.H2, g + kOffW3);
-    colsum(net, M, kWidth, 1, net.dZ3, kWidth, none, 0, g + kOffB3);
+    wgrad(net, plan, M, net.dZ3, net.H2, g + kOffW3);
+    colsum(net, plan, M, kWidth, 1, net.dZ3, kWidth, none, 0, g + kOffB3);
     hipLaunchKernelGGL(k_dense_bwd_data<true>, dim3((M / 16) * 8), dim3(64), 0, st, M, net.dZ3,
                        net.W3b, net.Z2, net.dZ2, (float*)nullptr);
     // layer 2
-    wgrad(net, M, net.dZ2, net.H1, g + kOffW2);
-    colsum(net, M, kWidth, 1, net.dZ2, kWidth, none, 0, g + kOffB2);
+    wgrad(net, plan, M, net.dZ2, net.H1, g + kOffW2);
+    colsum(net, plan, M, kWidth, 1, net.dZ2, kWidth, none, 0, g + kOffB2);
     hipLaunchKernelGGL(k_dense_bwd_data<false>, dim3((M / 16) * 8), dim3(64), 0, st, M, net.dZ2,
                        net.W2b, net.Z1, (__bf16*)nullptr, net.dZ1);
     // layer 1
-    colsum(net, M, kWidth, kIn, net.dZ1, kWidth, net.Xb, kIn, g + kOffW1);
-    colsum(net, M, kWidth, 1, net.dZ1, kWidth, none, 0, g + kOffB1);
+    colsum(net, plan, M, kWidth, kIn, net.dZ1, kWidth, net.Xb, kIn, g + kOffW1);
+    colsum(net, plan, M, kWidth, 1, net.dZ1, kWidth, none, 0, g + kOffB1);
+    // every second stage
+    hipLaunchKernelGGL(k_sum_jobs, dim3(nblk(plan.nmax, 64), plan.njobs), dim3(256), 0, st,
+                       plan.jobs, net.part);
     return hipGetLastError();
 }
 

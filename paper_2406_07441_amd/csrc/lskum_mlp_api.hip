@@ -225,7 +225,7 @@ int lskum_mlp_create(uint64_t seed, int64_t max_rows, void* hip_stream, lskum_ml
     chk(dalloc(&n.dZ3, cap * W));
     chk(dalloc(&n.dZ2, cap * W));
     chk(dalloc(&n.dZ1, cap * W));
-    chk(dalloc(&n.part, (cap / M::kChunk) * W * W));
+    chk(dalloc(&n.part, M::part_floats(cap)));
     chk(dalloc(&n.d_loss, 1));
     for (hipEvent_t& ev : n.ev) chk(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     if (e != hipSuccess) return bail(hip_err(e, "network allocation"));
