@@ -24,6 +24,7 @@ static_assert(kParams == 34308, "parameter count");
 constexpr int kChunk = 256;   // rows per partial sum of the gradients (multiple of 32)
 constexpr int kRowAlign = 32; // workspace rows are padded to a multiple of this
 constexpr int kMaxSumJobs = 8; // sums over rows in one backward pass
+constexpr int kMaxColJobs = 6; // of which column sums computed without matrix cores
 
 struct Net {
     int device = 0;

@@ -262,24 +262,44 @@ __global__ void __launch_bounds__(256) k_layer_out_bwd(int M, const float* __res
     dZ3[g] = (__bf16)(s * gelu_prime(Z3[g]));
 }
 
-// Partial sums of small products over one chunk of rows (grid.y = chunk),
-// one thread per output, rows in fixed order:
-// part[chunk][r][c] = sum_{m in chunk} P[m][r] Q[m][c] (Q == nullptr: P[m][r]).
-template <class TP, class TQ>
-__global__ void __launch_bounds__(256) k_colsum(int M, int mchunk, int R, int Cn,
-                                               const TP* __restrict__ P, int ldp,
-                                               const TQ* __restrict__ Q, int ldq,
-                                               float* __restrict__ part) {
+// Partial sums of small products over one chunk of rows, one thread per
+// output, rows in fixed order: part[chunk][r][c] = sum_{m in chunk} P[m][r]
+// Q[m][c] (no Q: P[m][r]).  All such sums of a backward pass in one launch:
+// grid.y = chunk, grid.z = job.
+struct ColJobs {
+    int32_t R[kMaxColJobs], Cn[kMaxColJobs], ldp[kMaxColJobs], ldq[kMaxColJobs];
+    int32_t p_bf16[kMaxColJobs];  // P stored as bf16, else fp32
+    const void* P[kMaxColJobs];
+    const __bf16* Q[kMaxColJobs];  // nullptr: plain column sums of P
+    float* part[kMaxColJobs];
+};
+
+template <class TP>
+__device__ __forceinline__ float colsum_rows(const TP* __restrict__ P, int ldp,
+                                             const __bf16* __restrict__ Q, int ldq, int r, int c,
+                                             int m0, int m1) {
+    float s = 0.0f;
+    if (Q) {
+        for (int m = m0; m < m1; ++m)
+            s += (float)P[(int64_t)m * ldp + r] * (float)Q[(int64_t)m * ldq + c];
+    } else {
+        for (int m = m0; m < m1; ++m) s += (float)P[(int64_t)m * ldp + r];
+    }
+    return s;
+}
+
+__global__ void __launch_bounds__(256) k_colsum_jobs(int M, int mchunk, ColJobs J) {
+    const int y = blockIdx.z;
+    const int R = J.R[y], Cn = J.Cn[y];
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= R * Cn) return;
     const int r = g / Cn, c = g % Cn;
     const int m0 = blockIdx.y * mchunk, m1 = min(M, m0 + mchunk);
-    float s = 0.0f;
-    for (int m = m0; m < m1; ++m) {
-        const float pv = (float)P[(int64_t)m * ldp + r];
-        s += Q ? pv * (float)Q[(int64_t)m * ldq + c] : pv;
-    }
-    part[(int64_t)blockIdx.y * R * Cn + g] = s;
+    const float s =
+        J.p_bf16[y]
+            ? colsum_rows((const __bf16*)J.P[y], J.ldp[y], J.Q[y], J.ldq[y], r, c, m0, m1)
+            : colsum_rows((const float*)J.P[y], J.ldp[y], J.Q[y], J.ldq[y], r, c, m0, m1);
+    J.part[y][(int64_t)blockIdx.y * R * Cn + g] = s;
 }
 
 // All second-stage sums of one backward pass in one launch: out_y[k] =
@@ -512,6 +532,9 @@ struct SumPlan {
     int64_t off = 0;
     // registers a sum of nch chunk partials of n values; returns where its
     // partials start in net.part
+    ColJobs cols{};
+    int ncols = 0;
+    int colmax = 0;
     int64_t add(int n, int nch, float* out) {
         jobs.n[njobs] = n;
         jobs.nch[njobs] = nch;
@@ -527,13 +550,21 @@ struct SumPlan {
 
 constexpr int kColRows = 64;  // rows per thread in a column-sum first stage
 
-template <class TP, class TQ>
-static void colsum(Net& net, SumPlan& plan, int M, int R, int Cn, const TP* P, int ldp,
-                   const TQ* Q, int ldq, float* out) {
+// Registers the column sums of P (times Q when given) over rows; their first
+// stage runs with the others at the end of the backward pass.
+static void colsum(Net& net, SumPlan& plan, int M, int R, int Cn, const void* P, bool p_bf16,
+                   int ldp, const __bf16* Q, int ldq, float* out) {
     const int nch = (M + kColRows - 1) / kColRows;
-    float* dst = net.part + plan.add(R * Cn, nch, out);
-    hipLaunchKernelGGL((k_colsum<TP, TQ>), dim3(nblk(R * Cn, 256), nch), dim3(256), 0, net.stream,
-                       M, kColRows, R, Cn, P, ldp, Q, ldq, dst);
+    const int k = plan.ncols++;
+    plan.cols.R[k] = R;
+    plan.cols.Cn[k] = Cn;
+    plan.cols.ldp[k] = ldp;
+    plan.cols.ldq[k] = ldq;
+    plan.cols.p_bf16[k] = p_bf16;
+    plan.cols.P[k] = P;
+    plan.cols.Q[k] = Q;
+    plan.cols.part[k] = net.part + plan.add(R * Cn, nch, out);
+    plan.colmax = std::max(plan.colmax, R * Cn);
 }
 
 static void wgrad(Net& net, SumPlan& plan, int M, const __bf16* dZ, const __bf16* H, float* out) {
@@ -552,27 +583,29 @@ int64_t part_floats(int64_t cap) {
 hipError_t backward(Net& net, int M) {
     hipStream_t st = net.stream;
     float* g = net.grad;
-    const float* none = nullptr;
     SumPlan plan;
     // layer 4
-    colsum(net, plan, M, kOut, kWidth, net.dY, kOut, net.H3, kWidth, g + kOffW4);
-    colsum(net, plan, M, kOut, 1, net.dY, kOut, none, 0, g + kOffB4);
+    colsum(net, plan, M, kOut, kWidth, net.dY, false, kOut, net.H3, kWidth, g + kOffW4);
+    colsum(net, plan, M, kOut, 1, net.dY, false, kOut, nullptr, 0, g + kOffB4);
     hipLaunchKernelGGL(k_layer_out_bwd, dim3(nblk((int64_t)M * kWidth, 256)), dim3(256), 0, st, M,
                        net.dY, net.W4b, net.Z3, net.dZ3);
     // layer 3
     wgrad(net, plan, M, net.dZ3, net.H2, g + kOffW3);
-    colsum(net, plan, M, kWidth, 1, net.dZ3, kWidth, none, 0, g + kOffB3);
+    colsum(net, plan, M, kWidth, 1, net.dZ3, true, kWidth, nullptr, 0, g + kOffB3);
     hipLaunchKernelGGL(k_dense_bwd_data<true>, dim3((M / 16) * 8), dim3(64), 0, st, M, net.dZ3,
                        net.W3b, net.Z2, net.dZ2, (float*)nullptr);
     // layer 2
     wgrad(net, plan, M, net.dZ2, net.H1, g + kOffW2);
-    colsum(net, plan, M, kWidth, 1, net.dZ2, kWidth, none, 0, g + kOffB2);
+    colsum(net, plan, M, kWidth, 1, net.dZ2, true, kWidth, nullptr, 0, g + kOffB2);
     hipLaunchKernelGGL(k_dense_bwd_data<false>, dim3((M / 16) * 8), dim3(64), 0, st, M, net.dZ2,
                        net.W2b, net.Z1, (__bf16*)nullptr, net.dZ1);
     // layer 1
-    colsum(net, plan, M, kWidth, kIn, net.dZ1, kWidth, net.Xb, kIn, g + kOffW1);
-    colsum(net, plan, M, kWidth, 1, net.dZ1, kWidth, none, 0, g + kOffB1);
-    // every second stage
+    colsum(net, plan, M, kWidth, kIn, net.dZ1, false, kWidth, net.Xb, kIn, g + kOffW1);
+    colsum(net, plan, M, kWidth, 1, net.dZ1, false, kWidth, nullptr, 0, g + kOffB1);
+    // the column sums' first stage, then every second stage
+    hipLaunchKernelGGL(k_colsum_jobs, dim3(nblk(plan.colmax, 256), (M + kColRows - 1) / kColRows,
+                                           plan.ncols),
+                       dim3(256), 0, st, M, kColRows, plan.cols);
     hipLaunchKernelGGL(k_sum_jobs, dim3(nblk(plan.nmax, 64), plan.njobs), dim3(256), 0, st,
                        plan.jobs, net.part);
     return hipGetLastError();
