@@ -365,7 +365,9 @@ __global__ void __launch_bounds__(256) k_refresh(const float* __restrict__ theta
 __global__ void __launch_bounds__(256) k_adam(int n, float lr, float b1, float b2, float eps,
                                               float c1, float c2, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v,
-                                              float* __restrict__ theta) {
+                                              float* __restrict__ theta, __bf16* __restrict__ W1,
+                                              __bf16* __restrict__ W2, __bf16* __restrict__ W3,
+                                              __bf16* __restrict__ W4) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const float gk = g[k];
@@ -373,7 +375,13 @@ __global__ void __launch_bounds__(256) k_adam(int n, float lr, float b1, float b
     const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
     m[k] = mk;
     v[k] = vk;
-    theta[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+    const float t = theta[k] - lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+    theta[k] = t;
+    // the bf16 copy the forward and backward kernels read (as k_refresh makes it)
+    if (k >= kOffW1 && k < kOffW1 + kWidth * kIn) W1[k - kOffW1] = (__bf16)t;
+    else if (k >= kOffW2 && k < kOffW2 + kWidth * kWidth) W2[k - kOffW2] = (__bf16)t;
+    else if (k >= kOffW3 && k < kOffW3 + kWidth * kWidth) W3[k - kOffW3] = (__bf16)t;
+    else if (k >= kOffW4 && k < kOffW4 + kOut * kWidth) W4[k - kOffW4] = (__bf16)t;
 }
 
 // Minibatch gather: row r takes dataset row floor(h * n / 2^64), h the
@@ -622,8 +630,9 @@ hipError_t adam_step(Net& net, float lr) {
     const float c1 = 1.0f - std::pow(b1, (float)net.step);
     const float c2 = 1.0f - std::pow(b2, (float)net.step);
     hipLaunchKernelGGL(k_adam, dim3(nblk(kParams, 256)), dim3(256), 0, net.stream, kParams, lr, b1,
-                       b2, 1e-8f, c1, c2, net.grad, net.m, net.v, net.theta);
-    return refresh_weights(net);
+                       b2, 1e-8f, c1, c2, net.grad, net.m, net.v, net.theta, net.W1b, net.W2b,
+                       net.W3b, net.W4b);
+    return hipGetLastError();
 }
 
 hipError_t gather(Net& net, int64_t n, const float* X, const float* T, int B, uint64_t seed,
