@@ -225,6 +225,15 @@ int lskum_batch_info(const lskum_batch* b, int64_t* n_points, int64_t* nnz, int3
 
 int lskum_batch_set_params(lskum_batch* b, const lskum_params* prm);
 
+/* Sets the CFL number of each condition (cfl: n_cond finite values > 0, host
+ * memory, copied): the local time step of eq. (25) uses its condition's
+ * value, so conditions with strong shocks can run a smaller CFL than the rest
+ * of the batch (a choice of the caller; the paper uses one CFL).  Until this
+ * is called, and again after lskum_batch_set_params changes params.cfl,
+ * every condition uses params.cfl.  Errors: LSKUM_ERR_ARG for NULL or a
+ * non-positive value. */
+int lskum_batch_set_cfl(lskum_batch* b, const double* cfl);
+
 /* Solves all conditions (graph-replayed iterations, device-side retirement)
  * until all retire or max_iters.  reps (n_cond entries, may be NULL): per
  * condition iterations, status (OK, NOT_CONVERGED or NONPHYSICAL), residual

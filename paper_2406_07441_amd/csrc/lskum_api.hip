@@ -304,7 +304,7 @@ void free_state(lskum::State& s) {
     void* ptrs[] = {s.U,    s.q,      s.qx[0], s.qx[1],  s.qy[0],   s.qy[1],    s.qxl, s.Rs,
                     s.qyl,  s.R,      s.dU,    s.jv0,    s.jv2,      s.D,
                     s.jv0f, s.jv2f,  s.dUf,    s.Df,      s.rr,       s.fsum, s.partial,
-                    s.res_hist, s.flags, s.active, s.status, s.iters, s.res_last, s.tol_abs,
+                    s.res_hist, s.flags, s.active, s.status, s.iters, s.res_last, s.tol_abs, s.cfl,
                     s.vinf};
     for (void* p : ptrs) (void)hipFree(p);
     if (s.own_stream && s.stream) (void)hipStreamDestroy(s.stream);
@@ -455,6 +455,7 @@ int init_state(lskum::State& s, const lskum::Cloud& c, const lskum_params* prm,
     chk(dalloc(&s.iters, nc));
     chk(dalloc(&s.res_last, nc));
     chk(dalloc(&s.tol_abs, nc));
+    chk(dalloc(&s.cfl, nc));
     chk(dalloc(&s.vinf, 2 * nc));
     if (e != hipSuccess) return hip_fail(e, "state allocation");
     std::vector<double> vinf(2 * nc), zero(nc, 0.0);
@@ -467,6 +468,7 @@ int init_state(lskum::State& s, const lskum::Cloud& c, const lskum_params* prm,
                           s.stream));
     HIPCHK(hipMemcpyAsync(s.tol_abs, zero.data(), nc * sizeof(double), hipMemcpyHostToDevice,
                           s.stream));
+    HIPCHK(lskum::reset_cfl(s));
     HIPCHK(lskum::launch_clear_flags(s.flags, s.stream));
     HIPCHK(lskum::launch_reset_components(s));
     HIPCHK(lskum::launch_free_stream(s));
@@ -746,7 +748,7 @@ int lskum_state_set_params(lskum_state* so, const lskum_params* prm) {
     lskum::State& s = so->s;
     const lskum::Params np = to_params(prm);
     // the captured iteration depends on everything but the stopping rule
-    const bool same_kernels = np.gamma == s.prm.gamma && np.cfl == s.prm.cfl &&
+    const bool same_kernels = np.gamma == s.prm.gamma &&
                               np.inner_iters == s.prm.inner_iters &&
                               np.jvp_mode == s.prm.jvp_mode && np.precision == s.prm.precision &&
                               np.limiter == s.prm.limiter && np.limiter_k == s.prm.limiter_k &&
@@ -763,8 +765,10 @@ int lskum_state_set_params(lskum_state* so, const lskum_params* prm) {
         s.have_dU = false;
         HIPCHK(lskum::clear_increment(s, 0, s.cloud->n));
     }
+    const bool new_cfl = np.cfl != s.prm.cfl;
     s.prm = np;
     apply_lanes(s);
+    if (new_cfl) HIPCHK(lskum::reset_cfl(s));  // per-condition values give way to the new one
     return LSKUM_OK;
 }
 
@@ -1024,6 +1028,18 @@ int lskum_batch_set_params(lskum_batch* b, const lskum_params* prm) {
     int r = lskum_state_set_params(&tmp, prm);
     std::swap(tmp.s, b->s);
     return r;
+}
+
+int lskum_batch_set_cfl(lskum_batch* b, const double* cfl) {
+    if (!b || !cfl) return fail(LSKUM_ERR_ARG, "NULL argument");
+    lskum::State& s = b->s;
+    const int nc = b->c.ncomp;
+    for (int k = 0; k < nc; ++k)
+        if (!(cfl[k] > 0.0) || !std::isfinite(cfl[k]))
+            return fail(LSKUM_ERR_ARG, "cfl must be finite and > 0");
+    HIPCHK(hipMemcpyAsync(s.cfl, cfl, nc * sizeof(double), hipMemcpyHostToDevice, s.stream));
+    HIPCHK(hipStreamSynchronize(s.stream));
+    return LSKUM_OK;
 }
 
 int lskum_batch_solve(lskum_batch* b, lskum_report* reps, double* seconds_total) {

@@ -545,7 +545,8 @@ __device__ __forceinline__ void residual_pair(int8_t ty, const D2& t, const D2& 
 // the first lane finishes the point.
 template <bool MIXED, int LANES>
 __global__ void __launch_bounds__(kBlock) k_residual(
-    int64_t n, double gamma, double cfl, const D2* __restrict__ xy, const D2* __restrict__ frame,
+    int64_t n, double gamma, const double* __restrict__ cfl, const D2* __restrict__ xy,
+    const D2* __restrict__ frame,
     const int8_t* __restrict__ type, const int32_t* __restrict__ off,
     const int32_t* __restrict__ idx, const PointGeom* __restrict__ geom,
     const int32_t* __restrict__ comp, const int32_t* __restrict__ active,
@@ -619,7 +620,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(
             const D4 j2 = {erf(sx), exp(-(sx * sx)), erf(sy), exp(-(sy * sy))};
             const double a = sqrt(gamma * pr / rho);
             const PointGeom& G = geom[p];
-            const double dt = cfl * G.lsq.w / (sqrt(usq) + a);
+            const double dt = cfl[comp ? comp[p] : 0] * G.lsq.w / (sqrt(usq) + a);
             double Dp = 1.0 / dt;
             if (variant == 0) {
                 // Anandhanarayanan et al.: split Jacobians -> +-rho(A+-) I (eq. 34-35)
@@ -1156,7 +1157,7 @@ __global__ void __launch_bounds__(kBlock) k_update(int64_t n, double gamma, D4* 
 // the implicit scheme's local time step dt = CFL rmin / (|u| + a) at the
 // current state, then the next q-variables.  Outer points keep their state.
 __global__ void __launch_bounds__(kBlock) k_explicit_update(
-    int64_t n, double gamma, double cfl, const int8_t* __restrict__ type,
+    int64_t n, double gamma, const double* __restrict__ cfl, const int8_t* __restrict__ type,
     const PointGeom* __restrict__ geom, const int32_t* __restrict__ comp,
     const int32_t* __restrict__ active, const D4* __restrict__ R, D4* __restrict__ U,
     D4* __restrict__ q, int32_t* __restrict__ flags) {
@@ -1168,7 +1169,7 @@ __global__ void __launch_bounds__(kBlock) k_explicit_update(
     const double usq = u1 * u1 + u2 * u2;
     const double pr = (gamma - 1.0) * (u.w - 0.5 * rho * usq);
     const double a = sqrt(gamma * pr / rho);
-    const double dt = cfl * geom[p].lsq.w / (sqrt(usq) + a);
+    const double dt = cfl[comp ? comp[p] : 0] * geom[p].lsq.w / (sqrt(usq) + a);
     const D4 r = R[p];
     u.x -= dt * r.x;
     u.y -= dt * r.y;
@@ -1352,7 +1353,7 @@ static void residual_lanes(State& s, bool in_step) {
     const Cloud& c = *s.cloud;
     const unsigned nb = grid_for(c.n * LANES);
     hipLaunchKernelGGL((k_residual<MIXED, LANES>), dim3(nb), dim3(kBlock), 0, s.stream, c.n,
-                       s.prm.gamma, s.prm.cfl, c.xy, c.frame, c.type, c.off, c.idx, c.geom, c.comp,
+                       s.prm.gamma, s.cfl, c.xy, c.frame, c.type, c.off, c.idx, c.geom, c.comp,
                        s.active, s.U, s.q, s.prm.limiter ? s.qxl : s.qx[s.qsel],
                        s.prm.limiter ? s.qyl : s.qy[s.qsel], s.R, s.D, s.jv0, s.jv2, s.jv0f,
                        s.jv2f, s.Df, s.rr, s.flags, s.prm.variant,
@@ -1496,7 +1497,7 @@ hipError_t launch_sweeps(State& s) {
 hipError_t launch_explicit_update(State& s) {
     const Cloud& c = *s.cloud;
     hipLaunchKernelGGL(k_explicit_update, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream, c.n,
-                       s.prm.gamma, s.prm.cfl, c.type, c.geom, c.comp, s.active, s.R, s.U, s.q,
+                       s.prm.gamma, s.cfl, c.type, c.geom, c.comp, s.active, s.R, s.U, s.q,
                        s.flags);
     return hipGetLastError();
 }
@@ -1538,6 +1539,18 @@ hipError_t launch_aosf_to_soa(const F4* aos, double* soa, int64_t n, hipStream_t
 
 hipError_t launch_clear_flags(int32_t* flags, hipStream_t st) {
     hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, st, flags);
+    return hipGetLastError();
+}
+
+__global__ void k_fill(int n, double v, double* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = v;
+}
+
+hipError_t reset_cfl(State& s) {
+    const int nc = s.cloud->ncomp;
+    hipLaunchKernelGGL(k_fill, dim3((nc + 255) / 256), dim3(256), 0, s.stream, nc, s.prm.cfl,
+                       s.cfl);
     return hipGetLastError();
 }
 

@@ -137,6 +137,7 @@ struct State {
     int32_t* iters = nullptr;
     double* res_last = nullptr;
     double* tol_abs = nullptr;             // 0 disables device-side retirement
+    double* cfl = nullptr;                 // per component CFL number (params.cfl unless set)
     double* vinf = nullptr;                // 2 per component: free-stream velocity
     double* rr = nullptr;                  // per point R_rho^2 (0 at outer points)
     hipStream_t stream = nullptr;
@@ -203,6 +204,8 @@ hipError_t launch_aosf_to_soa(const F4* aos, double* soa, int64_t n, hipStream_t
 hipError_t launch_clear_flags(int32_t* flags, hipStream_t st);
 // zero increment (both precisions) of points [p0, p0 + n): after a new U
 hipError_t clear_increment(State& s, int64_t p0, int64_t n);
+// every component's CFL number to params.cfl
+hipError_t reset_cfl(State& s);
 
 // Error reporting shared by the C-ABI source files: records msg for
 // lskum_last_error() and returns code.

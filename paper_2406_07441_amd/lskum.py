@@ -77,6 +77,7 @@ _SIGS = {
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lskum_batch_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lskum_batch_set_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lskum_batch_set_cfl": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lskum_batch_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lskum_batch_step_timed": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lskum_batch_get_U": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int]),
@@ -326,6 +327,12 @@ class Batch:
     def set_params(self, params: Params):
         _check(lib().lskum_batch_set_params(self.h, C.byref(params)))
         self.params = params
+
+    def set_cfl(self, cfl):
+        """CFL number per condition (n_cond values > 0)."""
+        cfl = np.ascontiguousarray(cfl, dtype=np.float64)
+        assert cfl.shape == (self.n_cond,)
+        _check(lib().lskum_batch_set_cfl(self.h, cfl.ctypes.data))
 
     def solve(self):
         """Returns (list of Report dicts, total seconds)."""

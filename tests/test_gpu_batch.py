@@ -45,6 +45,38 @@ def test_batch_step_equals_single_states_bitwise(lk, setup):
         assert np.array_equal(bat.get_U(k), st.get_U()), k
 
 
+def test_batch_per_condition_cfl_equals_single_states_bitwise(lk, setup):
+    # each condition's CFL reaches its local time step: the batch equals single
+    # states run at those CFL numbers, graph-replayed and stepped; a change of
+    # params.cfl sets every condition back to it
+    a, b, ga, gb, conds = setup
+    cfl = [50.0, 10.0, 25.0]
+    prm = lk.default_params(cfl=50.0, inner_iters=1, check_every=2, tol_rel=0.0, max_iters=4)
+    bat = lk.Batch([ga, gb], [c[0] for c in conds], [c[1] for c in conds], [c[2] for c in conds], prm)
+    bat.set_cfl(cfl)
+    bat.solve()
+    for k, (ci, m, al) in enumerate(conds):
+        st = lk.State([ga, gb][ci], m, al, lk.default_params(cfl=cfl[k], inner_iters=1))
+        for _ in range(4):
+            st.step(want_res=False)
+        assert np.array_equal(bat.get_U(k), st.get_U()), k
+        st.close()
+    with pytest.raises(lk.LskumError):
+        bat.set_cfl([50.0, 0.0, 25.0])
+    prm2 = lk.default_params(cfl=20.0, inner_iters=1, check_every=2, tol_rel=0.0, max_iters=4)
+    bat.set_params(prm2)
+    U0 = [bat.get_U(k) for k in range(3)]
+    bat.solve()
+    for k, (ci, m, al) in enumerate(conds):
+        st = lk.State([ga, gb][ci], m, al, lk.default_params(cfl=20.0, inner_iters=1))
+        st.set_U(U0[k])
+        for _ in range(4):
+            st.step(want_res=False)
+        assert np.array_equal(bat.get_U(k), st.get_U()), k
+        st.close()
+    bat.close()
+
+
 def test_batch_solve_matches_single_solves(lk, setup):
     a, b, ga, gb, conds = setup
     prm = lk.default_params(cfl=100.0, inner_iters=1, check_every=10, tol_rel=1e-4, max_iters=3000)
