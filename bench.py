@@ -380,7 +380,7 @@ def warm_start_run(lk, cloudgen, train_steps: int, held_out: int):
     bf = lk.Batch([gh], cc, hm, ha, prm_mx)
     r_bf, t_bf = bf.solve()
     bf.close()
-    # (c) mixed-precision batch, warm start (inference and judge inside the timing)
+    # (c) mixed-precision batch, warm start (inference and residual check inside the timing)
     bw = lk.Batch([gh], cc, hm, ha, prm_mx)
     Xh = bw.features()
     torch.cuda.synchronize()

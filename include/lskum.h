@@ -329,7 +329,7 @@ int lskum_batch_features(lskum_batch* b, float* X, float* T);
 
 /* Warm start: sets U of every point to the network's prediction (outer
  * points at the free stream, wall points with tangential velocity only),
- * then judges each condition by its residual norm: a condition whose
+ * then checks each condition's residual norm: a condition whose
  * prediction is non-finite or non-physical (rho < 0.05 or gamma p < 0.05),
  * or whose residual is not below its free-stream residual, goes back to the
  * free stream.  fallback / res_warm (host, 1 entry for a state, n_cond for a

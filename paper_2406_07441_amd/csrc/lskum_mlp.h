@@ -51,7 +51,7 @@ struct Net {
     float* part = nullptr;  // gradient partials of one backward pass, part_floats(capacity)
     double* d_loss = nullptr;
     int32_t* d_bad = nullptr;      // per component: 1 if the prediction is unusable
-    double* d_res_fs = nullptr;    // per component free-stream residual (judge)
+    double* d_res_fs = nullptr;    // per component free-stream residual (residual check)
     int64_t ncomp_cap = 0;
     hipEvent_t ev[2] = {};
 };
@@ -75,9 +75,9 @@ hipError_t features(const State& s, int64_t p0, int64_t m, float* Xout, float* T
 // U of points [p0, p0 + m) from the predictions Y; marks d_bad[comp] for
 // non-finite or non-physical predictions.
 hipError_t pred_to_U(Net& net, const State& s, int64_t p0, int64_t m, const float* Y);
-// Judge: components whose residual res[k] is not finite or not below the
+// Residual check: components whose residual res[k] is not finite or not below the
 // free-stream residual are flagged in d_bad and reset to the free stream.
-hipError_t judge_and_fallback(Net& net, const State& s, const double* res);
+hipError_t vet_and_fallback(Net& net, const State& s, const double* res);
 
 }  // namespace mlp
 }  // namespace lskum

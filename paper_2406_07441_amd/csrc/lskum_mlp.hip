@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(256) k_pred_to_U(int64_t p0, int64_t m, const 
         u1 += (double)y[1];
         u2 += (double)y[2];
         gp += (double)y[3];
-        // unusable prediction: the judge sends the whole component back to the free stream
+        // unusable prediction: the residual check sends the whole component back to the free stream
         if (!(rho > 0.05) || !(gp > 0.05) || !(fabs(u1) + fabs(u2) < 1e3)) {
             bad[k] = 1;
             rho = 1.0;
@@ -493,8 +493,8 @@ __global__ void __launch_bounds__(256) k_pred_to_U(int64_t p0, int64_t m, const 
     U[p] = {rho, rho * u1, rho * u2, pr / (gamma - 1.0) + 0.5 * rho * (u1 * u1 + u2 * u2)};
 }
 
-__global__ void k_judge(int ncomp, const double* __restrict__ res, const double* __restrict__ res_fs,
-                        int32_t* __restrict__ bad) {
+__global__ void k_vet(int ncomp, const double* __restrict__ res, const double* __restrict__ res_fs,
+                      int32_t* __restrict__ bad) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= ncomp) return;
     if (!(res[k] < res_fs[k])) bad[k] = 1;
@@ -656,9 +656,9 @@ hipError_t pred_to_U(Net& net, const State& s, int64_t p0, int64_t m, const floa
     return hipGetLastError();
 }
 
-hipError_t judge_and_fallback(Net& net, const State& s, const double* res) {
+hipError_t vet_and_fallback(Net& net, const State& s, const double* res) {
     const Cloud& c = *s.cloud;
-    hipLaunchKernelGGL(k_judge, dim3(nblk(c.ncomp, 256)), dim3(256), 0, s.stream, c.ncomp, res,
+    hipLaunchKernelGGL(k_vet, dim3(nblk(c.ncomp, 256)), dim3(256), 0, s.stream, c.ncomp, res,
                        net.d_res_fs, net.d_bad);
     hipLaunchKernelGGL(k_pred_to_U<true>, dim3(nblk(c.n, 256)), dim3(256), 0, s.stream, (int64_t)0,
                        c.n, (const float*)nullptr, c.type, c.frame, c.comp, s.vinf, s.prm.gamma,

@@ -112,8 +112,8 @@ int state_features(lskum::State& s, float* X, float* T) {
     return LSKUM_OK;
 }
 
-// Predicts U chunk by chunk on the network's workspace, then judges every
-// component by its residual norm and sends rejected ones to the free stream.
+// Predicts U chunk by chunk on the network's workspace, then checks every
+// component's residual norm and sends rejected ones to the free stream.
 int warm_start(M::Net& n, lskum::State& s, int32_t* fallback, double* res_warm) {
     const lskum::Cloud& c = *s.cloud;
     const int nc = c.ncomp;
@@ -149,7 +149,7 @@ int warm_start(M::Net& n, lskum::State& s, int32_t* fallback, double* res_warm) 
     HIPCHK(lskum::launch_q_derivatives(s));
     HIPCHK(lskum::launch_residual(s, 0));
     HIPCHK(lskum::launch_norm(s, 0));
-    HIPCHK(M::judge_and_fallback(n, s, s.res_hist));
+    HIPCHK(M::vet_and_fallback(n, s, s.res_hist));
     HIPCHK(lskum::launch_reset_components(s));
     HIPCHK(lskum::launch_clear_flags(s.flags, s.stream));
     HIPCHK(lskum::launch_q_from_U(s));

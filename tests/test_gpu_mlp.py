@@ -217,7 +217,7 @@ def test_warm_start_zero_network_keeps_free_stream(lk, small):
     net.set_params(np.zeros(OM.N_PARAMS, np.float32))
     fb, res = net.warm_start(st)
     # the prediction is the free stream itself: its residual is not below the
-    # free-stream residual, so the judge keeps the free stream
+    # free-stream residual, so the residual check keeps the free stream
     assert fb[0] == 1 and res[0] == res_fs
     assert np.array_equal(st.get_U(), U0)
     bad = np.zeros(OM.N_PARAMS, np.float32)
@@ -229,9 +229,9 @@ def test_warm_start_zero_network_keeps_free_stream(lk, small):
     st.close()
 
 
-def test_warm_start_state_and_judge(lk, small):
+def test_warm_start_state_and_residual_check(lk, small):
     """A network with constant output c: U is the prediction map of c (or the
-    free stream when the judge rejects it) and the judged residual equals
+    free stream when the residual check rejects it) and the checked residual equals
     the oracle's residual of that state."""
     c, gc = small
     mach, aoa = 0.6, 2.0
@@ -287,7 +287,7 @@ def test_warm_start_gain_held_out(lk):
         print(f"M {mach} aoa {aoa}: free stream {r_fs.iters} its, warm {r_ws.iters} its, "
               f"res_warm/res_fs {res[0] / r_fs.res_fs:.3e}, dCL {r_ws.cl - r_fs.cl:.2e}")
         assert r_fs.status == 0 and r_ws.status == 0
-        # the judge accepted the prediction: its residual is below the free stream's
+        # the residual check accepted the prediction: its residual is below the free stream's
         assert fb[0] == 0 and res[0] < 0.5 * r_fs.res_fs
         assert r_ws.iters <= 1.02 * r_fs.iters
         assert abs(r_ws.cl - r_fs.cl) <= 1e-6 and abs(r_ws.cd - r_fs.cd) <= 1e-6
