@@ -518,7 +518,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
-              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+              "(independent flow conditions would go to different GPUs; one cloud "
+              "would split into point partitions with halo exchanges)", file=sys.stderr)
         sys.exit(2)
     if args.steps % 10 or args.warmup % 10:
         print("--steps and --warmup must be multiples of 10", file=sys.stderr)
