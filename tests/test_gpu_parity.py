@@ -6,8 +6,9 @@ same input state; colours bit-exact.  Inputs: the free-stream start and
 oracle states after 1, 10, 50 and 200 iterations of the 160 x 40 O-grid
 (M 0.63, 2 deg) -- several colours, wall/interior/outer points and ragged
 neighbour counts (14/19/24) -- plus a jittered 320 x 96 cloud at M 0.85,
-tiny boxes and wide-stencil boxes; and 200 graph-replayed iterations of the
-160 x 40 case against 200 oracle iterations.
+tiny boxes and wide-stencil boxes, and a 48 x 12 O-grid at M 1.2 with a bow
+shock; and 200 graph-replayed iterations of the 160 x 40 case (600 of the
+supersonic one) against as many oracle iterations.
 """
 import numpy as np
 import pytest
@@ -420,3 +421,35 @@ def test_tiny_clouds_parity(lk, n):
         print(f"box {n}x{n} order {prm.order}: dU rel err {e:.3e}")
         assert e < TOL
         st.close()
+
+
+def test_supersonic_bow_shock_parity(lk):
+    # M 1.2, AoA 0 with the limiter (the paper's supersonic case on a small
+    # O-grid): one iteration from a state with the shock forming, then 600
+    # graph-replayed iterations to the converged field, against the oracle
+    cloud = cg.ogrid(48, 12)
+    kw = dict(cfl=100.0, inner_iters=1, limiter=1, limiter_k=5.0)
+    o = O.Oracle(cloud, mach=1.2, aoa_deg=0.0, **kw)
+    U = o.free_stream()
+    for _ in range(20):
+        U, _, _, _ = o.iteration(U)
+    gc = lk.Cloud(cloud)
+    st = lk.State(gc, 1.2, 0.0, lk.default_params(**kw))
+    st.set_U(U)
+    st.step()
+    _, _, dUo, _ = o.iteration(U)
+    e = rel(st.get_dU(), dUo)
+    print(f"supersonic dU at iteration 20: rel err {e:.3e}")
+    assert e < TOL
+    st.close()
+    Uo, it, hist = o.solve(o.free_stream(), 600)
+    prm = lk.default_params(check_every=50, max_iters=600, tol_rel=0.0, **kw)
+    st = lk.State(gc, 1.2, 0.0, prm)
+    rep = st.solve()
+    assert rep.iters == 600
+    e = rel(st.get_U(), Uo)
+    cl, cd = st.forces()
+    clo, cdo = o.forces(Uo)
+    print(f"supersonic 600 iterations: U rel err {e:.3e}, cd {cd:.6f} vs {cdo:.6f}")
+    assert e < 1e-8 and abs(cl) < 1e-9 and abs(cd - cdo) < 1e-8
+    st.close()

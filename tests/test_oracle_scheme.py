@@ -16,7 +16,7 @@ fixes, not against a retyped copy of the oracle:
   * Algorithm 4 colours a hand-traced example exactly and always yields a
     proper colouring;
   * a uniform pressure exerts no force; zero incidence on the symmetric
-    profile gives zero lift.
+    profile gives zero lift, subsonic and supersonic (M 1.2, with a shock).
 """
 import numpy as np
 import pytest
@@ -241,6 +241,23 @@ def test_zero_lift_at_zero_incidence():
     assert hist[-1] < 1e-3 * hist[0]
     cl, cd = o.forces(U)
     assert abs(cl) < 1e-5
+
+
+def test_supersonic_zero_incidence_converges_with_zero_lift():
+    # the paper's supersonic case (M 1.2, AoA 0): a bow shock ahead of the
+    # nose; with the limiter the iteration reaches its fixed point, which is
+    # mirror symmetric, so the lift vanishes
+    c = cg.ogrid(48, 12)
+    o = O.Oracle(c, mach=1.2, aoa_deg=0.0, cfl=100.0, inner_iters=1, limiter=1, limiter_k=5.0)
+    U, it, hist = o.solve(o.free_stream(), 600)
+    assert it == 600 and hist[-1] < 1e-8 * hist[0]
+    cl, cd = o.forces(U)
+    assert abs(cl) < 1e-9 and np.isfinite(cd)
+    # supersonic in the far field, subsonic pocket behind the shock at the nose
+    rho, m1, m2, E = U
+    p = 0.4 * (E - 0.5 * (m1 * m1 + m2 * m2) / rho)
+    mach = np.hypot(m1, m2) / rho / np.sqrt(1.4 * p / rho)
+    assert mach.max() > 1.2 and mach[c.type == 0].min() < 0.1
 
 
 def test_limiter_keeps_linear_fields_and_clips_extrema():
