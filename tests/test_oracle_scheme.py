@@ -243,6 +243,22 @@ def test_zero_lift_at_zero_incidence():
     assert abs(cl) < 1e-5
 
 
+def test_wall_residual_and_increment_keep_tangency():
+    # flow tangency at wall points: neither R nor the increment has a
+    # component of momentum along the wall normal, whatever the state
+    c = cg.ogrid(48, 12, jitter_p=0.04, seed=3)
+    o = O.Oracle(c, mach=0.7, aoa_deg=4.0, cfl=50.0, inner_iters=1)
+    U = o.free_stream()
+    for _ in range(3):
+        U, R, dU, _ = o.iteration(U)
+    w = c.type == 0
+    nx, ny = -c.ty[w], c.tx[w]
+    for F in (R, dU):
+        normal = F[1, w] * nx + F[2, w] * ny
+        assert np.abs(F[1:3, w]).max() > 0
+        assert np.abs(normal).max() <= 1e-14 * np.abs(F[1:3, w]).max()
+
+
 def test_supersonic_zero_incidence_converges_with_zero_lift():
     # the paper's supersonic case (M 1.2, AoA 0): a bow shock ahead of the
     # nose; with the limiter the iteration reaches its fixed point, which is
