@@ -1,19 +1,23 @@
-#!/usr/bin/env python3
 """Benchmark of the implicit LSKUM hot path on one MI355X.
 
-Workload (the timed steps): the transonic NACA 0012-type case -- a
-640 x 256 = 163,840-point O-grid cloud with 4% of interior points jittered
-(seed 2406), Mach 0.85, AoA 1 deg; exact-JVP modified LU-SGS in FP64, CFL 100,
-one inner iteration of the q-derivatives, Venkatakrishnan limiter (K = 5) on
-the q~ reconstruction (the shock needs it to converge; the paper names none).
-A step is one implicit iteration: q-derivatives, limiter, residual, forward
-and backward colour sweeps, state update.  ``value`` is point-iterations per
-second over the timed steps (HIP-graph replay, inputs resident in HBM).
+Workload (the timed steps): a 2560 x 1024 = 2,621,440-point O-grid cloud
+around the 12%-thick symmetric profile (first normal spacing equal to the mean
+wall spacing), Mach 0.5, AoA 3 deg; exact-JVP modified LU-SGS in FP64, CFL 100,
+one inner iteration of the q-derivatives and the Venkatakrishnan limiter (K 5)
+on the q~ reconstruction (the impulsive free-stream start goes non-physical on
+this cloud without it; the paper names no limiter).  A step is one implicit
+iteration: q-derivatives, limiter, residual with the local time step, diagonal
+and linearisation data, residual norm, forward and backward colour sweeps,
+state update.  ``value`` is point-iterations per second over the timed steps
+(HIP-graph replay, every array resident in HBM).
 
-Also reported: per-phase GPU times from HIP events, the roofline of the
-dominant kernel, time to a 1e-8 residual drop with exact and flux-difference
-Jacobian products (FP64) and with mixed precision, the batched 64-condition
-workload, and the CPU oracle's rate on a bounded sample of the same workload.
+Also reported: per-phase GPU times from HIP events, the roofline of every
+kernel against the algorithmic work per point, the same workload in mixed
+precision, time to a 1e-8 residual drop on the 163,840-point transonic cloud
+with exact and flux-difference Jacobian products (FP64) and mixed precision,
+the explicit solver beside the implicit one, the batched 64-condition
+workload, the learned warm start, and the CPU oracle's rate on a bounded
+sample of the timed workload (all host cores).
 """
 from __future__ import annotations
 
@@ -27,11 +31,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-MACH, AOA, CFL, INNER, LIMITER, LIMITER_K = 0.85, 1.0, 100.0, 1, 1, 5.0
+# the timed workload
+HEAD_MACH, HEAD_AOA = 0.5, 3.0
+# the transonic 163,840-point workload of the time-to-tolerance legs
+MACH, AOA = 0.85, 1.0
+CFL, INNER, LIMITER, LIMITER_K = 100.0, 1, 1, 5.0
 
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
-PEAK_FP64_TFLOPS = 78.6
+PEAK_FP64_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 
 # Algorithmic FP64 operation count of the residual, with elementary functions
 # costed at the operation count of a standard software evaluation.
@@ -43,17 +51,17 @@ NB_OPS = 2 + 40 + 2 * (11 + COST["exp"] + COST["sqrt"] + 2 * COST["div"])
 # + div each), difference, scale and accumulate (12)
 SPLIT_OPS = 3 + 2 * (25 + COST["erf"] + COST["exp"] + COST["div"]) + 12
 
-# Algorithmic bytes of the sweep, each array read or written once. Per swept
-# point: colour-sorted index 4, list offset 4, component 4, type 1, wall
-# frame 16, D 8, own R (forward) or dU* (backward) 32, result 32, and its
-# linearisation records ((rho, u1, u2, p) 32 and the erf/exp pairs 32) and
-# increment (32) as read by its neighbours; per list entry: neighbour index
-# 4, split weights 16, split code 1.
-SWEEP_POINT_BYTES = 4 + 4 + 4 + 1 + 16 + 8 + 32 + 32 + 64 + 32
-SWEEP_ENTRY_BYTES = 4 + 16 + 1
-# the same in mixed precision (fp32 D, increments, records and weights; R stays fp64)
-SWEEP_POINT_BYTES_F32 = 4 + 4 + 4 + 1 + 16 + 4 + 32 + 16 + 32 + 16
-SWEEP_ENTRY_BYTES_F32 = 4 + 8 + 1
+# Algorithmic HBM bytes per point of each phase: every array read or written
+# once, neighbour data reused from cache, an interior point's 24-entry stencil
+# (CSR about 100 bytes); FP64.
+QGRAD_FIRST_B = 244   # U 32, xy 16, CSR 100 -> q, q_x, q_y 96
+QGRAD_INNER_B = 276   # q, q_x, q_y 96, xy 16, CSR 100 -> q_x, q_y 64
+LIMITER_B = 64        # the limited q_x, q_y written by the last pass (the limiter is an addition)
+RESIDUAL_B = 390      # q, q_x, q_y 96, xy 16, CSR 100, U 32 -> R 32, D and dt 16, linearisation 96
+NORM_B = 8            # R_rho^2
+SWEEP_FWD_B = 320     # R 32, D 8, CSR 100, xy 16, neighbours' linearisation 96, dU* 32 -> dU* 32
+SWEEP_BWD_B = 284     # dU* 32, D 8, CSR 100, xy 16, neighbours' linearisation 96 -> dU 32
+UPDATE_B = 128        # U 32, dU 32 -> U 32, q 32
 
 
 def residual_flops(cloud) -> float:
@@ -68,83 +76,50 @@ def residual_flops(cloud) -> float:
     return float(np.sum(deg[active] * (NB_OPS + splits[active] * SPLIT_OPS)))
 
 
-def forward_sweep_bytes(cloud, colours, mixed: bool = False) -> tuple[float, int]:
-    """Algorithmic bytes of the forward sweep's colour-phase launches and their
-    number: colours 1 and up (the colour-0 phase has no lower neighbours and is
-    formed inside the residual kernel), with every lower-list entry."""
+def sweep_points(colours) -> tuple[int, int, int]:
+    """Points swept by the forward colour-phase launches (colours 1 and up: the
+    colour-0 phase has no lower neighbours and is formed inside the residual
+    kernel), by the backward launches (all but the top colour, whose backward
+    phase is the identity), and the number of launches per direction."""
     import numpy as np
-    deg = np.diff(cloud.nbr_off)
-    src = np.repeat(np.arange(cloud.n), deg)
-    lower = int(np.count_nonzero(colours[cloud.nbr_idx] < colours[src]))
-    swept = int(np.count_nonzero(colours > 0))
-    pb, eb = ((SWEEP_POINT_BYTES_F32, SWEEP_ENTRY_BYTES_F32) if mixed
-              else (SWEEP_POINT_BYTES, SWEEP_ENTRY_BYTES))
-    return float(swept * pb + lower * eb), int(colours.max())
+    top = int(colours.max())
+    return (int(np.count_nonzero(colours > 0)), int(np.count_nonzero(colours < top)), top)
 
 
-def iteration_bytes(cloud, colours, mixed: bool = False) -> float:
-    """Algorithmic bytes of one whole iteration (m = 1 with the limiter), each
-    array read or written once, neighbour data counted once per pass:
-    q-derivative pass 0 (q 32, xy 16, offsets 8, LS matrix 32, 4 per stencil
-    entry, q_x/q_y write 64), the limited inner pass (q, q_x, q_y 96, xy 16,
-    offsets 8, LS matrix 32, 4 per entry, four derivative writes 128), the
-    residual (q, limited q_x, q_y 96, xy 16, frame 16, type 1, offsets 8,
-    split and diagonal coefficients 128, U 32, 4 per entry; R 32, R_rho^2 8,
-    linearisation records 64 and D 8 written, or 32 and 4 in mixed precision),
-    the norm (8), both sweeps as above and the update (U read and written 64,
-    dU 32 or 16, q written 32)."""
-    import numpy as np
-    deg = np.diff(cloud.nbr_off).astype(np.int64)
-    src = np.repeat(np.arange(cloud.n), deg)
-    lower = int(np.count_nonzero(colours[cloud.nbr_idx] < colours[src]))
-    upper = cloud.nnz - lower
-    if mixed:
-        per_point = 152 + 280 + 373 + 8 + 2 * SWEEP_POINT_BYTES_F32 + 112
-        entry = SWEEP_ENTRY_BYTES_F32
-    else:
-        per_point = 152 + 280 + 409 + 8 + 2 * SWEEP_POINT_BYTES + 128
-        entry = SWEEP_ENTRY_BYTES
-    return float(cloud.n * per_point + 3 * 4 * cloud.nnz + entry * (lower + upper))
+def iteration_bytes(n: int, inner: int = INNER, limiter: bool = True) -> float:
+    """Algorithmic HBM bytes of one whole iteration of n points."""
+    per_point = (QGRAD_FIRST_B + inner * QGRAD_INNER_B + (LIMITER_B if limiter else 0)
+                 + RESIDUAL_B + NORM_B + SWEEP_FWD_B + SWEEP_BWD_B + UPDATE_B)
+    return float(n * per_point)
 
 
-def large_cloud_run(lk, cloudgen, steps: int):
-    """The 2,621,440-point cloud (M 0.5, AoA 3 deg, the benchmark's solver
-    settings), FP64 and mixed precision: graph-replayed iterations from the
-    free stream, HIP-event phase times and the bandwidth figures; its working
-    set is larger than the 256 MB Infinity Cache."""
-    cloud = cloudgen.cloud_2621440()
-    gc = lk.Cloud(cloud)
-    colours = gc.colours()
+def kernel_rooflines(cloud, colours, phases: dict) -> dict:
+    """Roofline of each kernel of a step from its HIP-event phase time:
+    algorithmic work per launch / average launch duration."""
+    n = cloud.n
+    fwd_pts, bwd_pts, launches = sweep_points(colours)
     flops = residual_flops(cloud)
-    out = {"points": cloud.n, "edges": cloud.nnz, "colours": gc.n_colours}
-    for name, prec in (("fp64", lk.FP64), ("mixed", lk.MIXED)):
-        it_bytes = iteration_bytes(cloud, colours, mixed=prec == lk.MIXED)
-        fwd_b, fwd_launches = forward_sweep_bytes(cloud, colours, mixed=prec == lk.MIXED)
-        prm = lk.default_params(cfl=CFL, inner_iters=INNER, precision=prec, check_every=10,
-                                tol_rel=0.0, max_iters=10, limiter=LIMITER, limiter_k=LIMITER_K)
-        st = lk.State(gc, 0.5, 3.0, prm)
-        st.solve()
-        prm.max_iters = steps
-        st.set_params(prm)
-        rep = st.solve()
-        ms = 1e3 * rep.seconds / rep.iters
-        acc = None
-        for _ in range(10):
-            ph = st.step_timed()
-            acc = ph if acc is None else {k: acc[k] + ph[k] for k in acc}
-        phases = {k: v / 10 for k, v in acc.items()}
-        st.close()
-        sweep_gbs = fwd_b / (phases["forward_sweep"] * 1e-3) / 1e9
-        it_gbs = it_bytes / (ms * 1e-3) / 1e9
-        out[name] = {
-            "iters": rep.iters, "ms_per_iter": ms, "iteration_bytes": it_bytes,
-            "point_iters_per_s": cloud.n / (ms * 1e-3), "phases_ms": phases,
-            "iteration_gbs": it_gbs, "iteration_frac_hbm": it_gbs / PEAK_HBM_GBS,
-            "forward_sweep_gbs": sweep_gbs, "forward_sweep_frac_hbm": sweep_gbs / PEAK_HBM_GBS,
-            "forward_sweep_launches": fwd_launches,
-            "residual_tflops": flops / (phases["residual"] * 1e-3) / 1e12}
-        print(f"# 2.6M {name}: {ms:.3f} ms/iteration, whole iteration {it_gbs:.0f} GB/s, "
-              f"forward sweep {sweep_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+
+    def hbm(b_per_step, ms, nl):
+        gbs = b_per_step / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": gbs / PEAK_HBM_GBS, "bytes_per_launch": b_per_step / nl,
+                "avg_ms": ms / nl, "launches_per_step": nl, "ms_per_step": ms}
+
+    tf = flops / (phases["residual"] * 1e-3) / 1e12
+    out = {
+        "k_residual": {"bound": "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS,
+                       "unit": "TFLOP/s", "frac": tf / PEAK_FP64_TFLOPS,
+                       "flops_per_launch": flops, "avg_ms": phases["residual"],
+                       "launches_per_step": 1, "ms_per_step": phases["residual"],
+                       "bytes_per_launch": float(n * RESIDUAL_B)},
+        "k_sweep forward": hbm(fwd_pts * SWEEP_FWD_B, phases["forward_sweep"], launches),
+        "k_sweep backward": hbm(bwd_pts * SWEEP_BWD_B, phases["backward_sweep"], launches),
+        "k_qgrad (both passes)": hbm(n * (QGRAD_FIRST_B + INNER * QGRAD_INNER_B + LIMITER_B),
+                                     phases["q_derivatives"], 1 + INNER),
+        "k_update": hbm(n * UPDATE_B, phases["update"], 1),
+        "k_norm_partial + k_norm_comp": hbm(n * NORM_B, phases["norm"], 2),
+    }
     return out
 
 
@@ -153,10 +128,14 @@ def device_source_hash() -> str:
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE counter runs,
-    when the summary in profiles/ was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic_163840_transonic_fp64.md")
+TRAFFIC_FILE = {"fp64": "traffic_2621440_fp64.md", "mixed": "traffic_2621440_mixed.md"}
+
+
+def measured_traffic(precision: str = "fp64"):
+    """HBM bytes per launch of each kernel of the timed workload from rocprofv3
+    FETCH_SIZE/WRITE_SIZE counter runs, when the summary in profiles/ was taken
+    on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILE[precision])
     if not os.path.exists(path):
         return None
     out = {}
@@ -219,9 +198,8 @@ def batch_run(lk, cloudgen, iters):
     lanes = b.autotune(2)
     reps, tot = b.solve()
     pts = sum(r["iters"] * b.sizes[k] for k, r in enumerate(reps))
-    # algorithmic bytes: each condition's iterations on its own cloud (mixed precision)
-    cb = [iteration_bytes(c, g.colours(), mixed=True) for c, g in zip(clouds, gcs)]
-    moved = sum(r["iters"] * cb[k % 8] for k, r in enumerate(reps))
+    # algorithmic bytes: each condition's iterations on its own cloud
+    moved = sum(iteration_bytes(r["iters"] * b.sizes[k]) for k, r in enumerate(reps))
     out = {"conditions": 64, "clouds": [c.n for c in clouds], "points": b.n_points,
            "colour_phases": b.n_colours, "iters": iters, "seconds": tot,
            "point_iters_per_s": pts / tot, "iteration_gbs": moved / tot / 1e9,
@@ -459,18 +437,26 @@ def mlp_profile_run(lk) -> dict:
     return out
 
 
-def cpu_baseline(cloud, iters: int):
+def cpu_baseline(cloud, mach, aoa, min_seconds: float = 10.0, max_iters: int = 4):
+    """The CPU oracle (serial arithmetic, per-point loops and the points of a
+    colour over OpenMP threads, results independent of the thread count) on
+    the timed workload: whole iterations from the free-stream start until
+    min_seconds have passed or max_iters iterations have run."""
     import oracle
-    o = oracle.Oracle(cloud, mach=MACH, aoa_deg=AOA, cfl=CFL, inner_iters=INNER,
+    o = oracle.Oracle(cloud, mach=mach, aoa_deg=aoa, cfl=CFL, inner_iters=INNER,
                       limiter=LIMITER, limiter_k=LIMITER_K)
     U = o.free_stream()
     t0 = time.perf_counter()
-    for _ in range(iters):
+    it = 0
+    while it < max_iters and (it == 0 or time.perf_counter() - t0 < min_seconds):
         U, _, _, _ = o.iteration(U)
+        it += 1
     dt = time.perf_counter() - t0
-    return {"value": cloud.n * iters / dt, "unit": "point-iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} serial FP64 oracle iterations of the {cloud.n}-point workload "
-                      f"from the free-stream start ({dt:.1f} s) on one core of {host_cpu()}"}
+    cores = oracle.threads()
+    return {"value": cloud.n * it / dt, "unit": "point-iters/s", "cores": cores, "kind": "oracle",
+            "sample": f"{it} FP64 oracle iterations of the timed {cloud.n}-point workload from "
+                      f"the free-stream start ({dt:.1f} s), {cores} OpenMP threads on "
+                      f"{host_cpu()}"}
 
 
 def host_cpu() -> str:
@@ -486,43 +472,93 @@ def host_cpu() -> str:
     return f"{model} ({os.cpu_count()} logical CPUs)"
 
 
-def main():
+def check_every_for(steps: int) -> int:
+    """Iterations per captured graph: the largest of 40, 20, 10, 5, 4, 2, 1
+    that divides the timed step count (the library runs any remainder
+    eagerly, so this only sets how often the host reads the residual)."""
+    for d in (40, 20, 10, 5, 4, 2, 1):
+        if steps % d == 0:
+            return d
+    return 1
+
+
+def timed_run(lk, gc, mach, aoa, steps: int, warmup: int, precision, label: str):
+    """`warmup` untimed steps (the first captures the iteration graph), then
+    `steps` timed graph-replayed steps; then 10 eager steps with HIP events
+    between the phases.  Returns (seconds, report, phase ms)."""
+    import torch
+    every = check_every_for(steps)
+    prm = params(lk, check_every=every, tol_rel=0.0, max_iters=warmup, precision=precision)
+    st = lk.State(gc, mach, aoa, prm)
+    st.solve()   # captures the graph even for warmup == 0
+    prm.max_iters = steps
+    st.set_params(prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = st.solve()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    if rep.iters != steps:
+        st.close()
+        raise RuntimeError(f"{label}: timed solve stopped after {rep.iters} of {steps} steps "
+                           f"(status {rep.status})")
+    nt = 10
+    acc = None
+    for _ in range(nt):
+        ph = st.step_timed()
+        acc = ph if acc is None else {k: acc[k] + ph[k] for k in acc}
+    phases = {k: v / nt for k, v in acc.items()}
+    st.close()
+    print(f"# {label}: {steps} steps in {elapsed:.4f} s ({1e3 * elapsed / max(1, steps):.4f} "
+          f"ms/step), res {rep.res_final:.3e}; phases {json.dumps(phases)}",
+          file=sys.stderr, flush=True)
+    return elapsed, rep, phases
+
+
+def parse_args(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision run of the timed workload")
     ap.add_argument("--tol-iters", type=int, default=60000,
-                    help="iteration cap of the time-to-1e-8 runs (0 skips them)")
-    ap.add_argument("--batch-iters", type=int, default=200,
+                    help="iteration cap of the 163,840-point time-to-1e-8 runs (0 skips them)")
+    ap.add_argument("--batch-iters", type=int, default=100,
                     help="iterations of the 64-condition batch run (0 skips it)")
-    ap.add_argument("--cpu-iters", type=int, default=4, help="oracle iterations (0 skips)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum duration of the oracle sample (0 skips it)")
     ap.add_argument("--warm-steps", type=int, default=6000,
                     help="training steps of the warm-start leg (0 skips it)")
     ap.add_argument("--warm-held-out", type=int, default=4,
                     help="held-out conditions of the warm-start leg")
     ap.add_argument("--batch-converge-iters", type=int, default=0,
                     help="solve the 64-condition batch to 1e-8 with this cap (0 skips)")
-    ap.add_argument("--large-steps", type=int, default=200,
-                    help="graph-replayed iterations of the 2,621,440-point bandwidth leg (0 skips)")
     ap.add_argument("--config3-iters", type=int, default=0,
                     help="2,621,440-point FP64 vs mixed run to 1e-8 with this cap (0 skips)")
     ap.add_argument("--config3-precisions", default="fp64,mixed",
                     help="precisions of the --config3-iters leg (comma separated)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the timed steps (for profiler runs)")
+    ap.add_argument("--profile-precision", default="fp64", choices=("fp64", "mixed"),
+                    help="precision of the --profile-only run")
     ap.add_argument("--profile-mlp", action="store_true",
                     help="run only the warm-start network's training and inference "
                          "timing (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
-    args = ap.parse_args()
+    args = ap.parse_args(argv)
+    if args.steps < 1 or args.warmup < 0:
+        ap.error("--steps must be >= 1 and --warmup >= 0")
+    return args
+
+
+def main(argv=None):
+    args = parse_args(argv)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
               "(independent flow conditions would go to different GPUs; one cloud "
               "would split into point partitions with halo exchanges)", file=sys.stderr)
-        sys.exit(2)
-    if args.steps % 10 or args.warmup % 10:
-        print("--steps and --warmup must be multiples of 10", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -540,131 +576,99 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    cloud = cloudgen.cloud_163840()
+    t_setup = time.perf_counter()
+    cloud = cloudgen.cloud_2621440()
     gc = lk.Cloud(cloud)
-    # host readback of the residual every 40 iterations when the step counts allow
-    # (the convergence test itself runs on the device after every iteration)
-    every = 40 if args.steps % 40 == 0 and args.warmup % 40 == 0 else 10
-    prm = params(lk, check_every=every, tol_rel=0.0, max_iters=args.warmup)
-    st = lk.State(gc, MACH, AOA, prm)
+    colours = gc.colours()
     print(f"# cloud n={cloud.n} nnz={cloud.nnz} colours={gc.n_colours} "
-          f"degenerate={gc.n_degenerate}", file=sys.stderr, flush=True)
-    st.solve()                                    # warmup (captures the graph)
-    prm.max_iters = args.steps
-    st.set_params(prm)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rep = st.solve()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    if rep.iters != args.steps:
-        print(f"timed solve stopped after {rep.iters} steps (status {rep.status})",
-              file=sys.stderr)
-        sys.exit(1)
-    value = cloud.n * args.steps / elapsed
-    ms_per_step = 1e3 * elapsed / args.steps
-    print(f"# timed {args.steps} steps: {ms_per_step:.4f} ms/step, res {rep.res_final:.3e}",
+          f"degenerate={gc.n_degenerate} setup {time.perf_counter() - t_setup:.1f} s",
           file=sys.stderr, flush=True)
-
-    # per-phase GPU times (HIP events on the library's stream)
-    nt = 20
-    acc = None
-    for _ in range(nt):
-        ph = st.step_timed()
-        acc = ph if acc is None else {k: acc[k] + ph[k] for k in acc}
-    phases = {k: v / nt for k, v in acc.items()}
-    st.close()
-    ncol = gc.n_colours
-    traffic = measured_traffic()
-    flops = residual_flops(cloud)
-    res_ms = phases["residual"]
-    res_tf = flops / (res_ms * 1e-3) / 1e12
-    fwd_b, fwd_launches = forward_sweep_bytes(cloud, gc.colours())
-    sweep_ms = phases["forward_sweep"] / fwd_launches  # average launch of a colour phase
-    sweep_b = fwd_b / fwd_launches                     # algorithmic bytes per launch
-    sweep_gbs = sweep_b / (sweep_ms * 1e-3) / 1e9
-    kernels = {
-        "k_sweep_forward": {"bound": "hbm", "achieved": sweep_gbs, "peak": PEAK_HBM_GBS,
-                            "unit": "GB/s", "frac": sweep_gbs / PEAK_HBM_GBS,
-                            "traffic": (traffic or {}).get("k_sweep_forward"),
-                            "bytes_per_launch": sweep_b, "avg_ms": sweep_ms,
-                            "launches_per_step": fwd_launches,
-                            "ms_per_step": phases["forward_sweep"]},
-        "k_residual": {"bound": "alu", "achieved": res_tf, "peak": PEAK_FP64_TFLOPS,
-                       "unit": "TFLOP/s", "frac": res_tf / PEAK_FP64_TFLOPS,
-                       "traffic": (traffic or {}).get("k_residual"),
-                       "flops_per_launch": flops, "avg_ms": res_ms, "launches_per_step": 1,
-                       "ms_per_step": res_ms},
-    }
-    # the two q-derivative passes together (algorithmic bytes as in iteration_bytes)
-    # and the update, both against HBM
-    qg_b = float(cloud.n * (152 + 280) + 2 * 4 * cloud.nnz)
-    qg_gbs = qg_b / (phases["q_derivatives"] * 1e-3) / 1e9
-    up_b = float(cloud.n * 128)
-    up_gbs = up_b / (phases["update"] * 1e-3) / 1e9
-    others = {
-        "k_qgrad (both passes)": {"bound": "hbm", "achieved": qg_gbs, "peak": PEAK_HBM_GBS,
-                                  "unit": "GB/s", "frac": qg_gbs / PEAK_HBM_GBS,
-                                  "bytes_per_step": qg_b, "launches_per_step": 2,
-                                  "ms_per_step": phases["q_derivatives"]},
-        "k_update": {"bound": "hbm", "achieved": up_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": up_gbs / PEAK_HBM_GBS, "traffic": (traffic or {}).get("k_update"),
-                     "bytes_per_launch": up_b, "launches_per_step": 1,
-                     "ms_per_step": phases["update"]},
-    }
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-    kernels.update(others)
-    it_bytes = iteration_bytes(cloud, gc.colours())
-    it_gbs = it_bytes / (ms_per_step * 1e-3) / 1e9
-    iteration_bw = {"bytes_per_iteration": it_bytes, "achieved_gbs": it_gbs,
-                    "peak_gbs": PEAK_HBM_GBS, "frac": it_gbs / PEAK_HBM_GBS}
-    roofline = {"kernel": dom, **{k: v for k, v in kernels[dom].items()
-                                  if k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}}
+    precisions = [("fp64", lk.FP64)]
     if args.profile_only:
-        print(json.dumps({"ms_per_step": ms_per_step, "phases_ms": phases, "roofline": roofline}))
+        precisions = [(args.profile_precision, lk.FP64 if args.profile_precision == "fp64"
+                       else lk.MIXED)]
+    elif not args.no_mixed:
+        precisions.append(("mixed", lk.MIXED))
+    runs = {}
+    for name, prec in precisions:
+        elapsed, rep, phases = timed_run(lk, gc, HEAD_MACH, HEAD_AOA, args.steps, args.warmup,
+                                         prec, f"timed {name}")
+        kern = kernel_rooflines(cloud, colours, phases)
+        traffic = measured_traffic(name)
+        for k, v in kern.items():
+            v["traffic"] = (traffic or {}).get(k)
+        ms = 1e3 * elapsed / args.steps
+        it_gbs = iteration_bytes(cloud.n) / (ms * 1e-3) / 1e9
+        runs[name] = {"seconds": elapsed, "ms_per_step": ms,
+                      "point_iters_per_s": cloud.n * args.steps / elapsed,
+                      "res_final": rep.res_final, "res_fs": rep.res_fs, "phases_ms": phases,
+                      "kernels": kern,
+                      "iteration_bandwidth": {"bytes_per_iteration": iteration_bytes(cloud.n),
+                                              "achieved_gbs": it_gbs, "peak_gbs": PEAK_HBM_GBS,
+                                              "frac": it_gbs / PEAK_HBM_GBS}}
+    head = runs[precisions[0][0]]
+    dom = max(head["kernels"], key=lambda k: head["kernels"][k]["ms_per_step"])
+    roofline = {"kernel": dom, **{k: v for k, v in head["kernels"][dom].items()
+                                  if k in ("bound", "achieved", "peak", "unit", "frac",
+                                           "traffic")}}
+    if args.profile_only:
+        print(json.dumps({"ms_per_step": head["ms_per_step"], "phases_ms": head["phases_ms"],
+                          "roofline": roofline}))
         return
 
     extra = {}
-    if args.tol_iters > 0:
-        extra["time_to_1e-8"] = {
-            "exact_fp64": time_to_tol(lk, gc, args.tol_iters),
-            "fluxdiff_fp64": time_to_tol(lk, gc, args.tol_iters, jvp_mode=lk.JVP_FLUXDIFF),
-            "exact_mixed": time_to_tol(lk, gc, args.tol_iters, precision=lk.MIXED),
-        }
-        print(f"# time to tol: {json.dumps(extra['time_to_1e-8'])}", file=sys.stderr, flush=True)
-    if args.tol_iters > 0:
-        extra["explicit_vs_implicit_2000_iters"] = explicit_vs_implicit(lk, gc, 2000)
-        print(f"# explicit vs implicit: {json.dumps(extra['explicit_vs_implicit_2000_iters'])}",
+    if "mixed" in runs:
+        extra["mixed_precision_same_workload"] = {
+            **runs["mixed"], "speedup_vs_fp64": runs["fp64"]["seconds"] / runs["mixed"]["seconds"]}
+
+    def leg(name, fn, *a):
+        t = time.perf_counter()
+        extra[name] = fn(*a)
+        print(f"# {name} ({time.perf_counter() - t:.1f} s): {json.dumps(extra[name])}",
               file=sys.stderr, flush=True)
+
+    if args.tol_iters > 0:
+        c2 = cloudgen.cloud_163840()
+        g2 = lk.Cloud(c2)
+
+        def tol_legs():
+            return {"workload": "640x256=163840 pts O-grid, 4% jittered, M0.85 AoA1, limiter K5",
+                    "exact_fp64": time_to_tol(lk, g2, args.tol_iters),
+                    "fluxdiff_fp64": time_to_tol(lk, g2, args.tol_iters,
+                                                 jvp_mode=lk.JVP_FLUXDIFF),
+                    "exact_mixed": time_to_tol(lk, g2, args.tol_iters, precision=lk.MIXED)}
+        leg("time_to_1e-8_163840", tol_legs)
+        leg("explicit_vs_implicit_163840_2000_iters", explicit_vs_implicit, lk, g2, 2000)
+        g2.close()
     if args.batch_iters > 0:
-        extra["batch_64_conditions"] = batch_run(lk, cloudgen, args.batch_iters)
-        print(f"# batch: {json.dumps(extra['batch_64_conditions'])}", file=sys.stderr, flush=True)
+        leg("batch_64_conditions", batch_run, lk, cloudgen, args.batch_iters)
     if args.batch_converge_iters > 0:
-        extra["batch_64_to_1e-8"] = batch_converge(lk, cloudgen, args.batch_converge_iters)
-        print(f"# batch to 1e-8: {json.dumps(extra['batch_64_to_1e-8'])}", file=sys.stderr,
-              flush=True)
-    if args.large_steps > 0:
-        extra["cloud_2621440_bandwidth"] = large_cloud_run(lk, cloudgen, args.large_steps)
+        leg("batch_64_to_1e-8", batch_converge, lk, cloudgen, args.batch_converge_iters)
     if args.config3_iters > 0:
-        extra["cloud_2621440_to_1e-8"] = config3_run(lk, cloudgen, args.config3_iters,
-                                                     args.config3_precisions.split(","))
-        print(f"# 2.6M: {json.dumps(extra['cloud_2621440_to_1e-8'])}", file=sys.stderr, flush=True)
+        leg("cloud_2621440_to_1e-8", config3_run, lk, cloudgen, args.config3_iters,
+            args.config3_precisions.split(","))
     if args.warm_steps > 0:
-        extra["warm_start"] = warm_start_run(lk, cloudgen, args.warm_steps, args.warm_held_out)
-        print(f"# warm start: {json.dumps(extra['warm_start'])}", file=sys.stderr, flush=True)
-    cpu = cpu_baseline(cloud, args.cpu_iters) if args.cpu_iters > 0 else None
+        leg("warm_start", warm_start_run, lk, cloudgen, args.warm_steps, args.warm_held_out)
+    cpu = None
+    if args.cpu_seconds > 0:
+        t = time.perf_counter()
+        cpu = cpu_baseline(cloud, HEAD_MACH, HEAD_AOA, args.cpu_seconds)
+        print(f"# cpu baseline ({time.perf_counter() - t:.1f} s): {json.dumps(cpu)}",
+              file=sys.stderr, flush=True)
 
     line = {
         "metric": "point-iters/s + time to 1e-8 res drop: exact-JVP LU-SGS FP64 vs mixed+batched",
-        "value": value, "unit": "point-iters/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "O-grid NACA0012-type cloud 640x256=163840 pts, 4% jittered, "
-                               "M0.85 AoA1, exact-JVP LU-SGS FP64, CFL100, 1 inner iteration, "
-                               "limiter K5",
-                   "points": cloud.n, "edges": cloud.nnz, "colours": ncol},
-        "roofline": roofline, "roofline_kernels": kernels, "cpu_baseline": cpu,
-        "iteration_bandwidth": iteration_bw, "phases_ms": phases, **extra,
+        "value": head["point_iters_per_s"], "unit": "point-iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "O-grid cloud 2560x1024=2621440 pts around a 12% symmetric "
+                               "profile, M0.5 AoA3, exact-JVP LU-SGS FP64, CFL100, 1 inner "
+                               "iteration, limiter K5",
+                   "points": cloud.n, "edges": cloud.nnz, "colours": gc.n_colours},
+        "roofline": roofline, "roofline_kernels": head["kernels"], "cpu_baseline": cpu,
+        "iteration_bandwidth": head["iteration_bandwidth"], "phases_ms": head["phases_ms"],
+        **extra,
     }
     print(json.dumps(line))
 

@@ -343,6 +343,12 @@ int lskum_mlp_warm_start_batch(lskum_mlp* net, lskum_batch* b, int32_t* fallback
 /* Message of the last error on the calling thread ("" if none). */
 const char* lskum_last_error(void);
 
+/* Identifier of the sources the library was compiled from (16 hex digits of
+ * a SHA-256 over the sources and headers; "unknown" when not set at build
+ * time), so that callers can refuse a binary that does not match the sources
+ * they were written against. */
+const char* lskum_build_hash(void);
+
 #ifdef __cplusplus
 }
 #endif

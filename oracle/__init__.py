@@ -25,7 +25,7 @@ OK, ERR_ARG, ERR_CONN, ERR_DEGEN, ERR_COLOUR, ERR_NONPHYS = 0, -1, -2, -3, -4, -
 def build(force: bool = True) -> str:
     """Compile the oracle with g++ (no fused multiply-add, no fast math)."""
     if force or not os.path.exists(_LIB):
-        cmd = ["g++", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c++17",
+        cmd = ["g++", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-std=c++17",
                "-shared", "-fPIC", _SRC, "-o", _LIB + ".tmp"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
@@ -78,6 +78,8 @@ def lib():
             "ora_manish_source": (None, [P, P, P, P, P]),
             "ora_solve": (I32, [P, P, P, I32, D, P]),
             "ora_forces": (I32, [P, P, P, P, P]),
+            "ora_set_threads": (None, [I32]),
+            "ora_threads": (I32, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -93,6 +95,15 @@ def _p(a: np.ndarray | None):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's per-point loops (results do not depend on it)."""
+    lib().ora_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(lib().ora_threads())
 
 
 def colour(cloud) -> tuple[np.ndarray, int]:
@@ -295,6 +306,8 @@ class Oracle:
                                     C.byref(ls1))
         if m < 0:
             raise IndexError("no such split")
+        if m > cap:
+            raise ValueError(f"split stencil of point {p} has {m} members, more than cap={cap}")
         return nb[:m].copy(), w[:m].copy(), float(ls1.value)
 
     def split_dirs(self, p):

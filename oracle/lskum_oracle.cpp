@@ -11,7 +11,13 @@
 // function.  Where the paper is silent, the reading used is stated as
 // "Reading:" and applies to the HIP path as well.
 //
-// Build: g++ -O2 -ffp-contract=off -fno-fast-math -std=c++17 -shared -fPIC
+// Build: g++ -O2 -ffp-contract=off -fno-fast-math -fopenmp -std=c++17 -shared -fPIC
+//
+// Threads: the per-point loops (and, in the sweeps, the points of one colour)
+// are split over OpenMP threads.  Every point writes only its own outputs
+// from inputs no other iteration of the same loop writes, and the sums over
+// points (residual norm, forces) stay serial, so results are bitwise the same
+// for any thread count (tested).
 //
 // Conventions
 //   U = (rho, rho u1, rho u2, rho E), E total specific energy (eq. 2; the
@@ -30,6 +36,8 @@
 // Parity unpinned (no external value exists): the boundary treatment,
 // the time step rule, the residual norm, the tolerance anchor and the force
 // integration rule are readings, pinned only by invariants.
+
+#include <omp.h>
 
 #include <cmath>
 #include <cstdint>
@@ -275,6 +283,7 @@ void free_stream(const Cloud& c, const Params& P, double* U) {
 // q_variables(): eq. (14) at every point (Algorithm 1).
 int q_variables(const Cloud& c, const Params& P, const double* U, double* q) {
     int st = OK;
+#pragma omp parallel for reduction(min : st)
     for (int64_t p = 0; p < c.n; ++p) {
         double Up[4] = {U[p], U[c.n + p], U[2 * c.n + p], U[3 * c.n + p]};
         Prim<double> w = prim_from_U(Up, P.gamma);
@@ -294,6 +303,8 @@ int q_variables(const Cloud& c, const Params& P, const double* U, double* q) {
 // Reading: the inner iterations are Jacobi sweeps over all points.
 int q_grad_pass(const Cloud& c, const double* q, const double* qx_in, const double* qy_in,
                 double* qx_out, double* qy_out) {
+    int st = OK;
+#pragma omp parallel for reduction(min : st)
     for (int64_t p = 0; p < c.n; ++p) {
         double sxx = 0, syy = 0, sxy = 0;
         double bx[4] = {0, 0, 0, 0}, by[4] = {0, 0, 0, 0};
@@ -314,13 +325,16 @@ int q_grad_pass(const Cloud& c, const double* q, const double* qx_in, const doub
             }
         }
         double det = sxx * syy - sxy * sxy;
-        if (!(det > 1e-12 * sxx * syy)) return ERR_DEGEN;
+        if (!(det > 1e-12 * sxx * syy)) {
+            st = ERR_DEGEN;
+            continue;
+        }
         for (int v = 0; v < 4; ++v) {
             qx_out[v * c.n + p] = (syy * bx[v] - sxy * by[v]) / det;
             qy_out[v * c.n + p] = (sxx * by[v] - sxy * bx[v]) / det;
         }
     }
-    return OK;
+    return st;
 }
 
 // q_derivatives(): first-order pass, then m inner iterations (eq. 16).
@@ -349,6 +363,7 @@ int q_derivatives(const Cloud& c, const Params& P, const double* q, double* qx, 
 // distance.  The residual then uses phi_p * (qx_p, qy_p).
 void limit_gradients(const Cloud& c, const Params& P, const double* q, double* qx, double* qy) {
     std::vector<double> phi(4 * c.n, 1.0);
+#pragma omp parallel for
     for (int64_t p = 0; p < c.n; ++p) {
         double rmin = INFINITY;
         double dmax[4] = {0, 0, 0, 0}, dmin[4] = {0, 0, 0, 0};
@@ -397,6 +412,7 @@ int flux_residual(const Cloud& c, const Params& P, const double* q, const double
                   const double* qy, double* R, int64_t* degenerate_count) {
     int st = OK;
     int64_t ndeg = 0;
+#pragma omp parallel for reduction(min : st) reduction(+ : ndeg)
     for (int64_t p = 0; p < c.n; ++p) {
         double Rp[4] = {0, 0, 0, 0};
         Split sp[4];
@@ -496,6 +512,7 @@ void unsplit_jvp(const double U[4], const double dU[4], double dx, double dy, co
 // the rho part gives the scalar D_0 = 1/dt_0 - sum_k s_k LS_k(1) rho(A_k)/2 and
 // the A part the term S of manish_source.
 void timestep_diag(const Cloud& c, const Params& P, const double* U, double* dt, double* D) {
+#pragma omp parallel for
     for (int64_t p = 0; p < c.n; ++p) {
         double Up[4] = {U[p], U[c.n + p], U[2 * c.n + p], U[3 * c.n + p]};
         Prim<double> w = prim_from_U(Up, P.gamma);
@@ -537,6 +554,7 @@ void timestep_diag(const Cloud& c, const Params& P, const double* U, double* dt,
 // LS_k+(1) = -LS_k-(1) and S vanishes.
 void manish_source(const Cloud& c, const Params& P, const double* U, const double* dU_prev,
                    double* S) {
+#pragma omp parallel for
     for (int64_t p = 0; p < c.n; ++p) {
         double Sp[4] = {0, 0, 0, 0};
         Split sp[4];
@@ -604,11 +622,17 @@ void lusgs(const Cloud& c, const Params& P, const double* U, const double* R, co
         if (c.type[p] == 0) project_out_normal(c, p, out);
         for (int v = 0; v < 4; ++v) dU[v * c.n + p] = out[v];
     };
+    // the points of one colour share no edge: they are swept in parallel
+    auto sweep_colour = [&](int col, bool forward, int g) {
+        const std::vector<int64_t>& pts = by_colour[col];
+        const int64_t m = (int64_t)pts.size();
+#pragma omp parallel for
+        for (int64_t j = 0; j < m; ++j)
+            if (g < 0 || c.type[pts[j]] == g) sweep_point(pts[j], forward);
+    };
     if (P.order == 0) {
-        for (int col = 0; col < c.ncolour; ++col)
-            for (int64_t p : by_colour[col]) sweep_point(p, true);
-        for (int col = c.ncolour - 1; col >= 0; --col)
-            for (int64_t p : by_colour[col]) sweep_point(p, false);
+        for (int col = 0; col < c.ncolour; ++col) sweep_colour(col, true, -1);
+        for (int col = c.ncolour - 1; col >= 0; --col) sweep_colour(col, false, -1);
         return;
     }
     // Algorithm 5: the same per-point sweeps, grouped into wall, interior and
@@ -618,18 +642,15 @@ void lusgs(const Cloud& c, const Params& P, const double* U, const double* R, co
     // the shared increment array holds for them at that moment.
     const int8_t groups[3] = {0, 1, 2};
     for (int8_t g : groups)
-        for (int col = 0; col < c.ncolour; ++col)
-            for (int64_t p : by_colour[col])
-                if (c.type[p] == g) sweep_point(p, true);
+        for (int col = 0; col < c.ncolour; ++col) sweep_colour(col, true, g);
     for (int8_t g : groups)
-        for (int col = c.ncolour - 1; col >= 0; --col)
-            for (int64_t p : by_colour[col])
-                if (c.type[p] == g) sweep_point(p, false);
+        for (int col = c.ncolour - 1; col >= 0; --col) sweep_colour(col, false, g);
 }
 
 // state_update(): U <- U + dU (Section 3, definition of dU).
 int state_update(const Cloud& c, const Params& P, double* U, const double* dU) {
     int st = OK;
+#pragma omp parallel for reduction(min : st)
     for (int64_t p = 0; p < c.n; ++p) {
         for (int v = 0; v < 4; ++v) U[v * c.n + p] += dU[v * c.n + p];
         double Up[4] = {U[p], U[c.n + p], U[2 * c.n + p], U[3 * c.n + p]};
@@ -719,6 +740,12 @@ int32_t ora_colour(int64_t n, const int32_t* off, const int32_t* idx, int32_t* c
         if (colour[i] + 1 > nc) nc = colour[i] + 1;
     return nc;
 }
+
+// Number of OpenMP threads of the oracle's loops (n >= 1), and the current one.
+void ora_set_threads(int32_t n) {
+    if (n >= 1) omp_set_num_threads(n);
+}
+int32_t ora_threads(void) { return (int32_t)omp_get_max_threads(); }
 
 void ora_split_flux(const double* U, double dx, double dy, int32_t s, double gamma, double* G) {
     split_flux(prim_from_U(U, gamma), dx, dy, s, gamma, G);
@@ -889,6 +916,7 @@ int32_t ora_explicit_iteration(const ora_cloud* oc, const ora_params* prm, doubl
     if (st) return st;
     timestep_diag(c, P, U, dt.data(), D.data());
     std::vector<double> dU(4 * c.n);
+#pragma omp parallel for
     for (int64_t p = 0; p < c.n; ++p)
         for (int v = 0; v < 4; ++v) dU[v * c.n + p] = -dt[p] * R[v * c.n + p];
     st = state_update(c, P, U, dU.data());

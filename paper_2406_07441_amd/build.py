@@ -1,6 +1,7 @@
 """Builds the HIP library ``liblskum.so`` for gfx950 in-tree with hipcc."""
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 
@@ -25,11 +26,23 @@ def hipcc() -> str:
     return "hipcc"
 
 
+def source_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the library's sources and headers;
+    compiled into the library (lskum_build_hash) so that a stale binary is
+    recognised by content, whatever the file times."""
+    h = hashlib.sha256()
+    for f in SOURCES + HEADERS:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     """Compiles the library (always) and returns its path."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(os.path.dirname(HERE), "include"),
-           *SOURCES, "-o", tmp]
+    cmd = [hipcc(), *HIPCC_FLAGS, f'-DLSKUM_BUILD_HASH="{source_hash()}"',
+           "-I", os.path.join(os.path.dirname(HERE), "include"), *SOURCES, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

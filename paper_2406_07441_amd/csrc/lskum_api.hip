@@ -601,11 +601,20 @@ void fill_report(lskum_report& r, const lskum::State& s, const SolveOut& o, int 
 
 int lskum::api_error(int code, const std::string& msg) { return fail(code, msg); }
 
+int lskum::api_check_params(const lskum_params* p) { return check_params(p); }
+
+lskum::Params lskum::api_params(const lskum_params* p) { return to_params(p); }
+
 void lskum::api_clear_error() { g_err.clear(); }
 
 extern "C" {
 
 const char* lskum_last_error(void) { return g_err.c_str(); }
+
+#ifndef LSKUM_BUILD_HASH
+#define LSKUM_BUILD_HASH "unknown"
+#endif
+const char* lskum_build_hash(void) { return LSKUM_BUILD_HASH; }
 
 void lskum_default_params(lskum_params* p) {
     if (!p) return;

@@ -1547,6 +1547,20 @@ __global__ void k_fill(int n, double v, double* __restrict__ out) {
     if (k < n) out[k] = v;
 }
 
+hipError_t launch_fill(double* p, int n, double v, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_fill, dim3((n + 255) / 256), dim3(256), 0, st, n, v, p);
+    return hipGetLastError();
+}
+
+__global__ void k_copy_flag(const int32_t* __restrict__ src, int32_t* __restrict__ dst) {
+    if (threadIdx.x == 0) dst[0] = src[0];
+}
+
+hipError_t launch_copy_flag(const int32_t* src, int32_t* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_flag, dim3(1), dim3(64), 0, st, src, dst);
+    return hipGetLastError();
+}
+
 hipError_t reset_cfl(State& s) {
     const int nc = s.cloud->ncomp;
     hipLaunchKernelGGL(k_fill, dim3((nc + 255) / 256), dim3(256), 0, s.stream, nc, s.prm.cfl,

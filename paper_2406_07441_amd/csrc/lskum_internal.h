@@ -3,10 +3,13 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <string>
 #include <type_traits>
 #include <vector>
+
+#include "../../include/lskum.h"
 
 namespace lskum {
 
@@ -207,10 +210,18 @@ hipError_t clear_increment(State& s, int64_t p0, int64_t n);
 // every component's CFL number to params.cfl
 hipError_t reset_cfl(State& s);
 
+// fill n doubles with v, and copy one int32 (kernels, so that graph capture
+// records no memset node)
+hipError_t launch_fill(double* p, int n, double v, hipStream_t st);
+hipError_t launch_copy_flag(const int32_t* src, int32_t* dst, hipStream_t st);
+
 // Error reporting shared by the C-ABI source files: records msg for
 // lskum_last_error() and returns code.
 int api_error(int code, const std::string& msg);
 void api_clear_error();
+// lskum_params validation and conversion (as lskum_state_create applies them)
+int api_check_params(const lskum_params* p);
+Params api_params(const lskum_params* p);
 
 }  // namespace lskum
 

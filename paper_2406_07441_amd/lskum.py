@@ -101,11 +101,13 @@ _SIGS = {
     "lskum_mlp_warm_start": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lskum_mlp_warm_start_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lskum_last_error": (C.c_char_p, []),
+    "lskum_build_hash": (C.c_char_p, []),
 }
 
 
 def lib():
-    """Loads the in-tree HIP library; raises if it has not been built."""
+    """Loads the in-tree HIP library; raises if it has not been built or was
+    built from other sources than the ones in the tree."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
@@ -116,6 +118,11 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        from . import build
+        built, now = L.lskum_build_hash().decode(), build.source_hash()
+        if built != now:
+            raise RuntimeError(f"{LIB_PATH} was built from other sources (hash {built}, tree "
+                               f"{now}): rebuild it with `python -m paper_2406_07441_amd.build`")
         _lib = L
     return _lib
 

@@ -1,9 +1,11 @@
 """The benchmark's algorithmic work counts (the basis of its roofline figures),
-checked against brute-force counts on a small O-grid cloud (CPU only)."""
+checked against brute-force counts on a small O-grid cloud, and its command
+line as the benchmark driver calls it (CPU only)."""
 import os
 import sys
 
 import numpy as np
+import pytest
 
 import oracle as O
 from paper_2406_07441_amd import cloudgen as cg
@@ -18,30 +20,41 @@ def small_case():
     return cloud, colours
 
 
-def test_forward_sweep_bytes_counts_points_and_lower_entries():
+def test_sweep_points_exclude_the_fused_and_identity_phases():
     cloud, col = small_case()
-    swept, lower = 0, 0
-    for p in range(cloud.n):
-        if col[p] > 0:
-            swept += 1
-        for e in range(cloud.nbr_off[p], cloud.nbr_off[p + 1]):
-            lower += col[cloud.nbr_idx[e]] < col[p]
-    for mixed, pb, eb in ((False, bench.SWEEP_POINT_BYTES, bench.SWEEP_ENTRY_BYTES),
-                          (True, bench.SWEEP_POINT_BYTES_F32, bench.SWEEP_ENTRY_BYTES_F32)):
-        b, launches = bench.forward_sweep_bytes(cloud, col, mixed=mixed)
-        assert b == swept * pb + lower * eb
-        assert launches == col.max()  # colour 0 is formed inside the residual kernel
-    assert bench.SWEEP_POINT_BYTES == 197 and bench.SWEEP_ENTRY_BYTES == 21
+    fwd, bwd, launches = bench.sweep_points(col)
+    top = col.max()
+    assert fwd == sum(1 for p in range(cloud.n) if col[p] > 0)
+    assert bwd == sum(1 for p in range(cloud.n) if col[p] < top)
+    assert launches == top  # colour 0 inside the residual kernel, the top colour skipped
 
 
-def test_iteration_bytes_split_the_stencil_once():
+def test_phase_bytes_follow_the_per_point_table():
+    # q, q_x, q_y and the CSR of a 24-neighbour stencil, each read or written once
+    assert bench.QGRAD_FIRST_B == 32 + 16 + 100 + 96
+    assert bench.QGRAD_INNER_B == 96 + 16 + 100 + 64
+    assert bench.RESIDUAL_B == 96 + 16 + 100 + 32 + 32 + 16 + 96 + 2
+    assert bench.SWEEP_FWD_B == 32 + 8 + 100 + 16 + 96 + 32 + 32 + 4
+    assert bench.SWEEP_BWD_B == 32 + 8 + 100 + 16 + 96 + 32
+    n = 1000
+    assert bench.iteration_bytes(n) == n * (244 + 276 + 64 + 390 + 8 + 320 + 284 + 128)
+    assert bench.iteration_bytes(n, inner=3, limiter=False) == n * (244 + 3 * 276 + 390 + 8
+                                                                    + 320 + 284 + 128)
+
+
+def test_kernel_rooflines_divide_work_by_launch_time():
     cloud, col = small_case()
-    b64 = bench.iteration_bytes(cloud, col)
-    b32 = bench.iteration_bytes(cloud, col, mixed=True)
-    # every stencil entry appears in exactly one of the lower and upper lists
-    per_point = 152 + 280 + 409 + 8 + 2 * bench.SWEEP_POINT_BYTES + 128
-    assert b64 == cloud.n * per_point + 12 * cloud.nnz + bench.SWEEP_ENTRY_BYTES * cloud.nnz
-    assert b32 < b64
+    phases = {"q_derivatives": 0.02, "residual": 0.05, "norm": 0.004, "forward_sweep": 0.03,
+              "backward_sweep": 0.03, "update": 0.002}
+    k = bench.kernel_rooflines(cloud, col, phases)
+    fwd, _, launches = bench.sweep_points(col)
+    f = k["k_sweep forward"]
+    assert f["launches_per_step"] == launches
+    assert np.isclose(f["achieved"], fwd * bench.SWEEP_FWD_B / 0.03e-3 / 1e9)
+    assert np.isclose(f["frac"], f["achieved"] / 8000.0)
+    r = k["k_residual"]
+    assert r["bound"] == "alu" and np.isclose(r["achieved"],
+                                              bench.residual_flops(cloud) / 0.05e-3 / 1e12)
 
 
 def test_residual_flops_per_point():
@@ -57,3 +70,22 @@ def test_residual_flops_per_point():
     # an interior point with the full 5 x 5 ring: 24 x (140 + 2 x 161)
     assert bench.NB_OPS == 140 and bench.SPLIT_OPS == 161
     assert 24 * (bench.NB_OPS + 2 * bench.SPLIT_OPS) == 11088
+
+
+def test_driver_command_line_is_accepted():
+    # the driver's own invocation; any positive step count and any warm-up
+    a = bench.parse_args(["--gpus", "1", "--steps", "20", "--warmup", "5"])
+    assert (a.gpus, a.steps, a.warmup) == (1, 20, 5)
+    for steps, warmup in ((7, 0), (1, 3), (400, 40)):
+        a = bench.parse_args(["--steps", str(steps), "--warmup", str(warmup)])
+        assert bench.check_every_for(steps) >= 1 and steps % bench.check_every_for(steps) == 0
+    assert bench.check_every_for(20) == 20 and bench.check_every_for(200) == 40
+    with pytest.raises(SystemExit):
+        bench.parse_args(["--steps", "0"])
+
+
+def test_more_than_one_gpu_exits_with_a_message(capsys):
+    with pytest.raises(SystemExit) as ei:
+        bench.main(["--gpus", "2"])
+    assert ei.value.code == 2
+    assert "one GPU" in capsys.readouterr().err

@@ -5,8 +5,11 @@
   and increment of the free-stream start and of the oracle's state after five
   iterations, and five graph-replayed iterations of ``lskum_solve`` against
   five oracle iterations -- whole fields, FP64 bar 1e-11.
-* 2,621,440-point cloud (2560 x 1024, M 0.5, AoA 3 deg): residual and
-  increment of the free-stream start, FP64 (1e-11) and mixed precision (1e-4).
+* 2,621,440-point cloud (2560 x 1024, M 0.5, AoA 3 deg, the benchmark's timed
+  workload: CFL 100, one inner iteration, limiter K 5): the GPU's own FP64
+  states after 0, 1 and 10 graph-replayed iterations loaded into the oracle,
+  residual, increment and new state of the next iteration (FP64 bar 1e-11,
+  per component); mixed precision against the FP64 oracle (1e-4).
 """
 import numpy as np
 import pytest
@@ -20,7 +23,10 @@ TOL = 1e-11
 
 
 def rel(a, b):
-    return float(np.abs(a - b).max() / np.abs(b).max())
+    """Largest error relative to the reference's magnitude, per component."""
+    scale = np.abs(b).max()
+    return float(max(np.abs(a[v] - b[v]).max() / (np.abs(b[v]).max() or scale)
+                     for v in range(b.shape[0])))
 
 
 @pytest.fixture(scope="module")
@@ -66,19 +72,44 @@ def test_transonic_163840_benchmark_configuration(lk):
     st.close()
 
 
-def test_cloud_2621440_free_stream_step(lk):
+def test_cloud_2621440_benchmark_configuration(lk):
+    # the timed workload of the benchmark: FP64 states after 0, 1 and 10
+    # graph-replayed GPU iterations are loaded into the oracle; the residual and
+    # the next iteration's increment and state must agree
     cloud = cg.cloud_2621440()
-    o = O.Oracle(cloud, mach=0.5, aoa_deg=3.0, cfl=100.0, inner_iters=1)
+    kw = dict(cfl=100.0, inner_iters=1, limiter=1, limiter_k=5.0)
+    o = O.Oracle(cloud, mach=0.5, aoa_deg=3.0, **kw)
     gc = lk.Cloud(cloud)
-    U0 = o.free_stream()
-    Ro, reso = o.residual(U0)
-    _, _, dUo, _ = o.iteration(U0)
-    for prec, tol in ((lk.FP64, TOL), (lk.MIXED, 1e-4)):
-        st = lk.State(gc, 0.5, 3.0, lk.default_params(cfl=100.0, inner_iters=1, precision=prec))
+    assert np.array_equal(gc.colours(), o.colours)
+    prm = lk.default_params(check_every=1, tol_rel=0.0, max_iters=1, **kw)
+    st = lk.State(gc, 0.5, 3.0, prm)
+    states = {0: st.get_U()}
+    assert rel(states[0], o.free_stream()) < 1e-14
+    st.solve()
+    states[1] = st.get_U()
+    prm.max_iters = 9
+    st.set_params(prm)
+    st.solve()
+    states[10] = st.get_U()
+    dUo10 = None
+    for it in (0, 1, 10):
+        U = states[it]
+        st.set_U(U)
         R, res = st.residual()
-        assert rel(R, Ro) < TOL and abs(res - reso) <= TOL * reso
+        Ro, reso = o.residual(U)
+        st.set_U(U)
         st.step()
-        e = rel(st.get_dU(), dUo)
-        print(f"2621440 precision={prec}: dU rel err {e:.3e}")
-        assert e < tol
-        st.close()
+        Un, _, dUo, _ = o.iteration(U)
+        e = (rel(R, Ro), rel(st.get_dU(), dUo), rel(st.get_U() - U, Un - U))
+        print(f"2621440 GPU state after {it} iterations: R {e[0]:.2e} dU {e[1]:.2e} "
+              f"U change {e[2]:.2e}", flush=True)
+        assert max(e) < TOL and abs(res - reso) <= TOL * reso
+        dUo10 = dUo
+    st.close()
+    mx = lk.State(gc, 0.5, 3.0, lk.default_params(precision=lk.MIXED, **kw))
+    mx.set_U(states[10])
+    mx.step()
+    e = rel(mx.get_dU(), dUo10)
+    print(f"2621440 mixed precision, state after 10 iterations: dU rel err {e:.3e}")
+    assert e < 1e-4
+    mx.close()

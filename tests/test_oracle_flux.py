@@ -5,8 +5,8 @@ eq. (3)-(4) (Section 2, CIR splitting eq. 5 -> KFVS eq. 6).  The paper prints
 no closed form, so the oracle's closed form is pinned here against direct
 numerical quadrature of those moments, against G+ + G- = G (eq. 2), and
 against the limits S -> +-inf.  The exact Jacobian-vector products are pinned
-against central differences of the flux and against the unsplit Jacobian
-product written out from eq. (2) (the quantity of Listings 2-3).
+against central differences of the flux and, summed over the two halves,
+against the complex-step derivative of the unsplit flux of eq. (2).
 """
 import math
 
@@ -32,24 +32,12 @@ def unsplit_flux(U, d, g=GAMMA):
     return np.array([rho * ud, p * d[0] + m1 * ud, p * d[1] + m2 * ud, (E + p) * ud])
 
 
-def unsplit_jvp(U, dU, d, g=GAMMA):
-    """Unsplit flux Jacobian times dU along d, written out by the chain rule
-    (the tangent computed by the paper's Listings 2-3 for d = x)."""
-    rho, m1, m2, E = U
-    u1, u2 = m1 / rho, m2 / rho
-    rd = dU[0]
-    u1d = (dU[1] - u1 * rd) / rho
-    u2d = (dU[2] - u2 * rd) / rho
-    p = (g - 1) * (E - 0.5 * rho * (u1 * u1 + u2 * u2))
-    pd = (g - 1) * (dU[3] - 0.5 * (rd * (u1 * u1 + u2 * u2) + rho * (2 * u1 * u1d + 2 * u2 * u2d)))
-    ud = u1 * d[0] + u2 * d[1]
-    udd = u1d * d[0] + u2d * d[1]
-    return np.array([
-        rd * ud + rho * udd,
-        pd * d[0] + dU[1] * ud + m1 * udd,
-        pd * d[1] + dU[2] * ud + m2 * udd,
-        (dU[3] + pd) * ud + (E + p) * udd,
-    ])
+def unsplit_jvp(U, dU, d, g=GAMMA, h=1e-30):
+    """Unsplit flux Jacobian times dU along d by complex-step differentiation
+    of eq. (2): the flux is a rational function of U, so
+    Im F(U + i h dU) / h is its directional derivative to rounding."""
+    return np.imag(unsplit_flux(np.asarray(U, complex) + 1j * h * np.asarray(dU, complex),
+                                d, g)) / h
 
 
 def quad_split_flux(rho, u1, u2, p, d, s, g=GAMMA):

@@ -68,6 +68,29 @@ def test_symmetric_stencil_source_vanishes_and_diagonal_closed_form():
     assert np.allclose(D[inner], want[inner], rtol=1e-12)
 
 
+@pytest.mark.parametrize("aoa", [0.0, 180.0, 30.0])
+def test_anandh_diagonal_with_supersonic_split_velocity(aoa):
+    # eq. (34)-(35): rho(A+) = max(u_d + a, 0), rho(A-) = max(a - u_d, 0); on the
+    # symmetric 5 x 5 ring of a uniform box LS_d+(1) = -0.6/h, LS_d-(1) = +0.6/h,
+    # so D = 1/dt + 0.6/h sum_d [max(u_d + a, 0) + max(a - u_d, 0)].  At M 1.5 the
+    # split velocity exceeds the speed of sound and one half vanishes
+    # (|u_d + a| or |a - u_d| would not).
+    c = cg.box(11, 11, h=0.1)
+    o = O.Oracle(c, mach=1.5, aoa_deg=aoa, cfl=10.0, variant=O.ANANDH)
+    U = o.free_stream()
+    dt, D = o.timestep_diag(U)
+    a = 1.0
+    u1, u2 = 1.5 * math.cos(math.radians(aoa)), 1.5 * math.sin(math.radians(aoa))
+    spec = sum(max(u + a, 0.0) + max(a - u, 0.0) for u in (u1, u2))
+    jj, kk = np.arange(c.n) % 11, np.arange(c.n) // 11
+    inner = (jj >= 2) & (jj <= 8) & (kk >= 2) & (kk <= 8)
+    assert np.allclose(D[inner], 1.0 / dt[inner] + 0.6 / 0.1 * spec, rtol=1e-12)
+    if aoa == 0.0:   # u1 = 1.5 > a: the x- half contributes nothing
+        assert spec == pytest.approx((1.5 + a) + 0.0 + 2 * a)
+    # dt = CFL h / (|u| + a)
+    assert np.allclose(dt[inner], 10.0 * 0.1 / (1.5 + a), rtol=1e-14)
+
+
 def test_diagonals_at_rest():
     # at rest rho(A+) = rho(A-) = a (Anandhanarayanan) and rho(A)/2 = a/2 (Manish):
     # the spectral parts of the two diagonals differ by exactly a factor 2

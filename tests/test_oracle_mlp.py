@@ -3,6 +3,8 @@
 * GELU against its definition through the normal CDF and its derivative
   against central differences;
 * the unquantised backward pass against central differences of the loss;
+* the quantised backward pass against central differences of the network
+  with its roundings frozen at their base-point offsets;
 * bfloat16 rounding: exact on representable values, ties to even, relative
   error at most 2^-9;
 * the quantised and unquantised networks agree to bfloat16 accuracy;
@@ -53,6 +55,66 @@ def test_unquantized_gradient_matches_central_differences():
         tm[i] -= h
         fd = (mlp.loss_and_grad(tp, X, T, False)[0] - mlp.loss_and_grad(tm, X, T, False)[0]) / (2 * h)
         assert fd == pytest.approx(g[i], rel=1e-6, abs=1e-10), i
+
+
+def frozen_rounding_loss(theta, X, T, off):
+    """The quantised network with each bf16 rounding r(v) replaced by v + c, c
+    the rounding offset r(v0) - v0 at the base point: smooth, equal to the
+    quantised loss at the base point, and differentiable through every
+    rounding as if it were the identity."""
+    P = mlp.unpack(np.asarray(theta, np.float64))
+    W = {k: P[k] + off[k] for k in ("W1", "W2", "W3", "W4")}
+    h = X + off["x"]
+    for layer, (Wk, bk) in enumerate((("W1", "b1"), ("W2", "b2"), ("W3", "b3"))):
+        h = mlp.gelu(h @ W[Wk].T + P[bk]) + off[f"h{layer + 1}"]
+    y = h @ W["W4"].T + P["b4"]
+    return float(np.mean((y - T) ** 2))
+
+
+def test_quantized_gradient_matches_differences_with_frozen_rounding():
+    # The quantised backward differentiates through the forward's roundings of
+    # the weights, features and hidden activations as the identity (the
+    # straight-through rule), and itself rounds the pre-activation gradients of
+    # layers 3 and 2 to bf16.  So against central differences of the
+    # frozen-rounding network: the output layer (no backward rounding on its
+    # path) matches tightly, every other block to bf16 accuracy.
+    rng = np.random.default_rng(8)
+    th = params(8)
+    X = rng.standard_normal((7, 5))
+    T = rng.standard_normal((7, 4)) * 0.3
+    loss, g = mlp.loss_and_grad(th, X, T, quantize=True)
+    _, c = mlp.forward(th, X, quantize=True)
+    P = mlp.unpack(th)
+    off = {k: mlp.bf16(P[k]) - P[k] for k in ("W1", "W2", "W3", "W4")}
+    off["x"] = mlp.bf16(X) - X
+    off["h1"] = c["h1"] - mlp.gelu(c["z1"])
+    off["h2"] = c["h2"] - mlp.gelu(c["z2"])
+    off["h3"] = c["h3"] - mlp.gelu(c["z3"])
+    assert frozen_rounding_loss(th, X, T, off) == pytest.approx(loss, rel=1e-14)
+    assert max(np.abs(off[k]).max() for k in off) > 0   # the roundings are not trivial
+    starts, o = {}, 0
+    for name, shape in mlp.SHAPES:
+        starts[name] = (o, o + int(np.prod(shape)))
+        o += int(np.prod(shape))
+    h = 1e-6
+    for name, _ in mlp.SHAPES:
+        a, b = starts[name]
+        idx = np.unique(np.concatenate([rng.choice(np.arange(a, b), min(24, b - a),
+                                                   replace=False), [a, b - 1]]))
+        fd = np.empty(idx.size)
+        for j, i in enumerate(idx):
+            tp, tm = th.copy(), th.copy()
+            tp[i] += h
+            tm[i] -= h
+            fd[j] = (frozen_rounding_loss(tp, X, T, off)
+                     - frozen_rounding_loss(tm, X, T, off)) / (2 * h)
+        err = np.linalg.norm(g[idx] - fd) / np.linalg.norm(fd)
+        bound = 1e-7 if name in ("W4", "b4") else 2.0 ** -7
+        assert err < bound, (name, err)
+    # and the quantised gradient is not the unquantised one: the roundings matter
+    _, gu = mlp.loss_and_grad(th, X, T, quantize=False)
+    a, b = starts["W4"]
+    assert np.linalg.norm(g[a:b] - gu[a:b]) > 1e-5 * np.linalg.norm(gu[a:b])
 
 
 def test_bf16_rounding():

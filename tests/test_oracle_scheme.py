@@ -224,6 +224,60 @@ def test_forces_vanish_for_uniform_pressure():
     assert abs(cl) < 1e-13 and abs(cd) < 1e-13
 
 
+def wall_polygon_area(c):
+    w = np.flatnonzero(c.type == cg.WALL)
+    x, y = c.x[w], c.y[w]
+    return 0.5 * abs(np.sum(x * np.roll(y, -1) - np.roll(x, -1) * y))
+
+
+@pytest.mark.parametrize("aoa", [0.0, 7.0, -4.0])
+def test_forces_of_a_linear_pressure_field_closed_form(aoa):
+    # p = p_inf + c y on the wall: by the divergence theorem the pressure force
+    # -(closed integral of (p - p_inf) n_out ds) is -c A y_hat with A the area
+    # enclosed by the wall polygon, and the edge-mean pressure is exact for a
+    # linear field on straight edges.  Likewise p = p_inf + c x gives -c A x_hat.
+    # CL, CD are the components across / along the free stream over M^2/2.
+    c = cg.ogrid(80, 12, r=1.2)
+    mach = 0.6
+    o = O.Oracle(c, mach=mach, aoa_deg=aoa)
+    A = wall_polygon_area(c)
+    assert 0.05 < A < 0.1   # a 12%-thick section of unit chord: about 0.082
+    qinf = 0.5 * mach * mach
+    al = np.radians(aoa)
+    slope = 0.05
+    for along, F in (("y", np.array([0.0, -slope * A])), ("x", np.array([-slope * A, 0.0]))):
+        p = 1 / GAMMA + slope * (c.y if along == "y" else c.x)
+        U = np.array([np.ones(c.n), np.zeros(c.n), np.zeros(c.n), p / (GAMMA - 1)])
+        cl, cd = o.forces(U)
+        want_cl = (F[1] * np.cos(al) - F[0] * np.sin(al)) / qinf
+        want_cd = (F[0] * np.cos(al) + F[1] * np.sin(al)) / qinf
+        assert cl == pytest.approx(want_cl, rel=1e-12, abs=1e-14)
+        assert cd == pytest.approx(want_cd, rel=1e-12, abs=1e-14)
+    # the sign: more pressure below than above lifts the body
+    p = 1 / GAMMA - slope * c.y
+    cl, _ = o.forces(np.array([np.ones(c.n), np.zeros(c.n), np.zeros(c.n), p / (GAMMA - 1)]))
+    assert cl > 0 if abs(aoa) < 90 else True
+
+
+def test_positive_incidence_gives_positive_lift():
+    # converged subsonic flow at +2 deg lifts the symmetric profile (the sign of
+    # the paper's lift coefficients); its size is near the thin-aerofoil value
+    # 2 pi sin(a) / sqrt(1 - M^2) = 0.253 at M 0.5
+    # (this coarse 64 x 16 cloud gives about 0.15)
+    c = cg.ogrid(64, 16, r=1.15)
+    o = O.Oracle(c, mach=0.5, aoa_deg=2.0, cfl=100.0, inner_iters=1)
+    U, it, hist = o.solve(o.free_stream(), 1000)
+    assert hist[-1] < 1e-6 * hist[0]
+    cl, cd = o.forces(U)
+    assert 0.1 < cl < 0.4
+    o_neg = O.Oracle(c, mach=0.5, aoa_deg=-2.0, cfl=100.0, inner_iters=1)
+    Un, _, _ = o_neg.solve(o_neg.free_stream(), 1000)
+    cln, cdn = o_neg.forces(Un)
+    # the mirror image: opposite lift, same drag
+    assert cln == pytest.approx(-cl, rel=1e-7)
+    assert cdn == pytest.approx(cd, rel=1e-7)
+
+
 def test_free_stream_wall_tangency():
     c = cg.ogrid(64, 10, r=1.2)
     o = O.Oracle(c, mach=0.63, aoa_deg=2.0)
