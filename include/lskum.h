@@ -234,6 +234,23 @@ int lskum_batch_set_params(lskum_batch* b, const lskum_params* prm);
  * non-positive value. */
 int lskum_batch_set_cfl(lskum_batch* b, const double* cfl);
 
+/* Copies the current CFL number of each condition (n_cond doubles, host). */
+int lskum_batch_get_cfl(const lskum_batch* b, double* cfl);
+
+/* Residual-driven CFL control (an addition: the paper runs one CFL number;
+ * strong-shock conditions of a batch can stall in a limit cycle at a CFL
+ * number that suits the rest).  During lskum_batch_solve the host reads every
+ * condition's residual norm after each replay of check_every iterations; at
+ * the end of each window of `window` iterations, a condition still iterating
+ * whose lowest residual over the window is not below its lowest residual over
+ * the previous window has its CFL number multiplied by `factor`, but not
+ * below cfl_min; the new numbers act from the next iteration on.  The
+ * window's memory persists across lskum_batch_solve calls and is cleared by
+ * this call.  window = 0 (the default) switches the control off.
+ * Errors: ARG unless window >= 0 and, for window > 0, 0 < factor < 1 and
+ * cfl_min > 0. */
+int lskum_batch_set_cfl_control(lskum_batch* b, int32_t window, double factor, double cfl_min);
+
 /* Solves all conditions (graph-replayed iterations, device-side retirement)
  * until all retire or max_iters.  reps (n_cond entries, may be NULL): per
  * condition iterations, status (OK, NOT_CONVERGED or NONPHYSICAL), residual

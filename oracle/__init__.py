@@ -42,7 +42,7 @@ class _Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("mach", C.c_double),
                 ("aoa_deg", C.c_double), ("inner_iters", C.c_int32), ("jvp_mode", C.c_int32),
                 ("limiter", C.c_int32), ("variant", C.c_int32), ("limiter_k", C.c_double),
-                ("order", C.c_int32), ("pad2", C.c_int32)]
+                ("order", C.c_int32), ("farfield", C.c_int32)]
 
 
 _lib = None
@@ -61,8 +61,8 @@ def lib():
             "ora_flux_jvp": (None, [P, P, D, D, I32, P, P]),
             "ora_q_from_U": (None, [I64, P, D, P]),
             "ora_U_from_q": (None, [I64, P, D, P]),
-            "ora_split_weights": (I32, [P, I64, I32, I32, P, P, P]),
-            "ora_split_dirs": (I32, [P, I64, P]),
+            "ora_split_weights": (I32, [P, I64, I32, I32, P, P, P, I32]),
+            "ora_split_dirs": (I32, [P, I64, P, I32]),
             "ora_free_stream": (None, [P, P, P]),
             "ora_q_grad_pass": (I32, [P, P, P, P, P, P]),
             "ora_q_derivatives": (I32, [P, P, P, P, P]),
@@ -124,10 +124,13 @@ ANANDH, MANISH = 0, 1
 COLOUR_ORDER, WALL_FIRST = 0, 1
 
 
+DIRICHLET, KINETIC = 0, 1
+
+
 def params(mach=0.63, aoa_deg=2.0, cfl=100.0, inner_iters=1, jvp_mode=0, gamma=GAMMA, limiter=0,
-           limiter_k=5.0, variant=ANANDH, order=COLOUR_ORDER):
+           limiter_k=5.0, variant=ANANDH, order=COLOUR_ORDER, farfield=DIRICHLET):
     return _Params(gamma, cfl, mach, aoa_deg, inner_iters, jvp_mode, limiter, variant, limiter_k,
-                   order, 0)
+                   order, farfield)
 
 
 def unsplit_jvp(U, dU, d, jvp_mode=0, gamma=GAMMA):
@@ -168,7 +171,7 @@ class Oracle:
 
     def __init__(self, cloud, mach=0.63, aoa_deg=2.0, cfl=100.0, inner_iters=1, jvp_mode=0,
                  gamma=GAMMA, colours=None, limiter=0, limiter_k=5.0, variant=ANANDH,
-                 order=COLOUR_ORDER):
+                 order=COLOUR_ORDER, farfield=DIRICHLET):
         self.cloud = cloud
         self._keep = [_f64(cloud.x), _f64(cloud.y), _f64(cloud.tx), _f64(cloud.ty),
                       np.ascontiguousarray(cloud.type, dtype=np.int8),
@@ -184,7 +187,7 @@ class Oracle:
         self.c = _Cloud(cloud.n, _p(k[0]), _p(k[1]), _p(k[2]), _p(k[3]), _p(k[4]), _p(k[5]),
                         _p(k[6]), _p(col), nc)
         self.prm = params(mach, aoa_deg, cfl, inner_iters, jvp_mode, gamma, limiter, limiter_k,
-                          variant, order)
+                          variant, order, farfield)
         self.n = cloud.n
 
     # -- state -------------------------------------------------------------
@@ -303,7 +306,7 @@ class Oracle:
         w = np.empty(cap)
         ls1 = C.c_double(0.0)
         m = lib().ora_split_weights(C.byref(self.c), int(p), int(k), cap, _p(nb), _p(w),
-                                    C.byref(ls1))
+                                    C.byref(ls1), int(self.prm.farfield))
         if m < 0:
             raise IndexError("no such split")
         if m > cap:
@@ -312,5 +315,5 @@ class Oracle:
 
     def split_dirs(self, p):
         out = np.empty(12)
-        ns = lib().ora_split_dirs(C.byref(self.c), int(p), _p(out))
+        ns = lib().ora_split_dirs(C.byref(self.c), int(p), _p(out), int(self.prm.farfield))
         return [((out[3 * k], out[3 * k + 1]), int(out[3 * k + 2])) for k in range(ns)]

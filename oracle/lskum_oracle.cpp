@@ -181,26 +181,30 @@ struct Params {
     double limiter_k;
     int32_t variant;                // 0 Anandhanarayanan et al., 1 Manish et al.
     int32_t order;                  // 0 colour order (Algorithm 6), 1 wall first (Algorithm 5)
+    int32_t farfield;               // 0 outer points held at the free stream, 1 kinetic far field
 };
 
 enum { OK = 0, ERR_ARG = -1, ERR_CONN = -2, ERR_DEGEN = -3, ERR_COLOUR = -4, ERR_NONPHYS = -5 };
 
 // One split stencil of a point: direction d, transverse e, sign s.
 // Reading: the wall uses its own (t, n) frame: splits t+, t-, n- (the fluid
-// side, dn > 0); interior points use x+, x-, y+, y-; outer points are Dirichlet.
+// side, dn > 0); interior points use x+, x-, y+, y-; outer points are
+// Dirichlet, or, with the kinetic far field, use their own (t, n) frame (n out
+// of the domain): splits t+, t-, n+ (the inner side, dn < 0), the n- half
+// coming from the free stream (see far_field_term).
 struct Split {
     double dx, dy, ex, ey;
     int s;
 };
 
-int splits_of(const Cloud& c, int64_t p, Split out[4]) {
-    if (c.type[p] == 2) return 0;
-    if (c.type[p] == 0) {
+int splits_of(const Cloud& c, int64_t p, Split out[4], bool farfield) {
+    if (c.type[p] == 2 && !farfield) return 0;
+    if (c.type[p] == 0 || c.type[p] == 2) {
         double tx = c.tx[p], ty = c.ty[p];
         double nx = -ty, ny = tx;
         out[0] = {tx, ty, nx, ny, +1};
         out[1] = {tx, ty, nx, ny, -1};
-        out[2] = {nx, ny, tx, ty, -1};
+        out[2] = {nx, ny, tx, ty, c.type[p] == 0 ? -1 : +1};
         return 3;
     }
     out[0] = {1.0, 0.0, 0.0, 1.0, +1};
@@ -402,6 +406,46 @@ void limit_gradients(const Cloud& c, const Params& P, const double* q, double* q
     }
 }
 
+// Distance from point p to its nearest neighbour.
+double nearest_distance(const Cloud& c, int64_t p) {
+    double rmin = INFINITY;
+    for (int32_t e = c.off[p]; e < c.off[p + 1]; ++e) {
+        int32_t i = c.idx[e];
+        double r = std::sqrt((c.x[i] - c.x[p]) * (c.x[i] - c.x[p]) +
+                             (c.y[i] - c.y[p]) * (c.y[i] - c.y[p]));
+        if (r < rmin) rmin = r;
+    }
+    return rmin;
+}
+
+// q-variables of the free stream (the state outer points start from).
+void free_stream_q(const Params& P, double q[4]) {
+    double a = P.aoa_deg * kPi / 180.0;
+    Prim<double> w{1.0, P.mach * std::cos(a), P.mach * std::sin(a), 1.0 / P.gamma};
+    double U[4];
+    U_from_prim(w, P.gamma, U);
+    q_from_prim(prim_from_U(U, P.gamma), P.gamma, q);
+}
+
+// Kinetic far field (reading; the paper holds no outer boundary treatment).
+// At an outer point with outward normal n, the molecules entering the domain
+// (v_n < 0) are those of the free stream: the n- split derivative of the
+// point is the one-sided difference to a ghost point one nearest-neighbour
+// distance h outside that carries the free stream,
+//   (G_n-(q_inf) - G_n-(q_0)) / h,
+// with the point's own (unreconstructed) q-variables.  The splits t+, t-
+// and n+ of the point's own stencil supply the rest of its residual.
+void far_field_term(const Cloud& c, const Params& P, int64_t p, const double* q, double F[4]) {
+    double nx = -c.ty[p], ny = c.tx[p];
+    double h = nearest_distance(c, p);
+    double qinf[4], q0[4], Gi[4], G0[4];
+    free_stream_q(P, qinf);
+    for (int v = 0; v < 4; ++v) q0[v] = q[v * c.n + p];
+    split_flux(prim_from_q(qinf, P.gamma), nx, ny, -1, P.gamma, Gi);
+    split_flux(prim_from_q(q0, P.gamma), nx, ny, -1, P.gamma, G0);
+    for (int v = 0; v < 4; ++v) F[v] = (Gi[v] - G0[v]) / h;
+}
+
 // flux_residual(): R_0 = sum over the point's split stencils k of
 //   sum_{i in N_k} w_i [ G_k(q~_i) - G_k(q~_0^(i)) ]            (eq. 11, 15)
 // with q~_i = q_i - 1/2 (dx_i qx_i + dy_i qy_i) and
@@ -416,7 +460,7 @@ int flux_residual(const Cloud& c, const Params& P, const double* q, const double
     for (int64_t p = 0; p < c.n; ++p) {
         double Rp[4] = {0, 0, 0, 0};
         Split sp[4];
-        int ns = splits_of(c, p, sp);
+        int ns = splits_of(c, p, sp, P.farfield != 0);
         for (int k = 0; k < ns; ++k) {
             Stencil stn = split_stencil(c, p, sp[k]);
             if (stn.degenerate) {
@@ -442,6 +486,11 @@ int flux_residual(const Cloud& c, const Params& P, const double* q, const double
                 split_flux(w0, sp[k].dx, sp[k].dy, sp[k].s, P.gamma, G0);
                 for (int v = 0; v < 4; ++v) Rp[v] += stn.w[j] * (Gi[v] - G0[v]);
             }
+        }
+        if (c.type[p] == 2 && P.farfield) {
+            double Fg[4];
+            far_field_term(c, P, p, q, Fg);
+            for (int v = 0; v < 4; ++v) Rp[v] += Fg[v];
         }
         if (c.type[p] == 0) project_out_normal(c, p, Rp);
         for (int v = 0; v < 4; ++v) R[v * c.n + p] = Rp[v];
@@ -518,17 +567,11 @@ void timestep_diag(const Cloud& c, const Params& P, const double* U, double* dt,
         Prim<double> w = prim_from_U(Up, P.gamma);
         double a = std::sqrt(P.gamma * w.p / w.rho);
         double umag = std::sqrt(w.u1 * w.u1 + w.u2 * w.u2);
-        double rmin = INFINITY;
-        for (int32_t e = c.off[p]; e < c.off[p + 1]; ++e) {
-            int32_t i = c.idx[e];
-            double r = std::sqrt((c.x[i] - c.x[p]) * (c.x[i] - c.x[p]) +
-                                 (c.y[i] - c.y[p]) * (c.y[i] - c.y[p]));
-            if (r < rmin) rmin = r;
-        }
+        double rmin = nearest_distance(c, p);
         double dtp = P.cfl * rmin / (umag + a);
         double Dp = 1.0 / dtp;
         Split sp[4];
-        int ns = splits_of(c, p, sp);
+        int ns = splits_of(c, p, sp, P.farfield != 0);
         for (int k = 0; k < ns; ++k) {
             Stencil stn = split_stencil(c, p, sp[k]);
             double ud = w.u1 * sp[k].dx + w.u2 * sp[k].dy;
@@ -539,6 +582,14 @@ void timestep_diag(const Cloud& c, const Params& P, const double* U, double* dt,
             double rad = (double)sp[k].s * ud + a;
             if (rad < 0.0) rad = 0.0;
             Dp -= (double)sp[k].s * stn.ls1 * rad;
+        }
+        if (c.type[p] == 2 && P.farfield && P.variant == 0) {
+            // the far-field ghost: an n- split with the single weight 1/h, LS(1) = 1/h,
+            // and the ghost's increment zero (the free stream is fixed)
+            double un = -w.u1 * c.ty[p] + w.u2 * c.tx[p];
+            double rad = a - un;
+            if (rad < 0.0) rad = 0.0;
+            Dp += rad / rmin;
         }
         dt[p] = dtp;
         D[p] = Dp;
@@ -558,7 +609,7 @@ void manish_source(const Cloud& c, const Params& P, const double* U, const doubl
     for (int64_t p = 0; p < c.n; ++p) {
         double Sp[4] = {0, 0, 0, 0};
         Split sp[4];
-        int ns = splits_of(c, p, sp);
+        int ns = splits_of(c, p, sp, P.farfield != 0);
         double Up[4] = {U[p], U[c.n + p], U[2 * c.n + p], U[3 * c.n + p]};
         double dUp[4] = {0, 0, 0, 0};
         if (dU_prev)
@@ -590,7 +641,7 @@ void lusgs(const Cloud& c, const Params& P, const double* U, const double* R, co
     for (int64_t i = 0; i < 4 * c.n; ++i) dU[i] = 0.0;
 
     auto sweep_point = [&](int64_t p, bool forward) {
-        if (c.type[p] == 2) {
+        if (c.type[p] == 2 && !P.farfield) {
             for (int v = 0; v < 4; ++v) dU[v * c.n + p] = 0.0;
             return;
         }
@@ -598,7 +649,7 @@ void lusgs(const Cloud& c, const Params& P, const double* U, const double* R, co
         if (forward)
             for (int v = 0; v < 4; ++v) acc[v] = R[v * c.n + p];
         Split sp[4];
-        int ns = splits_of(c, p, sp);
+        int ns = splits_of(c, p, sp, P.farfield != 0);
         for (int k = 0; k < ns; ++k) {
             Stencil stn = split_stencil(c, p, sp[k]);
             for (size_t j = 0; j < stn.nb.size(); ++j) {
@@ -694,7 +745,7 @@ typedef struct {
     int32_t inner_iters, jvp_mode;
     int32_t limiter, variant;
     double limiter_k;
-    int32_t order, pad2;
+    int32_t order, farfield;
 } ora_params;
 
 static Cloud to_cloud(const ora_cloud* c) {
@@ -702,7 +753,8 @@ static Cloud to_cloud(const ora_cloud* c) {
 }
 static Params to_params(const ora_params* p) {
     return Params{p->gamma,    p->cfl,     p->mach,      p->aoa_deg, p->inner_iters,
-                  p->jvp_mode, p->limiter, p->limiter_k, p->variant, p->order};
+                  p->jvp_mode, p->limiter, p->limiter_k, p->variant, p->order,
+                  p->farfield};
 }
 
 // Point colouring, Algorithm 4: colour(first point) = first colour; then for
@@ -776,13 +828,13 @@ void ora_U_from_q(int64_t n, const double* q, double gamma, double* U) {
 }
 
 // Split stencil of point p (split index k in the point's own order: wall
-// t+, t-, n-; interior x+, x-, y+, y-).  Writes up to cap members and weights;
+// t+, t-, n-; interior x+, x-, y+, y-; with farfield != 0, outer t+, t-, n+).  Writes up to cap members and weights;
 // returns the member count (0 for degenerate), or -1 if k is not a split.
 int32_t ora_split_weights(const ora_cloud* oc, int64_t p, int32_t k, int32_t cap, int32_t* nb,
-                          double* w, double* ls1) {
+                          double* w, double* ls1, int32_t farfield) {
     Cloud c = to_cloud(oc);
     Split sp[4];
-    int ns = splits_of(c, p, sp);
+    int ns = splits_of(c, p, sp, farfield != 0);
     if (k < 0 || k >= ns) return -1;
     Stencil st = split_stencil(c, p, sp[k]);
     *ls1 = st.ls1;
@@ -795,10 +847,10 @@ int32_t ora_split_weights(const ora_cloud* oc, int64_t p, int32_t k, int32_t cap
 }
 
 // Split directions of point p: writes (dx, dy, s) triples, returns the count.
-int32_t ora_split_dirs(const ora_cloud* oc, int64_t p, double* out) {
+int32_t ora_split_dirs(const ora_cloud* oc, int64_t p, double* out, int32_t farfield) {
     Cloud c = to_cloud(oc);
     Split sp[4];
-    int ns = splits_of(c, p, sp);
+    int ns = splits_of(c, p, sp, farfield != 0);
     for (int k = 0; k < ns; ++k) {
         out[3 * k] = sp[k].dx;
         out[3 * k + 1] = sp[k].dy;

@@ -25,7 +25,8 @@ published):
   point itself, in (dk, dj) lexicographic order -- the 8 grid neighbours plus
   the second ring, symmetric by construction;
 * wall frame: unit tangent t_j = (W_{j-1} - W_{j+1}) / |.|, so that the normal
-  n = (-t_y, t_x) points into the fluid; interior and outer points get t = (1, 0);
+  n = (-t_y, t_x) points into the fluid; the outer ring's frame by the same
+  rule, its normal pointing out of the domain; interior points get t = (1, 0);
 * optional jitter: each interior point independently with probability
   ``jitter_p`` is displaced by xi1*0.2*h_j*e_j + xi2*0.2*h_k*e_k, xi ~ U(-1, 1),
   where e_j, h_j (e_k, h_k) are the unit direction and half-length of the
@@ -181,6 +182,13 @@ def ogrid(nw: int, nk: int, r: float | None = None, t: float = 0.12,
     ln = np.hypot(dxw, dyw)
     tx[0, :] = dxw / ln
     ty[0, :] = dyw / ln
+    # outer ring: the same rule, so that n = (-t_y, t_x) points out of the domain
+    xo, yo = X[-1], Y[-1]
+    dxo = np.roll(xo, 1) - np.roll(xo, -1)
+    dyo = np.roll(yo, 1) - np.roll(yo, -1)
+    lo = np.hypot(dxo, dyo)
+    tx[-1, :] = dxo / lo
+    ty[-1, :] = dyo / lo
 
     off, idx = _ring_csr(nw, nk)
     return Cloud(x=np.ascontiguousarray(X.reshape(n)), y=np.ascontiguousarray(Y.reshape(n)),

@@ -469,6 +469,7 @@ int init_state(lskum::State& s, const lskum::Cloud& c, const lskum_params* prm,
     HIPCHK(hipMemcpyAsync(s.tol_abs, zero.data(), nc * sizeof(double), hipMemcpyHostToDevice,
                           s.stream));
     HIPCHK(lskum::reset_cfl(s));
+    s.h_cfl.assign(nc, s.prm.cfl);
     HIPCHK(lskum::launch_clear_flags(s.flags, s.stream));
     HIPCHK(lskum::launch_reset_components(s));
     HIPCHK(lskum::launch_free_stream(s));
@@ -496,8 +497,41 @@ struct SolveOut {
     bool any_flag = false;
 };
 
-int run_solve(lskum::State& s, SolveOut& out) {
+// One window step of the CFL control after `done` more iterations, from the
+// components' last residuals `rl` and activity `act`; uploads changed CFL
+// numbers (they take effect from the next iteration on).
+int cfl_control_step(lskum::State& s, lskum::CflControl& ctl, int done,
+                     const std::vector<double>& rl, const std::vector<int32_t>& act) {
+    const int nc = (int)rl.size();
+    for (int k = 0; k < nc; ++k)
+        if (act[k] && rl[k] < ctl.best_cur[k]) ctl.best_cur[k] = rl[k];
+    ctl.since += done;
+    if (ctl.since < ctl.window) return LSKUM_OK;
+    bool changed = false;
+    for (int k = 0; k < nc; ++k) {
+        if (!act[k] || ctl.best_cur[k] < ctl.best_prev[k]) continue;  // progress
+        const double c = std::max(ctl.cfl_min, s.h_cfl[k] * ctl.factor);
+        if (c < s.h_cfl[k]) {
+            s.h_cfl[k] = c;
+            ++ctl.cuts[k];
+            changed = true;
+        }
+    }
+    ctl.best_prev = ctl.best_cur;
+    ctl.best_cur.assign(nc, HUGE_VAL);
+    ctl.since = 0;
+    if (changed) {
+        HIPCHK(hipMemcpyAsync(s.cfl, s.h_cfl.data(), nc * sizeof(double), hipMemcpyHostToDevice,
+                              s.stream));
+        HIPCHK(hipStreamSynchronize(s.stream));
+    }
+    return LSKUM_OK;
+}
+
+int run_solve(lskum::State& s, SolveOut& out, lskum::CflControl* ctl = nullptr) {
     const int nc = s.cloud->ncomp;
+    if (ctl && ctl->window <= 0) ctl = nullptr;
+    std::vector<double> rl(ctl ? nc : 0);
     const int K = std::min(s.prm.check_every, s.res_cap);
     if (!s.graph || s.graph_iters != K) {
         if (s.graph) (void)hipGraphExecDestroy(s.graph);
@@ -527,19 +561,24 @@ int run_solve(lskum::State& s, SolveOut& out) {
     int it = 0;
     while (it < s.prm.max_iters) {
         int32_t f = 0;
+        int done = K;
         if (it + K <= s.prm.max_iters) {
             HIPCHK(hipGraphLaunch(s.graph, s.stream));
-            it += K;
         } else {
-            const int done = s.prm.max_iters - it;
+            done = s.prm.max_iters - it;
             for (int j = 0; j < done; ++j)
                 if (int e = enqueue_step(s, j)) return e;
-            it += done;
         }
+        it += done;
         HIPCHK(hipMemcpyAsync(act.data(), s.active, nc * sizeof(int32_t), hipMemcpyDeviceToHost,
                               s.stream));
         HIPCHK(hipMemcpyAsync(&f, s.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s.stream));
+        if (ctl)
+            HIPCHK(hipMemcpyAsync(rl.data(), s.res_last, nc * sizeof(double),
+                                  hipMemcpyDeviceToHost, s.stream));
         HIPCHK(hipStreamSynchronize(s.stream));
+        if (ctl)
+            if (int r = cfl_control_step(s, *ctl, done, rl, act)) return r;
         const double now =
             std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         int live = 0;
@@ -777,7 +816,10 @@ int lskum_state_set_params(lskum_state* so, const lskum_params* prm) {
     const bool new_cfl = np.cfl != s.prm.cfl;
     s.prm = np;
     apply_lanes(s);
-    if (new_cfl) HIPCHK(lskum::reset_cfl(s));  // per-condition values give way to the new one
+    if (new_cfl) {  // per-condition values give way to the new one
+        HIPCHK(lskum::reset_cfl(s));
+        s.h_cfl.assign(s.cloud->ncomp, s.prm.cfl);
+    }
     return LSKUM_OK;
 }
 
@@ -1048,6 +1090,30 @@ int lskum_batch_set_cfl(lskum_batch* b, const double* cfl) {
             return fail(LSKUM_ERR_ARG, "cfl must be finite and > 0");
     HIPCHK(hipMemcpyAsync(s.cfl, cfl, nc * sizeof(double), hipMemcpyHostToDevice, s.stream));
     HIPCHK(hipStreamSynchronize(s.stream));
+    s.h_cfl.assign(cfl, cfl + nc);
+    return LSKUM_OK;
+}
+
+int lskum_batch_get_cfl(const lskum_batch* b, double* cfl) {
+    if (!b || !cfl) return fail(LSKUM_ERR_ARG, "NULL argument");
+    std::copy(b->s.h_cfl.begin(), b->s.h_cfl.end(), cfl);
+    return LSKUM_OK;
+}
+
+int lskum_batch_set_cfl_control(lskum_batch* b, int32_t window, double factor, double cfl_min) {
+    if (!b) return fail(LSKUM_ERR_ARG, "batch is NULL");
+    if (window < 0 || (window > 0 && (!(factor > 0.0) || !(factor < 1.0) || !(cfl_min > 0.0) ||
+                                      !std::isfinite(cfl_min))))
+        return fail(LSKUM_ERR_ARG, "need window >= 0, and 0 < factor < 1, cfl_min > 0");
+    const int nc = b->c.ncomp;
+    lskum::CflControl& c = b->ctl;
+    c.window = window;
+    c.factor = factor;
+    c.cfl_min = cfl_min;
+    c.since = 0;
+    c.best_prev.assign(nc, HUGE_VAL);
+    c.best_cur.assign(nc, HUGE_VAL);
+    c.cuts.assign(nc, 0);
     return LSKUM_OK;
 }
 
@@ -1055,7 +1121,7 @@ int lskum_batch_solve(lskum_batch* b, lskum_report* reps, double* seconds_total)
     if (!b) return fail(LSKUM_ERR_ARG, "batch is NULL");
     lskum::State& s = b->s;
     SolveOut o;
-    if (int r = run_solve(s, o)) return r;
+    if (int r = run_solve(s, o, &b->ctl)) return r;
     std::vector<double> cl, cd;
     const bool have_forces = forces_all(s, cl, cd) == LSKUM_OK;
     const int nc = b->c.ncomp;

@@ -141,6 +141,7 @@ struct State {
     double* res_last = nullptr;
     double* tol_abs = nullptr;             // 0 disables device-side retirement
     double* cfl = nullptr;                 // per component CFL number (params.cfl unless set)
+    std::vector<double> h_cfl;             // host copy of cfl
     double* vinf = nullptr;                // 2 per component: free-stream velocity
     double* rr = nullptr;                  // per point R_rho^2 (0 at outer points)
     hipStream_t stream = nullptr;
@@ -180,6 +181,17 @@ struct State {
     int graph_iters = 0;
     hipEvent_t ev[8] = {};
     bool have_events = false;
+};
+
+// Residual-driven CFL control of a batch (lskum_batch_set_cfl_control): a
+// condition whose residual reaches no new minimum during a window of
+// iterations has its CFL number reduced.
+struct CflControl {
+    int window = 0;                           // iterations per window; 0 = off
+    double factor = 1.0, cfl_min = 0.0;
+    int since = 0;                            // iterations into the current window
+    std::vector<double> best_prev, best_cur;  // lowest residual of the previous / current window
+    std::vector<int32_t> cuts;                // reductions applied, per condition
 };
 
 // Kernel launchers (lskum_device.hip).  All enqueue on s->stream.
@@ -236,4 +248,5 @@ struct lskum_batch {
     lskum::Cloud c;  // union of the conditions' clouds
     lskum::State s;
     std::vector<int32_t> cond_cloud;
+    lskum::CflControl ctl;
 };

@@ -78,6 +78,8 @@ _SIGS = {
     "lskum_batch_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lskum_batch_set_params": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lskum_batch_set_cfl": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lskum_batch_get_cfl": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lskum_batch_set_cfl_control": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double]),
     "lskum_batch_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lskum_batch_step_timed": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lskum_batch_get_U": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int]),
@@ -340,6 +342,16 @@ class Batch:
         cfl = np.ascontiguousarray(cfl, dtype=np.float64)
         assert cfl.shape == (self.n_cond,)
         _check(lib().lskum_batch_set_cfl(self.h, cfl.ctypes.data))
+
+    def get_cfl(self) -> np.ndarray:
+        out = np.empty(self.n_cond)
+        _check(lib().lskum_batch_get_cfl(self.h, _ptr(out)))
+        return out
+
+    def set_cfl_control(self, window: int, factor: float = 0.3, cfl_min: float = 1.0):
+        """Residual-driven per-condition CFL control (window 0 switches it off)."""
+        _check(lib().lskum_batch_set_cfl_control(self.h, int(window), float(factor),
+                                                 float(cfl_min)))
 
     def solve(self):
         """Returns (list of Report dicts, total seconds)."""

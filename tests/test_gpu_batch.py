@@ -146,3 +146,41 @@ def test_batch_benchmark_workload_sampled_conditions(lk):
             print(f"batch condition {k} (cloud {clouds[k].n} points) precision={prec}: {e:.3e}")
             assert e < tol
         b.close()
+
+
+def test_cfl_control_cuts_only_a_stalled_condition(lk):
+    # Two conditions on a 48 x 12 O-grid with the limiter: M 1.2 (bow shock)
+    # reaches the round-off floor of its residual within about 900 iterations
+    # and from then on makes no new minimum -- a stall to the control -- while
+    # M 0.6 at 2 deg makes a new minimum in every 200-iteration window through
+    # 1,600 iterations.  The control must halve only the stalled condition's
+    # CFL number, never below its floor, and the batch must equal single
+    # states run with the same per-window CFL schedule, bitwise.
+    cloud = cg.ogrid(48, 12)
+    gc = lk.Cloud(cloud)
+    conds = [(1.2, 0.0), (0.6, 2.0)]
+    kw = dict(inner_iters=1, limiter=1, limiter_k=5.0, check_every=50, tol_rel=0.0)
+    prm = lk.default_params(cfl=100.0, max_iters=200, **kw)
+    b = lk.Batch([gc], [0, 0], [c[0] for c in conds], [c[1] for c in conds], prm)
+    b.set_cfl_control(200, 0.5, 20.0)
+    sched = []
+    for _ in range(8):
+        sched.append(b.get_cfl().copy())
+        reps, _ = b.solve()
+    final = b.get_cfl()
+    print("CFL schedule per 200-iteration window:", [s.tolist() for s in sched], final.tolist())
+    assert all(s[1] == 100.0 for s in sched) and final[1] == 100.0
+    assert sched[0][0] == 100.0 and sched[4][0] == 100.0   # converging: no cut
+    assert 20.0 <= final[0] < 100.0
+    assert all(s[0] in (100.0, 50.0, 25.0, 20.0) for s in sched)
+    assert reps[0]["res_final"] < 1e-13 * reps[0]["res_fs"]
+    for k, (m, a) in enumerate(conds):
+        st = lk.State(gc, m, a, lk.default_params(cfl=100.0, max_iters=200, **kw))
+        for s in sched:
+            st.set_params(lk.default_params(cfl=float(s[k]), max_iters=200, **kw))
+            st.solve()
+        assert np.array_equal(b.get_U(k), st.get_U()), k
+        st.close()
+    with pytest.raises(lk.LskumError):
+        b.set_cfl_control(100, 1.5, 10.0)
+    b.close()
