@@ -20,9 +20,12 @@
  *   - Point fields are passed as structure-of-arrays [4][n] of double:
  *     field v of point p at index v*n + p.  U = (rho, rho u1, rho u2, rho E)
  *     with E the total specific energy.
- *   - Point types: 0 wall, 1 interior, 2 outer (held at free stream).
+ *   - Point types: 0 wall, 1 interior, 2 outer (held at free stream, or
+ *     with the kinetic far field of lskum_params.farfield).
  *   - Wall frame: unit tangent (tx, ty); the normal n = (-ty, tx) must point
- *     into the fluid.  Interior/outer points ignore the frame.
+ *     into the fluid.  Outer points use their frame only with the kinetic far
+ *     field, and then n = (-ty, tx) must point out of the domain.  Interior
+ *     points ignore the frame.
  *   - Wall points, in storage order, must trace one closed body contour
  *     (used only by lskum_forces).
  *   - Connectivity is CSR (nbr_off[n+1], nbr_idx[nnz]) and must be symmetric
@@ -63,6 +66,7 @@ enum { LSKUM_FP64 = 0, LSKUM_MIXED = 1 };
 enum { LSKUM_ANANDH = 0, LSKUM_MANISH = 1 };
 enum { LSKUM_IMPLICIT = 0, LSKUM_EXPLICIT = 1 };
 enum { LSKUM_ORDER_COLOUR = 0, LSKUM_ORDER_WALL_FIRST = 1 };
+enum { LSKUM_FARFIELD_DIRICHLET = 0, LSKUM_FARFIELD_KINETIC = 1 };
 
 typedef struct lskum_cloud lskum_cloud; /* device geometry, CSR, colours */
 typedef struct lskum_state lskum_state; /* device flow state and work arrays */
@@ -108,6 +112,19 @@ typedef struct {
                                over its lower-/upper-colour neighbours, reading
                                what the increment array holds (zero at the
                                start of the forward sweep) */
+    int32_t farfield;       /* LSKUM_FARFIELD_DIRICHLET: outer points stay at
+                               the free stream (the paper names no outer
+                               boundary treatment).  LSKUM_FARFIELD_KINETIC (a
+                               reading of our own): an outer point with
+                               outward normal n takes the splits t+, t- and
+                               n+ (inner side) of its own stencil in its frame,
+                               and the molecules entering from outside from a
+                               free-stream ghost one nearest-neighbour distance
+                               h outside, R += (G_n-(U_inf) - G_n-(U_0)) / h,
+                               with (1/h) max(a - u_n, 0) in the diagonal
+                               (eq. 34-35; Anandhanarayanan variant); outer
+                               points are then swept and updated like the
+                               others and stay out of the residual norm */
 } lskum_params;
 
 typedef struct {
@@ -123,7 +140,7 @@ typedef struct {
 /* Fills p with the defaults: gamma 1.4, cfl 100, inner_iters 1, exact JVP,
  * fp64, check_every 10, tol_rel 1e-8, max_iters 20000, lanes 0 (library
  * choice), no limiter (limiter_k 5), Anandhanarayanan variant, implicit
- * scheme, colour order. */
+ * scheme, colour order, Dirichlet far field. */
 void lskum_default_params(lskum_params* p);
 
 /* Creates a cloud on the current HIP device from host arrays of n points.

@@ -206,10 +206,21 @@ int upload_cloud(lskum::Cloud& c) {
     c.n_active = 0;
     for (int64_t a : c.h_comp_active) c.n_active += a;
 
+    // wall and outer points keep their frame; outer points use it with the
+    // kinetic far field only, which needs a unit tangent at every one of them
     std::vector<lskum::D2> hxy(n), hfr(n);
+    c.outer_frames = true;
     for (int64_t p = 0; p < n; ++p) {
         hxy[p] = {c.h_x[p], c.h_y[p]};
-        hfr[p] = c.h_type[p] == 0 ? lskum::D2{c.h_tx[p], c.h_ty[p]} : lskum::D2{1.0, 0.0};
+        hfr[p] = {1.0, 0.0};
+        if (c.h_type[p] == 0) {
+            hfr[p] = {c.h_tx[p], c.h_ty[p]};
+        } else if (c.h_type[p] == 2) {
+            if (std::fabs(std::hypot(c.h_tx[p], c.h_ty[p]) - 1.0) < 1e-6)
+                hfr[p] = {c.h_tx[p], c.h_ty[p]};
+            else
+                c.outer_frames = false;
+        }
     }
 
     hipError_t e = hipSuccess;
@@ -311,6 +322,9 @@ void free_state(lskum::State& s) {
     s = lskum::State{};
 }
 
+constexpr const char* kNoOuterFrame =
+    "the kinetic far field needs a unit tangent (tx, ty) at every outer point";
+
 int check_params(const lskum_params* p) {
     if (!p) return fail(LSKUM_ERR_ARG, "params is NULL");
     if (!(p->gamma > 1.0) || !(p->cfl > 0.0) || p->inner_iters < 0 || p->inner_iters > 64 ||
@@ -330,6 +344,9 @@ int check_params(const lskum_params* p) {
         return fail(LSKUM_ERR_ARG, "variant must be LSKUM_ANANDH or LSKUM_MANISH");
     if (p->precision == 1 && p->jvp_mode == 1)
         return fail(LSKUM_ERR_ARG, "mixed precision supports the exact Jacobian products only");
+    if (p->farfield != 0 && p->farfield != 1)
+        return fail(LSKUM_ERR_ARG,
+                    "farfield must be LSKUM_FARFIELD_DIRICHLET or LSKUM_FARFIELD_KINETIC");
     return LSKUM_OK;
 }
 
@@ -337,7 +354,7 @@ lskum::Params to_params(const lskum_params* p) {
     return lskum::Params{p->gamma,       p->cfl,            p->inner_iters, p->jvp_mode,
                          p->precision,   p->check_every,    p->tol_rel,     p->max_iters,
                          p->sweep_lanes, p->residual_lanes, p->limiter,     p->limiter_k,
-                         p->variant,     p->scheme,         p->order};
+                         p->variant,     p->scheme,         p->order,       p->farfield};
 }
 
 // Lanes per point: the caller's choice, else 8 for the latency-bound sweeps
@@ -671,6 +688,7 @@ void lskum_default_params(lskum_params* p) {
     p->variant = LSKUM_ANANDH;
     p->scheme = LSKUM_IMPLICIT;
     p->order = LSKUM_ORDER_COLOUR;
+    p->farfield = LSKUM_FARFIELD_DIRICHLET;
 }
 
 int lskum_cloud_create(int64_t n, const double* x, const double* y, const int8_t* type,
@@ -737,6 +755,9 @@ int lskum_cloud_create(int64_t n, const double* x, const double* y, const int8_t
         delete cl;
         return r;
     }
+    if (!tx || !ty) {  // no frames given: outer points have none either
+        for (int64_t p = 0; p < n; ++p) c.outer_frames &= type[p] != 2;
+    }
     *out = cl;
     return LSKUM_OK;
 }
@@ -770,6 +791,7 @@ int lskum_state_create(const lskum_cloud* cl, double mach, double aoa_deg,
     *out = nullptr;
     int st = check_params(prm);
     if (st) return st;
+    if (prm->farfield && !cl->c.outer_frames) return fail(LSKUM_ERR_ARG, kNoOuterFrame);
     if (!(mach > 0.0) || !std::isfinite(aoa_deg)) return fail(LSKUM_ERR_ARG, "invalid flow condition");
     lskum_state* so = new (std::nothrow) lskum_state();
     if (!so) return fail(LSKUM_ERR_OOM, "host allocation");
@@ -794,6 +816,7 @@ int lskum_state_set_params(lskum_state* so, const lskum_params* prm) {
     int st = check_params(prm);
     if (st) return st;
     lskum::State& s = so->s;
+    if (prm->farfield && !s.cloud->outer_frames) return fail(LSKUM_ERR_ARG, kNoOuterFrame);
     const lskum::Params np = to_params(prm);
     // the captured iteration depends on everything but the stopping rule
     const bool same_kernels = np.gamma == s.prm.gamma &&
@@ -803,7 +826,7 @@ int lskum_state_set_params(lskum_state* so, const lskum_params* prm) {
                               np.sweep_lanes == s.prm.sweep_lanes &&
                               np.residual_lanes == s.prm.residual_lanes &&
                               np.variant == s.prm.variant && np.scheme == s.prm.scheme &&
-                              np.order == s.prm.order;
+                              np.order == s.prm.order && np.farfield == s.prm.farfield;
     if (s.graph && !same_kernels) {
         (void)hipGraphExecDestroy(s.graph);
         s.graph = nullptr;
@@ -1011,6 +1034,8 @@ int lskum_batch_create(int32_t n_clouds, const lskum_cloud* const* clouds, int32
             return fail(LSKUM_ERR_ARG, "condition refers to an invalid cloud");
         if (!(mach[k] > 0.0) || !std::isfinite(aoa_deg[k]))
             return fail(LSKUM_ERR_ARG, "invalid flow condition");
+        if (prm->farfield && !clouds[cond_cloud[k]]->c.outer_frames)
+            return fail(LSKUM_ERR_ARG, kNoOuterFrame);
         n += clouds[cond_cloud[k]]->c.n;
         nnz += clouds[cond_cloud[k]]->c.nnz;
     }
@@ -1053,6 +1078,7 @@ int lskum_batch_create(int32_t n_clouds, const lskum_cloud* const* clouds, int32
         delete b;
         return r;
     }
+    for (int32_t k = 0; k < n_cond; ++k) c.outer_frames &= clouds[cond_cloud[k]]->c.outer_frames;
     std::vector<double> m(mach, mach + n_cond), a(aoa_deg, aoa_deg + n_cond);
     if (int r = init_state(b->s, c, prm, m, a, hip_stream)) {
         free_state(b->s);

@@ -31,7 +31,16 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr double kInvSqrtPi = 0.56418958354775628694807945156077;
-constexpr int8_t kWall = 0, kOuter = 2;
+constexpr int8_t kWall = 0, kInterior = 1, kOuter = 2;
+
+// Frame points (wall, and outer points under the kinetic far field) split
+// their stencil along the tangent t and the normal n = (-t_y, t_x): t+, t-
+// and one normal half -- the fluid side (dn > 0, the n- split) at a wall, the
+// inner side (dn < 0, the n+ split) at an outer point, whose normal points
+// out of the domain.
+__device__ __forceinline__ bool in_normal_split(int8_t ty, double dn) {
+    return ty == kWall ? dn > 0.0 : dn < 0.0;
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Give XCD x the
 // contiguous range of logical blocks [x*per + min(x, rem), ...) so that
@@ -147,15 +156,14 @@ __global__ void __launch_bounds__(kBlock) k_precompute(int64_t n, const D2* __re
         sxy += dx * dy;
         const double d2 = dx * dx + dy * dy;
         rmin2 = d2 < rmin2 ? d2 : rmin2;
-        if (ty == kOuter) continue;
-        if (ty == kWall) {
+        if (ty != kInterior) {
             const double ds = dot_nc(dx, dy, t.x, t.y);
             const double dn = dot_nc(dx, dy, -t.y, t.x);
             if (ds != 0.0) {
                 const int k = ds < 0.0 ? 0 : 1;
                 saa[k] += ds * ds; sbb[k] += dn * dn; sab[k] += ds * dn; ++cnt[k];
             }
-            if (dn > 0.0) {
+            if (in_normal_split(ty, dn)) {
                 saa[2] += dn * dn; sbb[2] += ds * ds; sab[2] += ds * dn; ++cnt[2];
             }
         } else {
@@ -177,12 +185,14 @@ __global__ void __launch_bounds__(kBlock) k_precompute(int64_t n, const D2* __re
     } else {
         g.lsq = {syy / det, -sxy / det, sxx / det, sqrt(rmin2)};
     }
-    const int nsplit = ty == kOuter ? 0 : (ty == kWall ? 3 : 4);
+    const int nsplit = ty == kInterior ? 4 : 3;
     double cb[4] = {0, 0, 0, 0}, cab[4] = {0, 0, 0, 0};
     for (int k = 0; k < nsplit; ++k) {
         const double dk = saa[k] * sbb[k] - sab[k] * sab[k];
         if (cnt[k] < 2 || !(dk > 1e-12 * saa[k] * sbb[k])) {
-            atomicAdd(&counts[1], 1ull);  // degenerate half stencil: contributes 0
+            // degenerate half stencil: contributes 0 (counted for the points
+            // that always take part; outer splits only with the far field)
+            if (ty != kOuter) atomicAdd(&counts[1], 1ull);
             continue;
         }
         cb[k] = sbb[k] / dk;
@@ -190,18 +200,18 @@ __global__ void __launch_bounds__(kBlock) k_precompute(int64_t n, const D2* __re
     }
     // LS_k(1): the weight sums, with the weights exactly as the kernels form them
     double ls1[4] = {0, 0, 0, 0};
-    if (nsplit) {
+    {
         for (int32_t e = e0; e < e1; ++e) {
             const D2 ri = xy[idx[e]];
             const double dx = ri.x - r0.x, dy = ri.y - r0.y;
-            if (ty == kWall) {
+            if (ty != kInterior) {
                 const double ds = dot_nc(dx, dy, t.x, t.y);
                 const double dn = dot_nc(dx, dy, -t.y, t.x);
                 if (ds != 0.0) {
                     const int k = ds < 0.0 ? 0 : 1;
                     ls1[k] += cb[k] * ds + cab[k] * dn;
                 }
-                if (dn > 0.0) ls1[2] += cb[2] * dn + cab[2] * ds;
+                if (in_normal_split(ty, dn)) ls1[2] += cb[2] * dn + cab[2] * ds;
             } else {
                 if (dx != 0.0) {
                     const int k = dx < 0.0 ? 0 : 1;
@@ -503,10 +513,10 @@ __device__ __forceinline__ void residual_pair(int8_t ty, const D2& t, const D2& 
                     qi.z - 0.5 * (dx * gxi.z + dy * gyi.z), qi.w - 0.5 * (dx * gxi.w + dy * gyi.w)};
     const D4 qt0 = {q0.x - 0.5 * (dx * gx0.x + dy * gy0.x), q0.y - 0.5 * (dx * gx0.y + dy * gy0.y),
                     q0.z - 0.5 * (dx * gx0.z + dy * gy0.z), q0.w - 0.5 * (dx * gx0.w + dy * gy0.w)};
-    if (ty == kWall) {
+    if (ty != kInterior) {  // wall, or an outer point under the kinetic far field
         const double ds = dot_nc(dx, dy, t.x, t.y);
         const double dn = dot_nc(dx, dy, -t.y, t.x);
-        const bool in_t = ds != 0.0, in_n = dn > 0.0;
+        const bool in_t = ds != 0.0, in_n = in_normal_split(ty, dn);
         if (!in_t && !in_n) return;
         bad |= !(qti.w < 0.0) || !(qt0.w < 0.0);
         const Prim wi = prim_from_q(qti, inv_gm1, g14);
@@ -516,7 +526,9 @@ __device__ __forceinline__ void residual_pair(int8_t ty, const D2& t, const D2& 
             const double sg = ds < 0.0 ? 1.0 : -1.0;
             acc_split_diff<2>(wi, w0, t.x, t.y, sg, c.x * ds + c.y * dn, inv_gm1, Rp);
         }
-        if (in_n) acc_split_diff<2>(wi, w0, -t.y, t.x, -1.0, c2.x * dn + c2.y * ds, inv_gm1, Rp);
+        if (in_n)
+            acc_split_diff<2>(wi, w0, -t.y, t.x, ty == kWall ? -1.0 : 1.0, c2.x * dn + c2.y * ds,
+                              inv_gm1, Rp);
         return;
     }
     const bool in_x = dx != 0.0, in_y = dy != 0.0;
@@ -555,7 +567,8 @@ __global__ void __launch_bounds__(kBlock) k_residual(
     D4* __restrict__ jv0, D4* __restrict__ jv2, F4* __restrict__ jv0f, F4* __restrict__ jv2f,
     float* __restrict__ Df,
     double* __restrict__ rr_out, int32_t* __restrict__ flags, int variant, int fd,
-    D4* dUio, F4* dUfio, D4* __restrict__ Rs, const int32_t* __restrict__ colour, int sweep0) {
+    D4* dUio, F4* dUfio, D4* __restrict__ Rs, const int32_t* __restrict__ colour, int sweep0,
+    int farfield, const double* __restrict__ vinf) {
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t gt = (int64_t)lb * blockDim.x + threadIdx.x;
     const int64_t p = gt / LANES;
@@ -568,7 +581,9 @@ __global__ void __launch_bounds__(kBlock) k_residual(
         const D2 t = frame[p];
         double Rp[4] = {0, 0, 0, 0};
         int bad = 0;
-        if (ty != kOuter) {
+        // outer points take part only under the kinetic far field
+        const bool part = ty != kOuter || farfield;
+        if (part) {
             const D4 q0 = q[p], gx0 = qx[p], gy0 = qy[p];
             const PointGeom& G = geom[p];
             const D2 c0 = G.split[0], c1 = G.split[1], c2 = G.split[2], c3 = G.split[3];
@@ -604,6 +619,28 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                 Rp[1] -= mn * nx;
                 Rp[2] -= mn * ny;
             }
+            if (ty == kOuter && farfield) {
+                // kinetic far field: the n- half (molecules entering the domain)
+                // from a free-stream ghost one nearest-neighbour distance outside,
+                // (G_n-(U_inf) - G_n-(U_0)) / h with the point's own q
+                const int k = comp ? comp[p] : 0;
+                const double v1 = vinf[2 * k], v2 = vinf[2 * k + 1];
+                Prim wf;
+                wf.rho = 1.0;
+                wf.u1 = v1;
+                wf.u2 = v2;
+                wf.p = 1.0 / gamma;
+                wf.sb = sqrt(0.5 * gamma);
+                wf.isb = 1.0 / wf.sb;
+                wf.rhoE = wf.p * inv_gm1 + 0.5 * (v1 * v1 + v2 * v2);
+                const Prim w0 = prim_from_q(q[p], inv_gm1, g14);
+                double Gf[4], G0[4];
+                split_flux<2>(wf, -t.y, t.x, -1.0, inv_gm1, Gf);
+                split_flux<2>(w0, -t.y, t.x, -1.0, inv_gm1, G0);
+                const double ih = 1.0 / geom[p].lsq.w;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Rp[v] += (Gf[v] - G0[v]) * ih;
+            }
             rr_out[p] = ty != kOuter ? Rp[0] * Rp[0] : 0.0;
             R[p] = {Rp[0], Rp[1], Rp[2], Rp[3]};
 
@@ -634,6 +671,14 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                     Dp += G.ls1.y * fmax(a - u1, 0.0);
                     Dp -= G.ls1.z * fmax(u2 + a, 0.0);
                     Dp += G.ls1.w * fmax(a - u2, 0.0);
+                } else if (farfield) {
+                    // t+, t-, n+ of the stencil and the ghost's n- half, whose
+                    // single weight is 1/h (its increment is zero)
+                    const double ut = u1 * t.x + u2 * t.y, un = -u1 * t.y + u2 * t.x;
+                    Dp -= G.ls1.x * fmax(ut + a, 0.0);
+                    Dp += G.ls1.y * fmax(a - ut, 0.0);
+                    Dp -= G.ls1.z * fmax(un + a, 0.0);
+                    Dp += fmax(a - un, 0.0) / G.lsq.w;
                 }
             } else {
                 // Manish et al.: A+- = (A +- rho(A) I)/2, rho(A) = |u_d| + a (eq. 29-33); the
@@ -662,6 +707,19 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                     }
                     ca = G.ls1.x + G.ls1.y;
                     cb = G.ls1.z;
+                } else if (ty == kOuter && farfield) {
+                    const double ut = u1 * t.x + u2 * t.y, un = -u1 * t.y + u2 * t.x;
+                    Dp -= 0.5 * (fabs(ut) + a) * (G.ls1.x - G.ls1.y);
+                    Dp -= 0.5 * (fabs(un) + a) * G.ls1.z;
+                    if (fd) {
+                        unsplit_jvp<true>(u, dv, t.x, t.y, gamma - 1.0, Ja);
+                        unsplit_jvp<true>(u, dv, -t.y, t.x, gamma - 1.0, Jb);
+                    } else {
+                        unsplit_jvp<false>(u, dv, t.x, t.y, gamma - 1.0, Ja);
+                        unsplit_jvp<false>(u, dv, -t.y, t.x, gamma - 1.0, Jb);
+                    }
+                    ca = G.ls1.x + G.ls1.y;
+                    cb = G.ls1.z;
                 } else if (ty != kOuter) {
                     Dp -= 0.5 * (fabs(u1) + a) * (G.ls1.x - G.ls1.y);
                     Dp -= 0.5 * (fabs(u2) + a) * (G.ls1.z - G.ls1.w);
@@ -675,7 +733,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                     ca = G.ls1.x + G.ls1.y;
                     cb = G.ls1.z + G.ls1.w;
                 }
-                if (ty != kOuter)
+                if (part)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) Sv[v] = -0.5 * (ca * Ja[v] + cb * Jb[v]);
                 Rs[p] = {Rp[0] - Sv[0], Rp[1] - Sv[1], Rp[2] - Sv[2], Rp[3] - Sv[3]};
@@ -703,7 +761,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                 }
                 if (MIXED) {
                     float o[4] = {0.f, 0.f, 0.f, 0.f};
-                    if (ty != kOuter) {
+                    if (part) {
                         const float iD = 1.0f / (float)Dp;
 #pragma unroll
                         for (int v = 0; v < 4; ++v) o[v] = -((float)rs[v] + 0.0f) * iD;
@@ -717,7 +775,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                     dUfio[p] = {o[0], o[1], o[2], o[3]};
                 } else {
                     double o[4] = {0, 0, 0, 0};
-                    if (ty != kOuter) {
+                    if (part) {
                         const double iD = 1.0 / Dp;
 #pragma unroll
                         for (int v = 0; v < 4; ++v) o[v] = -(rs[v] + 0.0) * iD;
@@ -907,8 +965,10 @@ __device__ __forceinline__ Lin<T> load_lin(const Vec4<T>* jv0, int32_t i) {
 
 // Split weights and bits of the sweep-list entries of the colour-sorted point
 // q (thread per q): for interior points the x split (a) and y split (b) the
-// neighbour falls in, for wall points the t split (a) and, on the fluid side,
-// the n- split (b) -- membership and weights exactly as the residual forms them.
+// neighbour falls in; for frame points the t split (a) and the normal split
+// (b): n- on the fluid side of a wall point, n+ on the inner side of an outer
+// point (used under the kinetic far field) -- membership and weights exactly
+// as the residual forms them.
 __global__ void __launch_bounds__(kBlock) k_sweep_weights(int64_t n,
                                                           const int32_t* __restrict__ col_perm,
                                                           const D2* __restrict__ xy,
@@ -931,7 +991,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_weights(int64_t n,
         const double dx = ri.x - r0.x, dy = ri.y - r0.y;
         uint8_t cd = 0;
         double wa = 0.0, wb = 0.0;
-        if (ty == kWall) {
+        if (ty != kInterior) {
             const double ds = dot_nc(dx, dy, t.x, t.y);
             const double dn = dot_nc(dx, dy, -t.y, t.x);
             cd |= kSwWall;
@@ -940,11 +1000,11 @@ __global__ void __launch_bounds__(kBlock) k_sweep_weights(int64_t n,
                 cd |= kSwA | (ds < 0.0 ? kSwNegA : 0);
                 wa = cc.x * ds + cc.y * dn;
             }
-            if (dn > 0.0) {
-                cd |= kSwB;
+            if (in_normal_split(ty, dn)) {
+                cd |= kSwB | (dn < 0.0 ? kSwNegB : 0);
                 wb = G.split[2].x * dn + G.split[2].y * ds;
             }
-        } else if (ty != kOuter) {
+        } else {
             if (dx != 0.0) {
                 const D2 cc = dx < 0.0 ? G.split[0] : G.split[1];
                 cd |= kSwA | (dx < 0.0 ? kSwNegA : 0);
@@ -964,8 +1024,9 @@ __global__ void __launch_bounds__(kBlock) k_sweep_weights(int64_t n,
 
 // Contribution sum_k w_i^k A_k(U_i) dU_i of neighbour i to point p's sweep
 // sum (eq. 22-27) from the entry's weights and split bits: interior points
-// use the x and y split the neighbour falls in, wall points the t split and,
-// on the fluid side, the n- split (wall frame t of point p).
+// use the x and y split the neighbour falls in, frame points the t split and
+// the normal split (n- at a wall, n+ at a far-field outer point) in the frame
+// t of point p.
 template <class T, int MODE>
 __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<T>& w, int32_t i,
                                               const Vec4<T>* __restrict__ jv0,
@@ -996,13 +1057,14 @@ __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<
             for (int v = 0; v < 4; ++v) acc[v] += wa * J[v];
         }
         if (cd & kSwB) {
+            const double sg = (cd & kSwNegB) ? 1.0 : -1.0;
             if constexpr (MODE == 1) {
                 const double S = (-L.u1 * t.y + L.u2 * t.x) * L.sb;
-                jvp_fluxdiff(L, erf(S), exp(-(S * S)), U[i], -t.y, t.x, -1.0, dv, gamma,
+                jvp_fluxdiff(L, erf(S), exp(-(S * S)), U[i], -t.y, t.x, sg, dv, gamma,
                              1.0 / (gamma - 1.0), J);
             } else {
                 const T S = (-L.u1 * T(t.y) + L.u2 * T(t.x)) * L.sb;
-                jvp_exact<T>(L, erf(S), exp(-(S * S)), T(-t.y), T(t.x), T(-1), dv, gm1, inv_gm1, J);
+                jvp_exact<T>(L, erf(S), exp(-(S * S)), T(-t.y), T(t.x), T(sg), dv, gm1, inv_gm1, J);
             }
             const T wb = T(w.y);
 #pragma unroll
@@ -1049,7 +1111,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
     const int32_t* __restrict__ comp, const int32_t* __restrict__ active,
     const Vec4<T>* __restrict__ jv0, const Vec4<T>* __restrict__ jv2,
     const D4* __restrict__ U, const D4* __restrict__ R,
-    const T* __restrict__ Dg, Vec4<T>* __restrict__ dU, double gamma) {
+    const T* __restrict__ Dg, Vec4<T>* __restrict__ dU, double gamma, int farfield) {
     const int gt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int pt = gt / LANES, lane = gt % LANES;
     if (pt >= count) return;  // uniform over the lanes of a point
@@ -1106,7 +1168,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] += __shfl_xor(acc[v], o, 64);
     if (lane != 0) return;
-    if (ty == kOuter) {
+    if (ty == kOuter && !farfield) {
         if (FWD) dU[p] = {T(0), T(0), T(0), T(0)};
         return;
     }
@@ -1155,14 +1217,15 @@ __global__ void __launch_bounds__(kBlock) k_update(int64_t n, double gamma, D4* 
 
 // Explicit iteration (the paper's explicit LSKUM solver): U <- U - dt R with
 // the implicit scheme's local time step dt = CFL rmin / (|u| + a) at the
-// current state, then the next q-variables.  Outer points keep their state.
+// current state, then the next q-variables.  Outer points keep their state
+// unless the kinetic far field gives them a residual.
 __global__ void __launch_bounds__(kBlock) k_explicit_update(
     int64_t n, double gamma, const double* __restrict__ cfl, const int8_t* __restrict__ type,
     const PointGeom* __restrict__ geom, const int32_t* __restrict__ comp,
     const int32_t* __restrict__ active, const D4* __restrict__ R, D4* __restrict__ U,
-    D4* __restrict__ q, int32_t* __restrict__ flags) {
+    D4* __restrict__ q, int32_t* __restrict__ flags, int farfield) {
     const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (p >= n || !live(comp, active, p) || type[p] == kOuter) return;
+    if (p >= n || !live(comp, active, p) || (type[p] == kOuter && !farfield)) return;
     D4 u = U[p];
     const double rho = u.x, irho = 1.0 / rho;
     const double u1 = u.y * irho, u2 = u.z * irho;
@@ -1358,7 +1421,7 @@ static void residual_lanes(State& s, bool in_step) {
                        s.prm.limiter ? s.qyl : s.qy[s.qsel], s.R, s.D, s.jv0, s.jv2, s.jv0f,
                        s.jv2f, s.Df, s.rr, s.flags, s.prm.variant,
                        s.prm.jvp_mode, s.dU, s.dUf, s.Rs, c.colour,
-                       in_step && fused_first_colour(s));
+                       in_step && fused_first_colour(s), s.prm.farfield, s.vinf);
 }
 
 template <bool MIXED>
@@ -1440,12 +1503,12 @@ static void sweep_lanes(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T
                                c.col_perm, c.frame, c.type, c.lo_off, c.lo_idx,
                                list_weights<T>(c.lo_w, c.lo_wf), c.lo_code, c.comp, s.active,
                                jv0, jv2, s.U, s.prm.variant ? s.Rs : s.R, Dg, dU,
-                               s.prm.gamma);
+                               s.prm.gamma, s.prm.farfield);
         else
             hipLaunchKernelGGL((k_sweep<T, false, MODE, LANES>), g, b, 0, s.stream, start, cnt,
                                c.col_perm, c.frame, c.type, c.up_off, c.up_idx,
                                list_weights<T>(c.up_w, c.up_wf), c.up_code, c.comp, s.active,
-                               jv0, jv2, s.U, s.R, Dg, dU, s.prm.gamma);
+                               jv0, jv2, s.U, s.R, Dg, dU, s.prm.gamma, s.prm.farfield);
     }
 }
 
@@ -1498,7 +1561,7 @@ hipError_t launch_explicit_update(State& s) {
     const Cloud& c = *s.cloud;
     hipLaunchKernelGGL(k_explicit_update, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream, c.n,
                        s.prm.gamma, s.cfl, c.type, c.geom, c.comp, s.active, s.R, s.U, s.q,
-                       s.flags);
+                       s.flags, s.prm.farfield);
     return hipGetLastError();
 }
 

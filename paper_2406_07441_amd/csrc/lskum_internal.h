@@ -55,6 +55,7 @@ struct Cloud {
     int64_t n_active = 0;      // non-outer points
     int64_t n_wall = 0;
     double wall_orient = 1.0;  // +1 if the wall polygon runs counter-clockwise
+    bool outer_frames = true;  // every outer point has a unit tangent (kinetic far field)
     // device
     D2* xy = nullptr;          // coordinates
     D2* frame = nullptr;       // unit tangent (wall points); (1, 0) elsewhere
@@ -122,6 +123,7 @@ struct Params {
     int variant;  // 0 Anandhanarayanan et al., 1 Manish et al.
     int scheme;   // 0 implicit (LU-SGS), 1 explicit
     int order;    // 0 colour order (Algorithm 6), 1 wall points first (Algorithm 5)
+    int farfield; // 0 outer points at the free stream, 1 kinetic far field
 };
 
 // Device work arrays of one flow state.

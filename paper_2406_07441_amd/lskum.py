@@ -25,6 +25,7 @@ FP64, MIXED = 0, 1
 ANANDH, MANISH = 0, 1
 IMPLICIT, EXPLICIT = 0, 1
 ORDER_COLOUR, ORDER_WALL_FIRST = 0, 1
+FARFIELD_DIRICHLET, FARFIELD_KINETIC = 0, 1
 
 
 class LskumError(RuntimeError):
@@ -38,7 +39,8 @@ class Params(C.Structure):
                 ("jvp_mode", C.c_int32), ("precision", C.c_int32), ("check_every", C.c_int32),
                 ("tol_rel", C.c_double), ("max_iters", C.c_int32), ("sweep_lanes", C.c_int32),
                 ("residual_lanes", C.c_int32), ("limiter", C.c_int32), ("limiter_k", C.c_double),
-                ("variant", C.c_int32), ("scheme", C.c_int32), ("order", C.c_int32)]
+                ("variant", C.c_int32), ("scheme", C.c_int32), ("order", C.c_int32),
+                ("farfield", C.c_int32)]
 
 
 class Report(C.Structure):

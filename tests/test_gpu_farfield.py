@@ -1,0 +1,194 @@
+"""GPU parity of the kinetic far field (a reading; the paper gives no outer
+boundary treatment) with the oracle's.
+
+At an outer point with outward normal n the residual takes the t+, t- and
+n+ splits of its own stencil plus the free-stream ghost's n- half,
+(G_n-(U_inf) - G_n-(U_0)) / h, and the diagonal the ghost's share
+(1/h) max(a - u_n, 0); outer points are swept and updated like the others.
+Bar as for the Dirichlet far field: 1e-11 relative per component for R, the
+q-derivatives and dU of one iteration (exact tangents, flux differences, the
+Manish variant, the limiter, wall-first order, the explicit scheme), and 1e-8
+for a converged field with its lift and drag.  Inputs: the 160 x 40 O-grid at
+M 0.63, 2 deg, whose outer ring carries the tangent with n pointing out of
+the domain, at the free stream and after 1 and 10 oracle iterations.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2406_07441_amd import cloudgen as cg
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+MACH, AOA = 0.63, 2.0
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    scale = np.abs(b).max()
+    return float(max(np.abs(a[v] - b[v]).max() / (np.abs(b[v]).max() or scale)
+                     for v in range(b.shape[0])))
+
+
+@pytest.fixture(scope="module")
+def lk():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2406_07441_amd import lskum
+    lskum.lib()
+    return lskum
+
+
+@pytest.fixture(scope="module")
+def ff(lk):
+    cloud = cg.cloud_6400()
+    o = O.Oracle(cloud, mach=MACH, aoa_deg=AOA, cfl=100.0, inner_iters=1, farfield=O.KINETIC)
+    U = o.free_stream()
+    states = {0: U.copy()}
+    for it in range(10):
+        U, _, _, _ = o.iteration(U)
+        if it + 1 in (1, 10):
+            states[it + 1] = U.copy()
+    return cloud, lk.Cloud(cloud), states
+
+
+def kinetic(lk, **kw):
+    return lk.default_params(farfield=lk.FARFIELD_KINETIC, **kw)
+
+
+@pytest.mark.parametrize("jvp_mode", [0, 1])
+def test_far_field_iteration_parity(lk, ff, jvp_mode):
+    cloud, gc, states = ff
+    kw = dict(cfl=100.0, inner_iters=1, jvp_mode=jvp_mode)
+    o = O.Oracle(cloud, mach=MACH, aoa_deg=AOA, farfield=O.KINETIC, **kw)
+    st = lk.State(gc, MACH, AOA, kinetic(lk, **kw))
+    outer = cloud.type == 2
+    for it, U in states.items():
+        st.set_U(U)
+        R, res = st.residual()
+        Ro, reso = o.residual(U)
+        st.set_U(U)
+        st.step()
+        _, _, dUo, _ = o.iteration(U)
+        dU = st.get_dU()
+        e = (rel(R, Ro), rel(dU, dUo))
+        print(f"kinetic far field mode={jvp_mode} it={it}: R {e[0]:.2e} dU {e[1]:.2e} "
+              f"outer |dU| {np.abs(dUo[:, outer]).max():.2e}")
+        # the outer points move: the boundary is not held at the free stream
+        assert np.abs(dUo[:, outer]).max() > 0.0
+        assert max(e) < TOL and abs(res - reso) <= TOL * reso
+    st.close()
+
+
+def test_far_field_variants_parity(lk, ff):
+    """Manish variant (lagged S over three carried iterations), the limiter,
+    wall-first order and the explicit scheme, each with the kinetic far field."""
+    cloud, gc, states = ff
+    # Manish: diagonal with rho(A)/2 and S from the previous increment
+    kw = dict(cfl=5.0, inner_iters=1)
+    o = O.Oracle(cloud, mach=MACH, aoa_deg=AOA, variant=O.MANISH, farfield=O.KINETIC, **kw)
+    st = lk.State(gc, MACH, AOA, kinetic(lk, variant=lk.MANISH, **kw))
+    U, dU = o.free_stream(), None
+    for it in range(3):
+        U, _, dU, res = o.iteration(U, dU)
+        res_gpu = st.step()
+        e = rel(st.get_dU(), dU)
+        print(f"kinetic far field, Manish it={it}: dU {e:.2e}")
+        assert e < TOL and abs(res_gpu - res) <= TOL * res
+    st.close()
+    # limiter (K 5) and wall-first order, one iteration from the state after 10
+    for extra in (dict(limiter=1, limiter_k=5.0), dict(order=1)):
+        kw = dict(cfl=100.0, inner_iters=1, **extra)
+        o = O.Oracle(cloud, mach=MACH, aoa_deg=AOA, farfield=O.KINETIC, **kw)
+        st = lk.State(gc, MACH, AOA, kinetic(lk, **kw))
+        U = states[10]
+        st.set_U(U)
+        st.step()
+        _, _, dUo, _ = o.iteration(U)
+        e = rel(st.get_dU(), dUo)
+        print(f"kinetic far field {extra}: dU {e:.2e}")
+        assert e < TOL
+        st.close()
+    # explicit scheme: outer points now carry a residual and move
+    o = O.Oracle(cloud, mach=MACH, aoa_deg=AOA, cfl=0.4, inner_iters=1, farfield=O.KINETIC)
+    st = lk.State(gc, MACH, AOA, kinetic(lk, cfl=0.4, scheme=lk.EXPLICIT))
+    U0 = o.free_stream()
+    U = U0
+    for _ in range(3):
+        U, _, res = o.explicit_iteration(U)
+        res_gpu = st.step()
+        assert abs(res_gpu - res) <= TOL * res
+    e = rel(st.get_U() - U0, U - U0)
+    print(f"kinetic far field, explicit: U change {e:.2e}")
+    assert e < TOL
+    st.close()
+
+
+def test_far_field_mixed_precision_and_batch(lk, ff):
+    cloud, gc, states = ff
+    kw = dict(cfl=100.0, inner_iters=1)
+    o = O.Oracle(cloud, mach=MACH, aoa_deg=AOA, farfield=O.KINETIC, **kw)
+    st = lk.State(gc, MACH, AOA, kinetic(lk, precision=lk.MIXED, **kw))
+    U = states[10]
+    st.set_U(U)
+    st.step()
+    _, _, dUo, _ = o.iteration(U)
+    e = rel(st.get_dU(), dUo)
+    print(f"kinetic far field, mixed: dU {e:.2e} vs the fp64 oracle")
+    assert e < 1e-4
+    st.close()
+    # a batch of two conditions equals single states bitwise
+    prm = kinetic(lk, check_every=5, max_iters=5, tol_rel=0.0, **kw)
+    b = lk.Batch([gc], [0, 0], [MACH, 0.5], [AOA, -1.0], prm)
+    b.solve()
+    for k, (m, a) in enumerate(((MACH, AOA), (0.5, -1.0))):
+        s1 = lk.State(gc, m, a, prm)
+        s1.solve()
+        assert np.array_equal(b.get_U(k), s1.get_U())
+        s1.close()
+    b.close()
+
+
+def test_far_field_converged_lifting_field(lk):
+    # both solvers run 2,000 iterations from the free stream on a 64 x 16
+    # O-grid at M 0.5, 2 deg to a residual drop below 1e-12; the fixed points
+    # and their forces agree, and differ from the Dirichlet far field's
+    cloud = cg.ogrid(64, 16, r=1.15)
+    kw = dict(cfl=100.0, inner_iters=1)
+    o = O.Oracle(cloud, mach=0.5, aoa_deg=2.0, farfield=O.KINETIC, **kw)
+    Uo, it, hist = o.solve(o.free_stream(), 2000)
+    assert hist[-1] < 1e-12 * hist[0]
+    gc = lk.Cloud(cloud)
+    st = lk.State(gc, 0.5, 2.0, kinetic(lk, check_every=100, max_iters=2000, tol_rel=0.0, **kw))
+    rep = st.solve()
+    assert rep.iters == 2000 and rep.res_final < 1e-12 * rep.res_fs
+    e = rel(st.get_U(), Uo)
+    cl, cd = st.forces()
+    clo, cdo = o.forces(Uo)
+    sd = lk.State(gc, 0.5, 2.0, lk.default_params(check_every=100, max_iters=2000, tol_rel=0.0,
+                                                  **kw))
+    sd.solve()
+    cld, _ = sd.forces()
+    print(f"kinetic far field, converged 64x16: U rel err {e:.3e}, cl {cl:.10f} / {clo:.10f}, "
+          f"cd {cd:.10f} / {cdo:.10f}; Dirichlet cl {cld:.10f}")
+    assert e < 1e-8
+    assert clo > 0.1 and abs(cl - clo) < 1e-8 and abs(cd - cdo) < 1e-8
+    assert abs(cl - cld) > 1e-6
+    st.close()
+    sd.close()
+
+
+def test_far_field_needs_outer_frames(lk):
+    # outer points without a unit tangent: the Dirichlet far field runs, the
+    # kinetic one is refused at state creation and by set_params
+    c = cg.box(8, 8, h=0.1)
+    c.tx = np.where(c.type == 2, 0.0, c.tx)
+    c.ty = np.where(c.type == 2, 0.0, c.ty)
+    gc = lk.Cloud(c)
+    with pytest.raises(lk.LskumError):
+        lk.State(gc, 0.5, 0.0, kinetic(lk))
+    st = lk.State(gc, 0.5, 0.0, lk.default_params())
+    with pytest.raises(lk.LskumError):
+        st.set_params(kinetic(lk))
+    st.close()
