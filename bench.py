@@ -186,6 +186,35 @@ def explicit_vs_implicit(lk, gc, iters):
     return out
 
 
+def residual_histories(lk, cloudgen, max_iters=20000, chunk=200):
+    """The 160 x 40 cloud (M 0.63, 2 deg, no limiter: the paper's scheme as
+    written) solved to 1e-8 with exact tangents and with flux differences in
+    FP64: iterations, time and the residual drop every `chunk` iterations --
+    the convergence-rate comparison of the paper's residual histories."""
+    cloud = cloudgen.cloud_6400()
+    gc = lk.Cloud(cloud)
+    out = {"workload": "O-grid 160x40=6400 pts, M0.63 AoA2, CFL100, m=1, no limiter"}
+    for name, mode in (("exact", lk.JVP_EXACT), ("fluxdiff", lk.JVP_FLUXDIFF)):
+        prm = lk.default_params(cfl=CFL, inner_iters=INNER, jvp_mode=mode, check_every=chunk,
+                                tol_rel=1e-8, max_iters=chunk)
+        st = lk.State(gc, 0.63, 2.0, prm)
+        hist, it, secs, status = [], 0, 0.0, -6
+        while it < max_iters:
+            rep = st.solve()
+            it += rep.iters
+            secs += rep.seconds
+            hist.append(float(f"{rep.res_final / rep.res_fs:.4e}"))
+            if rep.status != -6:
+                status = rep.status
+                break
+        cl, cd = st.forces()
+        out[name] = {"iters": it, "status": status, "seconds": secs, "cl": cl, "cd": cd,
+                     f"res_drop_every_{chunk}": hist}
+        st.close()
+    gc.close()
+    return out
+
+
 def batch_run(lk, cloudgen, iters):
     """64 conditions on 8 uneven clouds, FP32 sweeps / FP64 residual, autotuned."""
     import numpy as np
@@ -214,14 +243,17 @@ def batch_run(lk, cloudgen, iters):
 CHUNK_ITERS = 2000   # long solves run in chunks, each printing a progress line
 
 
-def solve_chunked(obj, prm, max_iters, n_cond, label):
+def solve_chunked(obj, prm, max_iters, n_cond, label, max_seconds=0.0):
     """Solves a State (n_cond 1) or Batch to its tolerance in chunks of
     CHUNK_ITERS iterations; returns per-condition (iters, seconds, status, cl,
-    cd) at first convergence and the total seconds."""
+    cd) at first convergence and the total seconds.  max_seconds > 0 stops
+    after the chunk that passes it."""
     done = [None] * n_cond
     total_it, total_s = 0, 0.0
     last = None
     while total_it < max_iters and any(d is None for d in done):
+        if max_seconds > 0 and total_s >= max_seconds:
+            break
         prm.max_iters = min(CHUNK_ITERS, max_iters - total_it)
         obj.set_params(prm)
         if n_cond == 1:
@@ -249,9 +281,17 @@ def solve_chunked(obj, prm, max_iters, n_cond, label):
     return done, total_s
 
 
-def batch_converge(lk, cloudgen, max_iters):
+# Residual-driven CFL control of the batch (a reading of our own: the paper
+# runs one CFL number): a condition whose residual reaches no new minimum over
+# a window of iterations has its CFL number cut by a factor, down to a floor.
+CFL_WINDOW, CFL_FACTOR, CFL_MIN = 2000, 0.3, 9.0
+
+
+def batch_converge(lk, cloudgen, max_iters, max_seconds=0.0):
     """The 64-condition batch solved to 1e-8 of each condition's free-stream
-    residual: time until all retire, per-condition iterations."""
+    residual with the per-condition CFL control: time until all retire,
+    per-condition iterations and final CFL numbers.  max_seconds > 0 stops
+    after the chunk that passes it (the rest are listed as not converged)."""
     import numpy as np
     clouds = cloudgen.batch_clouds()
     gcs = [lk.Cloud(c) for c in clouds]
@@ -261,12 +301,17 @@ def batch_converge(lk, cloudgen, max_iters):
     b = lk.Batch(gcs, np.arange(64) % 8, mach, aoa, prm)
     lanes = b.autotune(2)
     prm.sweep_lanes, prm.residual_lanes = lanes[0], lanes[1]
-    done, tot = solve_chunked(b, prm, max_iters, 64, "batch to 1e-8")
+    b.set_cfl_control(CFL_WINDOW, CFL_FACTOR, CFL_MIN)
+    done, tot = solve_chunked(b, prm, max_iters, 64, "batch to 1e-8", max_seconds)
     pts = sum(d["iters"] * b.sizes[k] for k, d in enumerate(done))
+    conv = [d["seconds"] for d in done if d["status"] == 0]
     out = {"conditions": 64, "points": b.n_points,
-           "seconds_until_all_retired": max(d["seconds"] for d in done),
+           "cfl_control": {"window": CFL_WINDOW, "factor": CFL_FACTOR, "cfl_min": CFL_MIN},
+           "seconds_until_all_retired": max(conv) if len(conv) == 64 else None,
+           "seconds_run": tot, "converged": len(conv),
            "point_iters_per_s": pts / tot, "lanes": {"sweep": lanes[0], "residual": lanes[1]},
            "iters": [d["iters"] for d in done],
+           "final_cfl": [float(f"{c:.3g}") for c in b.get_cfl()],
            "res_drop": [float(f"{d['res_drop']:.3e}") for d in done],
            "not_converged": [k for k, d in enumerate(done) if d["status"] != 0]}
     b.close()
@@ -534,6 +579,11 @@ def parse_args(argv=None):
                     help="held-out conditions of the warm-start leg")
     ap.add_argument("--batch-converge-iters", type=int, default=0,
                     help="solve the 64-condition batch to 1e-8 with this cap (0 skips)")
+    ap.add_argument("--batch-converge-seconds", type=float, default=0.0,
+                    help="stop the batch-to-1e-8 leg after this many seconds (0: no limit)")
+    ap.add_argument("--histories", action="store_true",
+                    help="residual histories to 1e-8 on the 6,400-point cloud, exact vs "
+                         "flux-difference products")
     ap.add_argument("--config3-iters", type=int, default=0,
                     help="2,621,440-point FP64 vs mixed run to 1e-8 with this cap (0 skips)")
     ap.add_argument("--config3-precisions", default="fp64,mixed",
@@ -643,7 +693,10 @@ def main(argv=None):
     if args.batch_iters > 0:
         leg("batch_64_conditions", batch_run, lk, cloudgen, args.batch_iters)
     if args.batch_converge_iters > 0:
-        leg("batch_64_to_1e-8", batch_converge, lk, cloudgen, args.batch_converge_iters)
+        leg("batch_64_to_1e-8", batch_converge, lk, cloudgen, args.batch_converge_iters,
+            args.batch_converge_seconds)
+    if args.histories:
+        leg("residual_histories_6400", residual_histories, lk, cloudgen)
     if args.config3_iters > 0:
         leg("cloud_2621440_to_1e-8", config3_run, lk, cloudgen, args.config3_iters,
             args.config3_precisions.split(","))

@@ -455,6 +455,147 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad(
     }
 }
 
+// The same q-derivative pass with the neighbour gathers staged in LDS.  Tile
+// b is the kTile consecutive points [b kTile, (b+1) kTile); the host lists
+// the union of their neighbours (tile_idx[tile_off[b] ...], sorted) and gives
+// every CSR entry its neighbour's position in that list (lnbr).  The block
+// first copies position, q (and the current derivatives) of the listed
+// points into LDS -- runs of consecutive indices, so mostly coalesced --
+// then every neighbour read of the sums comes from LDS: a point's 24
+// neighbour records are shared with the tile's other points instead of being
+// gathered 24 times from the caches.  Four lanes per point; the arithmetic
+// and summation order are those of k_qgrad<INNER, LIMIT, 4>, so the results
+// are the same bit for bit.
+static_assert(kQTile * 4 == kBlock, "a q-derivative tile is one point per four lanes");
+
+template <bool INNER, bool LIMIT>
+__global__ void __launch_bounds__(kBlock, 4) k_qgrad_tiled(
+    int64_t n, double K, const D2* __restrict__ xy, const int32_t* __restrict__ off,
+    const uint16_t* __restrict__ lnbr, const int32_t* __restrict__ tile_off,
+    const int32_t* __restrict__ tile_idx, int32_t hmax, const PointGeom* __restrict__ geom,
+    const int32_t* __restrict__ comp, const int32_t* __restrict__ active,
+    const D4* __restrict__ q, const D4* __restrict__ qx_in, const D4* __restrict__ qy_in,
+    D4* __restrict__ qx_out, D4* __restrict__ qy_out, D4* __restrict__ qxl,
+    D4* __restrict__ qyl) {
+    extern __shared__ D4 smem[];
+    D4* s_q = smem;
+    D4* s_gx = s_q + hmax;
+    D4* s_gy = s_gx + (INNER ? hmax : 0);
+    D2* s_r = reinterpret_cast<D2*>(s_gy + (INNER ? hmax : 0));
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int32_t h0 = tile_off[tile], nh = tile_off[tile + 1] - h0;
+    for (int32_t k = threadIdx.x; k < nh; k += kBlock) {
+        const int32_t i = tile_idx[h0 + k];
+        s_r[k] = xy[i];
+        s_q[k] = q[i];
+        if (INNER) {
+            s_gx[k] = qx_in[i];
+            s_gy[k] = qy_in[i];
+        }
+    }
+    __syncthreads();
+    const int64_t p = (int64_t)tile * kQTile + threadIdx.x / 4;
+    const int lane = threadIdx.x % 4;
+    if (p >= n || !live(comp, active, p)) return;  // uniform over the lanes of a point
+    const D2 r0 = xy[p];
+    const D4 q0 = q[p];
+    const double qv[4] = {q0.x, q0.y, q0.z, q0.w};
+    D4 gx0{}, gy0{};
+    if (INNER) {
+        gx0 = qx_in[p];
+        gy0 = qy_in[p];
+    }
+    double bx[4] = {0, 0, 0, 0}, by[4] = {0, 0, 0, 0};
+    double dmax[4] = {0, 0, 0, 0}, dmin[4] = {0, 0, 0, 0};
+    const int32_t e0 = off[p], e1 = off[p + 1];
+    for (int32_t e = e0 + lane; e < e1; e += 4) {
+        const int li = lnbr[e];
+        const D2 ri = s_r[li];
+        const double dx = ri.x - r0.x, dy = ri.y - r0.y;
+        const D4 qi = s_q[li];
+        double dq[4] = {qi.x - qv[0], qi.y - qv[1], qi.z - qv[2], qi.w - qv[3]};
+        if (LIMIT) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                dmax[v] = fmax(dmax[v], dq[v]);
+                dmin[v] = fmin(dmin[v], dq[v]);
+            }
+        }
+        if (INNER) {
+            const D4 gxi = s_gx[li], gyi = s_gy[li];
+            dq[0] -= 0.5 * (dx * (gxi.x - gx0.x) + dy * (gyi.x - gy0.x));
+            dq[1] -= 0.5 * (dx * (gxi.y - gx0.y) + dy * (gyi.y - gy0.y));
+            dq[2] -= 0.5 * (dx * (gxi.z - gx0.z) + dy * (gyi.z - gy0.z));
+            dq[3] -= 0.5 * (dx * (gxi.w - gx0.w) + dy * (gyi.w - gy0.w));
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            bx[v] += dx * dq[v];
+            by[v] += dy * dq[v];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        bx[v] = lane_sum<4>(bx[v]);
+        by[v] = lane_sum<4>(by[v]);
+    }
+    const D4 L = geom[p].lsq;
+    double gx[4], gy[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        gx[v] = L.x * bx[v] + L.y * by[v];
+        gy[v] = L.y * bx[v] + L.z * by[v];
+    }
+    if (lane == 0) {
+        qx_out[p] = {gx[0], gx[1], gx[2], gx[3]};
+        qy_out[p] = {gy[0], gy[1], gy[2], gy[3]};
+    }
+    if (!LIMIT) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int o = 2; o > 0; o >>= 1) {
+            dmax[v] = fmax(dmax[v], __shfl_xor(dmax[v], o, 64));
+            dmin[v] = fmin(dmin[v], __shfl_xor(dmin[v], o, 64));
+        }
+    const double kh = K * L.w;
+    const double eps2 = kh * kh * kh;
+    double fn[4] = {1, 1, 1, 1}, fd[4] = {1, 1, 1, 1};  // running minimum fn/fd
+    for (int32_t e = e0 + lane; e < e1; e += 4) {
+        const D2 ri = s_r[lnbr[e]];
+        const double dx = ri.x - r0.x, dy = ri.y - r0.y;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double d2 = -0.5 * (dx * gx[v] + dy * gy[v]);
+            if (d2 == 0.0) continue;
+            const double d1 = d2 > 0.0 ? dmax[v] : dmin[v];
+            const double nu = d1 * d1 + eps2 + 2.0 * d1 * d2;
+            const double de = d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2;
+            if (nu * fd[v] < fn[v] * de) {
+                fn[v] = nu;
+                fd[v] = de;
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int o = 2; o > 0; o >>= 1) {
+            const double on = __shfl_xor(fn[v], o, 64), od = __shfl_xor(fd[v], o, 64);
+            if (on * fd[v] < fn[v] * od) {
+                fn[v] = on;
+                fd[v] = od;
+            }
+        }
+    if (lane == 0) {
+        double phi[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) phi[v] = fmax(fn[v] / fd[v], 0.0);
+        qxl[p] = {phi[0] * gx[0], phi[1] * gx[1], phi[2] * gx[2], phi[3] * gx[3]};
+        qyl[p] = {phi[0] * gy[0], phi[1] * gy[1], phi[2] * gy[2], phi[3] * gy[3]};
+    }
+}
+
 // Unsplit Euler flux Jacobian product A_d(U) dU along unit direction d
 // (eq. 2 differentiated by hand): with u_d' = ((dm . d) - u_d drho)/rho and
 // p' = (gamma-1)(dE - u . dm + |u|^2 drho / 2),
@@ -1473,7 +1614,46 @@ static void qgrad_lanes(State& s) {
     s.qsel = cur;
 }
 
+// Tiled passes (LDS-staged neighbours): block = tile, dynamic LDS sized by
+// the cloud's largest tile neighbour list.
+static void qgrad_tiled(State& s) {
+    const Cloud& c = *s.cloud;
+    const dim3 g((unsigned)c.ntile), b(kBlock);
+    const double K = s.prm.limiter_k;
+    const int m = s.prm.inner_iters;
+    const bool lim = s.prm.limiter != 0;
+    const size_t lds0 = (size_t)c.tile_hmax * (sizeof(D4) + sizeof(D2));
+    const size_t lds1 = (size_t)c.tile_hmax * (3 * sizeof(D4) + sizeof(D2));
+    if (m == 0 && lim)
+        hipLaunchKernelGGL((k_qgrad_tiled<false, true>), g, b, lds0, s.stream, c.n, K, c.xy, c.off,
+                           c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom, c.comp, s.active,
+                           s.q, nullptr, nullptr, s.qx[0], s.qy[0], s.qxl, s.qyl);
+    else
+        hipLaunchKernelGGL((k_qgrad_tiled<false, false>), g, b, lds0, s.stream, c.n, K, c.xy,
+                           c.off, c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom, c.comp,
+                           s.active, s.q, nullptr, nullptr, s.qx[0], s.qy[0], nullptr, nullptr);
+    int cur = 0;
+    for (int it = 0; it < m; ++it) {
+        if (it == m - 1 && lim)
+            hipLaunchKernelGGL((k_qgrad_tiled<true, true>), g, b, lds1, s.stream, c.n, K, c.xy,
+                               c.off, c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom, c.comp,
+                               s.active, s.q, s.qx[cur], s.qy[cur], s.qx[1 - cur], s.qy[1 - cur],
+                               s.qxl, s.qyl);
+        else
+            hipLaunchKernelGGL((k_qgrad_tiled<true, false>), g, b, lds1, s.stream, c.n, K, c.xy,
+                               c.off, c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom, c.comp,
+                               s.active, s.q, s.qx[cur], s.qy[cur], s.qx[1 - cur], s.qy[1 - cur],
+                               nullptr, nullptr);
+        cur = 1 - cur;
+    }
+    s.qsel = cur;
+}
+
 hipError_t launch_q_derivatives(State& s) {
+    if (s.cloud->ntile > 0 && s.qgrad_lanes == 4) {
+        qgrad_tiled(s);
+        return hipGetLastError();
+    }
     switch (s.qgrad_lanes) {
         case 1: qgrad_lanes<1>(s); break;
         case 2: qgrad_lanes<2>(s); break;

@@ -25,9 +25,12 @@ MACH, AOA = 0.63, 2.0
 
 
 def rel(a, b):
+    """Largest error per component relative to the component's magnitude,
+    floored at 1e-4 of the field's largest (a smaller component holds only
+    rounding noise)."""
     a, b = np.asarray(a), np.asarray(b)
-    scale = np.abs(b).max()
-    return float(max(np.abs(a[v] - b[v]).max() / (np.abs(b[v]).max() or scale)
+    floor = 1e-4 * np.abs(b).max()
+    return float(max(np.abs(a[v] - b[v]).max() / max(np.abs(b[v]).max(), floor)
                      for v in range(b.shape[0])))
 
 
@@ -75,8 +78,11 @@ def test_far_field_iteration_parity(lk, ff, jvp_mode):
         e = (rel(R, Ro), rel(dU, dUo))
         print(f"kinetic far field mode={jvp_mode} it={it}: R {e[0]:.2e} dU {e[1]:.2e} "
               f"outer |dU| {np.abs(dUo[:, outer]).max():.2e}")
-        # the outer points move: the boundary is not held at the free stream
-        assert np.abs(dUo[:, outer]).max() > 0.0
+        # once the disturbance has reached them the outer points move: the
+        # boundary is not held at the free stream (at the free-stream start
+        # their stencils see uniform flow and their increment is zero)
+        if it > 0:
+            assert np.abs(dUo[:, outer]).max() > 0.0
         assert max(e) < TOL and abs(res - reso) <= TOL * reso
     st.close()
 
