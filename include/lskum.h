@@ -191,6 +191,31 @@ int lskum_state_get_dU(lskum_state* s, double* dU, int on_device);
  * Errors: NONPHYSICAL when a q~ has beta <= 0. */
 int lskum_residual(lskum_state* s, double* R, int on_device, double* res);
 
+/* Allocation-free residual, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the residual of lskum_residual for the flow condition
+ * (mach, aoa_deg) and the parameters' gamma, cfl, inner_iters, limiter,
+ * limiter_k and farfield, on the given cloud, with no state object.
+ *   U    device, [4][n] doubles (SoA), read;
+ *   R    device, [4][n] doubles, written (may be NULL);
+ *   res  device, 2 doubles written: [0] the norm of lskum_residual, [1] 1.0 if
+ *        a non-physical state (rho <= 0, p <= 0, or a q~ with beta <= 0) was
+ *        met, else 0.0.
+ * Every work array lies in a fixed device array of the library (64 MiB per
+ * GPU, held until the process ends), so clouds are limited to
+ * lskum_residual_noalloc_max_points() points; calls on one GPU share it, and
+ * calls that overlap on one GPU (other streams or threads) race.  All work is
+ * enqueued on hip_stream (NULL = the default stream) and nothing is
+ * synchronised; the call allocates nothing, copies nothing between host and
+ * device, and issues no memset (graph capture is allowed).  The first call on
+ * a device looks up the array's device address (HIP symbol lookup).
+ * Errors: ARG (NULL pointer, invalid parameters or flow condition, too many
+ * points, the cloud on another device than the current one), HIP. */
+int lskum_residual_noalloc(const lskum_cloud* c, double mach, double aoa_deg,
+                           const lskum_params* p, const double* U, double* R, double* res,
+                           void* hip_stream);
+int64_t lskum_residual_noalloc_max_points(void);
+
 /* q-derivatives of the current state after the first-order pass and
  * inner_iters inner iterations (eq. 16): qx, qy ([4][n]). */
 int lskum_q_derivatives(lskum_state* s, double* qx, double* qy, int on_device);

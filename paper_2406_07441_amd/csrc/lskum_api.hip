@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -732,6 +733,52 @@ lskum::Params lskum::api_params(const lskum_params* p) { return to_params(p); }
 
 void lskum::api_clear_error() { g_err.clear(); }
 
+// ---------------------------------------------------------------------------
+// Residual without allocation: lskum_residual_noalloc works in `scratch`, a
+// file-scope device array that every GPU holds once, for the life of the
+// process.  Its device address is taken with hipGetSymbolAddress on the first
+// call on each device (the array's name is only a host-side handle); calls on
+// one device share it, so overlapping calls race.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices] = {};
+
+// bytes per point of the scratch layout below, and the fixed part
+constexpr size_t kNoallocPerPoint = 11 * sizeof(lskum::D4) + 2 * sizeof(double);
+constexpr size_t kNoallocFixed = (size_t)1 << 20;
+
+int scratch_ptr(int dev, unsigned char** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) return fail(LSKUM_ERR_ARG, "device index out of range");
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "scratch symbol address");
+        g_scratch[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_scratch[dev];
+    return LSKUM_OK;
+}
+
+// carves 256-byte aligned arrays out of a byte range
+struct Carver {
+    unsigned char* p;
+    template <class T>
+    T* take(size_t count) {
+        T* r = reinterpret_cast<T*>(p);
+        p += (count * sizeof(T) + 255) & ~(size_t)255;
+        return r;
+    }
+};
+
+}  // namespace
+
 extern "C" {
 
 const char* lskum_last_error(void) { return g_err.c_str(); }
@@ -995,6 +1042,88 @@ int lskum_residual(lskum_state* so, double* R, int on_device, double* res) {
     if (int r = read_flags(s, &f)) return r;
     if (res) *res = hres;
     if (f) return fail(LSKUM_ERR_NONPHYSICAL, "non-physical reconstructed state (beta <= 0)");
+    return LSKUM_OK;
+}
+
+int64_t lskum_residual_noalloc_max_points(void) {
+    return (int64_t)((kScratchBytes - kNoallocFixed) / kNoallocPerPoint) - 256;
+}
+
+int lskum_residual_noalloc(const lskum_cloud* cl, double mach, double aoa_deg,
+                           const lskum_params* prm, const double* U, double* R, double* res,
+                           void* hip_stream) {
+    g_err.clear();
+    if (!cl || !U || !res) return fail(LSKUM_ERR_ARG, "NULL argument");
+    if (int st = check_params(prm)) return st;
+    if (!(mach > 0.0) || !std::isfinite(aoa_deg)) return fail(LSKUM_ERR_ARG, "invalid flow condition");
+    const lskum::Cloud& c = cl->c;
+    if (prm->farfield && !c.outer_frames) return fail(LSKUM_ERR_ARG, kNoOuterFrame);
+    if (c.n > lskum_residual_noalloc_max_points())
+        return fail(LSKUM_ERR_ARG, "cloud has " + std::to_string(c.n) +
+                                       " points, more than the allocation-free residual's "
+                                       "scratch holds (" +
+                                       std::to_string(lskum_residual_noalloc_max_points()) + ")");
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != c.device) return fail(LSKUM_ERR_ARG, "the cloud lives on another device");
+    unsigned char* base = nullptr;
+    if (int r = scratch_ptr(dev, &base)) return r;
+
+    // a state whose every array lies in scratch: fp64 arithmetic, the
+    // Anandhanarayanan variant (R does not depend on either)
+    lskum::State s;
+    s.cloud = &c;
+    s.prm = to_params(prm);
+    s.prm.precision = 0;
+    s.prm.variant = 0;
+    s.prm.scheme = 0;
+    apply_lanes(s);
+    s.stream = (hipStream_t)hip_stream;
+    const int64_t n = c.n;
+    const int nc = c.ncomp;
+    Carver cv{base};
+    s.U = cv.take<lskum::D4>(n);
+    s.q = cv.take<lskum::D4>(n);
+    for (int k = 0; k < 2; ++k) {
+        s.qx[k] = cv.take<lskum::D4>(n);
+        s.qy[k] = cv.take<lskum::D4>(n);
+    }
+    s.qxl = cv.take<lskum::D4>(n);
+    s.qyl = cv.take<lskum::D4>(n);
+    s.R = cv.take<lskum::D4>(n);
+    s.jv0 = cv.take<lskum::D4>(n);
+    s.jv2 = cv.take<lskum::D4>(n);
+    s.D = cv.take<double>(n);
+    s.rr = cv.take<double>(n);
+    s.partial = cv.take<double>(c.nchunk);
+    s.res_hist = cv.take<double>(nc);
+    s.res_last = cv.take<double>(nc);
+    s.tol_abs = cv.take<double>(nc);
+    s.cfl = cv.take<double>(nc);
+    s.vinf = cv.take<double>(2 * nc);
+    s.flags = cv.take<int32_t>(4);
+    s.active = cv.take<int32_t>(nc);
+    s.status = cv.take<int32_t>(nc);
+    s.iters = cv.take<int32_t>(nc);
+    if ((size_t)(cv.p - base) > kScratchBytes)
+        return fail(LSKUM_ERR_ARG, "cloud too large for the allocation-free residual");
+    const double a = aoa_deg * kPi / 180.0;
+    // per-condition values by fill kernels (no memset and no host copy)
+    HIPCHK(lskum::launch_fill(s.cfl, nc, s.prm.cfl, s.stream));
+    HIPCHK(lskum::launch_fill(s.tol_abs, nc, 0.0, s.stream));
+    for (int k = 0; k < nc; ++k) {
+        HIPCHK(lskum::launch_fill(s.vinf + 2 * k, 1, mach * std::cos(a), s.stream));
+        HIPCHK(lskum::launch_fill(s.vinf + 2 * k + 1, 1, mach * std::sin(a), s.stream));
+    }
+    HIPCHK(lskum::launch_clear_flags(s.flags, s.stream));
+    HIPCHK(lskum::launch_reset_components(s));
+    HIPCHK(lskum::launch_soa_to_aos(U, s.U, n, s.stream));
+    HIPCHK(lskum::launch_q_from_U(s));
+    HIPCHK(lskum::launch_q_derivatives(s));
+    HIPCHK(lskum::launch_residual(s, 0));
+    HIPCHK(lskum::launch_norm(s, 0));
+    if (R) HIPCHK(lskum::launch_aos_to_soa(s.R, R, n, s.stream));
+    HIPCHK(lskum::launch_residual_out(s.res_hist, s.flags, res, s.stream));
     return LSKUM_OK;
 }
 

@@ -1915,6 +1915,20 @@ hipError_t launch_fill(double* p, int n, double v, hipStream_t st) {
     return hipGetLastError();
 }
 
+__global__ void k_residual_out(const double* __restrict__ res, const int32_t* __restrict__ flags,
+                               double* __restrict__ out) {
+    if (threadIdx.x == 0) {
+        out[0] = res[0];
+        out[1] = flags[0] ? 1.0 : 0.0;
+    }
+}
+
+hipError_t launch_residual_out(const double* res, const int32_t* flags, double* out,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_residual_out, dim3(1), dim3(64), 0, st, res, flags, out);
+    return hipGetLastError();
+}
+
 __global__ void k_copy_flag(const int32_t* __restrict__ src, int32_t* __restrict__ dst) {
     if (threadIdx.x == 0) dst[0] = src[0];
 }

@@ -252,6 +252,9 @@ hipError_t reset_cfl(State& s);
 // records no memset node)
 hipError_t launch_fill(double* p, int n, double v, hipStream_t st);
 hipError_t launch_copy_flag(const int32_t* src, int32_t* dst, hipStream_t st);
+// out[0] = res[0], out[1] = 1 if flags[0] is set else 0
+hipError_t launch_residual_out(const double* res, const int32_t* flags, double* out,
+                               hipStream_t st);
 
 // Error reporting shared by the C-ABI source files: records msg for
 // lskum_last_error() and returns code.

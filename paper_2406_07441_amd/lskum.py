@@ -104,6 +104,9 @@ _SIGS = {
     "lskum_batch_features": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lskum_mlp_warm_start": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lskum_mlp_warm_start_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lskum_residual_noalloc": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lskum_residual_noalloc_max_points": (C.c_int64, []),
     "lskum_last_error": (C.c_char_p, []),
     "lskum_build_hash": (C.c_char_p, []),
 }
@@ -184,6 +187,24 @@ class Cloud:
             self.close()
         except Exception:
             pass
+
+
+def residual_noalloc(cloud: Cloud, mach: float, aoa_deg: float, params: Params, U, R, res,
+                     stream=None):
+    """lskum_residual_noalloc: U ([4][n] float64 device tensor) -> R (same
+    shape, or None) and res (2 float64 on the device: the norm, and 1.0 if a
+    non-physical state was met).  Enqueued on `stream` (torch stream or raw
+    handle; None = the default stream); nothing is synchronised."""
+    handle = None
+    if stream is not None:
+        handle = stream if isinstance(stream, int) else stream.cuda_stream
+    _check(lib().lskum_residual_noalloc(cloud.h, float(mach), float(aoa_deg), C.byref(params),
+                                        U.data_ptr(), None if R is None else R.data_ptr(),
+                                        res.data_ptr(), handle))
+
+
+def residual_noalloc_max_points() -> int:
+    return int(lib().lskum_residual_noalloc_max_points())
 
 
 class State:
