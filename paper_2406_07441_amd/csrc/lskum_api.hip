@@ -376,14 +376,11 @@ void free_state(lskum::State& s) {
         for (hipEvent_t ev : s.ev) (void)hipEventDestroy(ev);
     void* ptrs[] = {s.U,    s.q,      s.qx[0], s.qx[1],  s.qy[0],   s.qy[1],    s.qxl, s.Rs,
                     s.qyl,  s.R,      s.dU,    s.jv0,    s.jv2,      s.D,
-                    s.jv0f, s.jv2f,  s.dUf,    s.Df,      s.rr,       s.fsum, s.partial, s.Pr, s.Prf,
+                    s.jv0f, s.jv2f,  s.dUf,    s.Df,      s.rr,       s.fsum, s.partial,
                     s.res_hist, s.flags, s.active, s.status, s.iters, s.res_last, s.tol_abs, s.cfl,
                     s.vinf};
     for (void* p : ptrs) (void)hipFree(p);
     if (s.own_stream && s.stream) (void)hipStreamDestroy(s.stream);
-    if (s.side) (void)hipStreamDestroy(s.side);
-    if (s.fork_ev) (void)hipEventDestroy(s.fork_ev);
-    if (s.join_ev) (void)hipEventDestroy(s.join_ev);
     s = lskum::State{};
 }
 
@@ -502,9 +499,6 @@ int init_state(lskum::State& s, const lskum::Cloud& c, const lskum_params* prm,
         HIPCHK(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
         s.own_stream = true;
     }
-    HIPCHK(hipStreamCreateWithFlags(&s.side, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&s.fork_ev, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&s.join_ev, hipEventDisableTiming));
     const int64_t n = c.n;
     const int nc = c.ncomp;
     s.res_cap = 4096;
@@ -530,8 +524,6 @@ int init_state(lskum::State& s, const lskum::Cloud& c, const lskum_params* prm,
     chk(dalloc(&s.jv2f, n));
     chk(dalloc(&s.dUf, n));
     chk(dalloc(&s.Df, n));
-    chk(dalloc(&s.Pr, 4 * n));
-    chk(dalloc(&s.Prf, 4 * n));
     chk(dalloc(&s.rr, n));
     chk(dalloc(&s.fsum, 2 * nc));
     chk(dalloc(&s.partial, c.nchunk));

@@ -627,142 +627,6 @@ __device__ __forceinline__ void unsplit_jvp(const D4& u, const double dv[4], dou
     J[3] = (dv[3] + pd) * ud + (u.w + p) * udd;
 }
 
-// ---------------------------------------------------------------------------
-// Split-flux Jacobian-vector products for the sweeps.
-// ---------------------------------------------------------------------------
-template <class T>
-struct Lin {  // linearisation data of one neighbour
-    T rho, u1, u2, p, sb, beta, irho, ip;
-};
-
-// Tangent of the split flux along unit direction (dx, dy) with sign sg,
-// given erf(S) and exp(-S^2) at the linearisation state.  Hand-written
-// forward-mode derivative of the closed-form split flux (the paper's exact
-// Jacobian-vector product): with rho', u', p' from dU,
-//   beta' = (rho' - 2 beta p')/(2p),  S' = u_d' sqrt(beta) + u_d beta'/(2 sqrt(beta)),
-//   A' = sg exp(-S^2) S'/sqrt(pi),    B' = B (-2 S S' - beta'/(2 beta)),
-// and the product rule on each flux component.
-template <class T>
-__device__ __forceinline__ void jvp_exact(const Lin<T>& L, T er, T g, T dx, T dy, T sg,
-                                          const T dU[4], T gm1, T inv_gm1, T J[4]) {
-    const T rd = dU[0];
-    const T u1d = (dU[1] - L.u1 * rd) * L.irho;
-    const T u2d = (dU[2] - L.u2 * rd) * L.irho;
-    const T usq = L.u1 * L.u1 + L.u2 * L.u2;
-    const T pd = gm1 * (dU[3] - T(0.5) * rd * usq - L.rho * (L.u1 * u1d + L.u2 * u2d));
-    const T bd = (rd - T(2) * L.beta * pd) * (T(0.5) * L.ip);
-    const T ud = L.u1 * dx + L.u2 * dy;
-    const T udd = u1d * dx + u2d * dy;
-    const T isb = L.sb / L.beta;  // 1/sqrt(beta)
-    const T S = ud * L.sb;
-    const T Sd = udd * L.sb + T(0.5) * ud * bd * isb;
-    const T A = T(0.5) * (T(1) + sg * er);
-    const T Ad = sg * g * Sd * T(kInvSqrtPi);
-    const T B = g * T(0.5 * kInvSqrtPi) * isb;
-    const T Bd = B * (T(-2) * S * Sd - T(0.5) * bd / L.beta);
-    const T F = ud * A + sg * B;
-    const T Fd = udd * A + ud * Ad + sg * Bd;
-    const T rhoE = L.p * inv_gm1 + T(0.5) * L.rho * usq;
-    const T J0 = rd * F + L.rho * Fd;
-    const T mass = L.rho * F;
-    const T pAd = pd * A + L.p * Ad;
-    J[0] = J0;
-    J[1] = pAd * dx + u1d * mass + L.u1 * J0;
-    J[2] = pAd * dy + u2d * mass + L.u2 * J0;
-    J[3] = (dU[3] + pd) * ud * A + (rhoE + L.p) * (udd * A + ud * Ad) +
-           sg * ((dU[3] + T(0.5) * pd) * B + (rhoE + T(0.5) * L.p) * Bd);
-}
-
-// Split flux from the linearisation data (value only, used by the
-// flux-difference products).
-__device__ __forceinline__ void flux_lin(const Lin<double>& L, double er, double g, double dx,
-                                         double dy, double sg, double inv_gm1, double G[4]) {
-    const double ud = L.u1 * dx + L.u2 * dy;
-    const double A = 0.5 * (1.0 + sg * er);
-    const double B = g * (0.5 * kInvSqrtPi) / L.sb;
-    const double rhoE = L.p * inv_gm1 + 0.5 * L.rho * (L.u1 * L.u1 + L.u2 * L.u2);
-    const double mass = L.rho * (ud * A + sg * B);
-    G[0] = mass;
-    G[1] = L.p * A * dx + L.u1 * mass;
-    G[2] = L.p * A * dy + L.u2 * mass;
-    G[3] = (rhoE + L.p) * ud * A + sg * (rhoE + 0.5 * L.p) * B;
-}
-
-// Flux difference G(U + dU) - G(U) of eq. (28).
-__device__ __forceinline__ void jvp_fluxdiff(const Lin<double>& L, double er, double g, const D4& u,
-                                             double dx, double dy, double sg, const double dU[4],
-                                             double gamma, double inv_gm1, double J[4]) {
-    const double a0 = u.x + dU[0], a1 = u.y + dU[1], a2 = u.z + dU[2], a3 = u.w + dU[3];
-    Lin<double> W;
-    W.rho = a0;
-    W.irho = 1.0 / a0;
-    W.u1 = a1 * W.irho;
-    W.u2 = a2 * W.irho;
-    W.p = (gamma - 1.0) * (a3 - 0.5 * W.rho * (W.u1 * W.u1 + W.u2 * W.u2));
-    W.beta = 0.5 * W.rho / W.p;
-    W.sb = sqrt(W.beta);
-    const double S = (W.u1 * dx + W.u2 * dy) * W.sb;
-    double Ga[4], Gb[4];
-    flux_lin(W, erf(S), exp(-(S * S)), dx, dy, sg, inv_gm1, Ga);
-    flux_lin(L, er, g, dx, dy, sg, inv_gm1, Gb);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) J[v] = Ga[v] - Gb[v];
-}
-
-// The linearisation data of neighbour i from its (rho, u1, u2, p) record: the
-// derived quantities are formed here rather than read, which halves the bytes
-// a sweep gathers per neighbour for them.
-// One reciprocal, of rho p, gives both 1/rho and 1/p; the fp32 sweeps use
-// the hardware reciprocal and square root (about 1 ulp).
-template <class T>
-__device__ __forceinline__ Lin<T> lin_of(const Vec4<T>& a) {
-    T r, sb;
-    if constexpr (std::is_same_v<T, float>) {
-        r = __builtin_amdgcn_rcpf(a.x * a.w);
-    } else {
-        r = T(1) / (a.x * a.w);
-    }
-    const T irho = a.w * r, ip = a.x * r;
-    const T beta = T(0.5) * a.x * ip;
-    if constexpr (std::is_same_v<T, float>) {
-        sb = __builtin_amdgcn_sqrtf(beta);
-    } else {
-        sb = sqrt(beta);
-    }
-    return Lin<T>{a.x, a.y, a.z, a.w, sb, beta, irho, ip};
-}
-
-template <class T>
-__device__ __forceinline__ Lin<T> load_lin(const Vec4<T>* jv0, int32_t i) {
-    return lin_of(jv0[i]);
-}
-
-// Split-flux products of a point at its own state, P_k = A_k(U) dU, for the
-// four splits of the x/y frame: k = 0 x (G+), 1 x (G-), 2 y (G+), 3 y (G-).
-// An interior neighbour of a point reads the product of the split it lies in
-// (sign from its side), so each point's products are formed once, when its
-// increment is final, instead of once per (point, neighbour) pair.  MODE 0
-// exact tangent, 1 flux difference; erf/exp of S in x and y come from k2.
-template <class T, int MODE>
-__device__ __forceinline__ void split_product(int k, const Lin<T>& L, const Vec4<T>& k2,
-                                              const D4& u, const T dv[4], double gamma,
-                                              T J[4]) {
-    const bool ydir = k >= 2;
-    const T sg = (k & 1) ? T(-1) : T(1);
-    const T er = ydir ? k2.z : k2.x, g = ydir ? k2.w : k2.y;
-    const T dx = ydir ? T(0) : T(1), dy = ydir ? T(1) : T(0);
-    if constexpr (MODE == 1) {
-        jvp_fluxdiff(L, er, g, u, dx, dy, sg, dv, gamma, 1.0 / (gamma - 1.0), J);
-    } else {
-        jvp_exact<T>(L, er, g, dx, dy, sg, dv, T(gamma - 1.0), T(1.0 / (gamma - 1.0)), J);
-    }
-}
-
-// Index of the product an interior point reads for a list entry's split:
-// a neighbour on the negative side of the split direction enters G+.
-__device__ __forceinline__ int product_a(uint8_t cd) { return (cd & kSwNegA) ? 0 : 1; }
-__device__ __forceinline__ int product_b(uint8_t cd) { return (cd & kSwNegB) ? 2 : 3; }
-
 // Neighbour data of one stencil pair of the residual.
 struct Nbr {
     D2 r;
@@ -845,7 +709,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(
     float* __restrict__ Df,
     double* __restrict__ rr_out, int32_t* __restrict__ flags, int variant, int fd,
     D4* dUio, F4* dUfio, D4* __restrict__ Rs, const int32_t* __restrict__ colour, int sweep0,
-    int farfield, const double* __restrict__ vinf, D4* __restrict__ Pr, F4* __restrict__ Prf) {
+    int farfield, const double* __restrict__ vinf) {
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t gt = (int64_t)lb * blockDim.x + threadIdx.x;
     const int64_t p = gt / LANES;
@@ -1050,15 +914,6 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                         }
                     }
                     dUfio[p] = {o[0], o[1], o[2], o[3]};
-                    // the point's split products, from its fp32 records as a sweep forms them
-                    const F4 a0 = {(float)j0.x, (float)j0.y, (float)j0.z, (float)j0.w};
-                    const F4 k2 = {(float)j2.x, (float)j2.y, (float)j2.z, (float)j2.w};
-                    const Lin<float> L = lin_of(a0);
-                    for (int k = 0; k < 4; ++k) {
-                        float J[4];
-                        split_product<float, 0>(k, L, k2, u, o, gamma, J);
-                        Prf[4 * p + k] = {J[0], J[1], J[2], J[3]};
-                    }
                 } else {
                     double o[4] = {0, 0, 0, 0};
                     if (part) {
@@ -1073,15 +928,6 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                         }
                     }
                     dUio[p] = {o[0], o[1], o[2], o[3]};
-                    const Lin<double> L = lin_of(j0);
-                    for (int k = 0; k < 4; ++k) {
-                        double J[4];
-                        if (fd)
-                            split_product<double, 1>(k, L, j2, u, o, gamma, J);
-                        else
-                            split_product<double, 0>(k, L, j2, u, o, gamma, J);
-                        Pr[4 * p + k] = {J[0], J[1], J[2], J[3]};
-                    }
                 }
             }
             if (bad || !(rho > 0.0) || !(pr > 0.0)) flags[0] = 1;
@@ -1152,6 +998,112 @@ __global__ void k_reset_components(int ncomp, int32_t* __restrict__ active,
     iters[k] = 0;
 }
 
+// ---------------------------------------------------------------------------
+// Split-flux Jacobian-vector products for the sweeps.
+// ---------------------------------------------------------------------------
+template <class T>
+struct Lin {  // linearisation data of one neighbour
+    T rho, u1, u2, p, sb, beta, irho, ip;
+};
+
+// Tangent of the split flux along unit direction (dx, dy) with sign sg,
+// given erf(S) and exp(-S^2) at the linearisation state.  Hand-written
+// forward-mode derivative of the closed-form split flux (the paper's exact
+// Jacobian-vector product): with rho', u', p' from dU,
+//   beta' = (rho' - 2 beta p')/(2p),  S' = u_d' sqrt(beta) + u_d beta'/(2 sqrt(beta)),
+//   A' = sg exp(-S^2) S'/sqrt(pi),    B' = B (-2 S S' - beta'/(2 beta)),
+// and the product rule on each flux component.
+template <class T>
+__device__ __forceinline__ void jvp_exact(const Lin<T>& L, T er, T g, T dx, T dy, T sg,
+                                          const T dU[4], T gm1, T inv_gm1, T J[4]) {
+    const T rd = dU[0];
+    const T u1d = (dU[1] - L.u1 * rd) * L.irho;
+    const T u2d = (dU[2] - L.u2 * rd) * L.irho;
+    const T usq = L.u1 * L.u1 + L.u2 * L.u2;
+    const T pd = gm1 * (dU[3] - T(0.5) * rd * usq - L.rho * (L.u1 * u1d + L.u2 * u2d));
+    const T bd = (rd - T(2) * L.beta * pd) * (T(0.5) * L.ip);
+    const T ud = L.u1 * dx + L.u2 * dy;
+    const T udd = u1d * dx + u2d * dy;
+    const T isb = L.sb / L.beta;  // 1/sqrt(beta)
+    const T S = ud * L.sb;
+    const T Sd = udd * L.sb + T(0.5) * ud * bd * isb;
+    const T A = T(0.5) * (T(1) + sg * er);
+    const T Ad = sg * g * Sd * T(kInvSqrtPi);
+    const T B = g * T(0.5 * kInvSqrtPi) * isb;
+    const T Bd = B * (T(-2) * S * Sd - T(0.5) * bd / L.beta);
+    const T F = ud * A + sg * B;
+    const T Fd = udd * A + ud * Ad + sg * Bd;
+    const T rhoE = L.p * inv_gm1 + T(0.5) * L.rho * usq;
+    const T J0 = rd * F + L.rho * Fd;
+    const T mass = L.rho * F;
+    const T pAd = pd * A + L.p * Ad;
+    J[0] = J0;
+    J[1] = pAd * dx + u1d * mass + L.u1 * J0;
+    J[2] = pAd * dy + u2d * mass + L.u2 * J0;
+    J[3] = (dU[3] + pd) * ud * A + (rhoE + L.p) * (udd * A + ud * Ad) +
+           sg * ((dU[3] + T(0.5) * pd) * B + (rhoE + T(0.5) * L.p) * Bd);
+}
+
+// Split flux from the linearisation data (value only, used by the
+// flux-difference products).
+__device__ __forceinline__ void flux_lin(const Lin<double>& L, double er, double g, double dx,
+                                         double dy, double sg, double inv_gm1, double G[4]) {
+    const double ud = L.u1 * dx + L.u2 * dy;
+    const double A = 0.5 * (1.0 + sg * er);
+    const double B = g * (0.5 * kInvSqrtPi) / L.sb;
+    const double rhoE = L.p * inv_gm1 + 0.5 * L.rho * (L.u1 * L.u1 + L.u2 * L.u2);
+    const double mass = L.rho * (ud * A + sg * B);
+    G[0] = mass;
+    G[1] = L.p * A * dx + L.u1 * mass;
+    G[2] = L.p * A * dy + L.u2 * mass;
+    G[3] = (rhoE + L.p) * ud * A + sg * (rhoE + 0.5 * L.p) * B;
+}
+
+// Flux difference G(U + dU) - G(U) of eq. (28).
+__device__ __forceinline__ void jvp_fluxdiff(const Lin<double>& L, double er, double g, const D4& u,
+                                             double dx, double dy, double sg, const double dU[4],
+                                             double gamma, double inv_gm1, double J[4]) {
+    const double a0 = u.x + dU[0], a1 = u.y + dU[1], a2 = u.z + dU[2], a3 = u.w + dU[3];
+    Lin<double> W;
+    W.rho = a0;
+    W.irho = 1.0 / a0;
+    W.u1 = a1 * W.irho;
+    W.u2 = a2 * W.irho;
+    W.p = (gamma - 1.0) * (a3 - 0.5 * W.rho * (W.u1 * W.u1 + W.u2 * W.u2));
+    W.beta = 0.5 * W.rho / W.p;
+    W.sb = sqrt(W.beta);
+    const double S = (W.u1 * dx + W.u2 * dy) * W.sb;
+    double Ga[4], Gb[4];
+    flux_lin(W, erf(S), exp(-(S * S)), dx, dy, sg, inv_gm1, Ga);
+    flux_lin(L, er, g, dx, dy, sg, inv_gm1, Gb);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) J[v] = Ga[v] - Gb[v];
+}
+
+// The linearisation data of neighbour i from its (rho, u1, u2, p) record: the
+// derived quantities are formed here rather than read, which halves the bytes
+// a sweep gathers per neighbour for them.
+// One reciprocal, of rho p, gives both 1/rho and 1/p; the fp32 sweeps use
+// the hardware reciprocal and square root (about 1 ulp).
+template <class T>
+__device__ __forceinline__ Lin<T> load_lin(const Vec4<T>* jv0, int32_t i) {
+    const Vec4<T> a = jv0[i];
+    T r, sb;
+    if constexpr (std::is_same_v<T, float>) {
+        r = __builtin_amdgcn_rcpf(a.x * a.w);
+    } else {
+        r = T(1) / (a.x * a.w);
+    }
+    const T irho = a.w * r, ip = a.x * r;
+    const T beta = T(0.5) * a.x * ip;
+    if constexpr (std::is_same_v<T, float>) {
+        sb = __builtin_amdgcn_sqrtf(beta);
+    } else {
+        sb = sqrt(beta);
+    }
+    return Lin<T>{a.x, a.y, a.z, a.w, sb, beta, irho, ip};
+}
+
 // Split weights and bits of the sweep-list entries of the colour-sorted point
 // q (thread per q): for interior points the x split (a) and y split (b) the
 // neighbour falls in; for frame points the t split (a) and the normal split
@@ -1212,88 +1164,74 @@ __global__ void __launch_bounds__(kBlock) k_sweep_weights(int64_t n,
 }
 
 // Contribution sum_k w_i^k A_k(U_i) dU_i of neighbour i to point p's sweep
-// sum (eq. 22-27) from the entry's weights and split bits.  Interior points
-// use the x and y split the neighbour falls in and read the neighbour's own
-// products (split_product).  Frame points use the t split and the normal split
-// (n- at a wall, n+ at a far-field outer point) in the frame t of point p, so
-// their products are formed here, with erf/exp at the neighbour's state.
-template <class T, int MODE, bool FRAME>
+// sum (eq. 22-27) from the entry's weights and split bits: interior points
+// use the x and y split the neighbour falls in, frame points the t split and
+// the normal split (n- at a wall, n+ at a far-field outer point) in the frame
+// t of point p.
+template <class T, int MODE>
 __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<T>& w, int32_t i,
                                               const Vec4<T>* __restrict__ jv0,
-                                              const Vec4<T>* __restrict__ Pr,
+                                              const Vec4<T>* __restrict__ jv2,
                                               const D4* __restrict__ U,
                                               const Vec4<T>* __restrict__ dU, double gamma,
                                               T acc[4]) {
-    if (!(cd & kSwWall)) {
-        if (cd & kSwA) {
-            const Vec4<T> P = Pr[4 * (int64_t)i + product_a(cd)];
-            const T wa = T(w.x);
-            acc[0] += wa * P.x;
-            acc[1] += wa * P.y;
-            acc[2] += wa * P.z;
-            acc[3] += wa * P.w;
-        }
-        if (cd & kSwB) {
-            const Vec4<T> P = Pr[4 * (int64_t)i + product_b(cd)];
-            const T wb = T(w.y);
-            acc[0] += wb * P.x;
-            acc[1] += wb * P.y;
-            acc[2] += wb * P.z;
-            acc[3] += wb * P.w;
-        }
-        return;
-    }
-    if constexpr (!FRAME) return;
     const T gm1 = T(gamma - 1.0), inv_gm1 = T(1.0 / (gamma - 1.0));
     const Vec4<T> di = dU[i];
     const T dv[4] = {di.x, di.y, di.z, di.w};
     const Lin<T> L = load_lin(jv0, i);
+    const Vec4<T> k2 = jv2[i];  // interior entries only; loaded with the rest
     T J[4];
-    if (cd & kSwA) {
-        const double sg = (cd & kSwNegA) ? 1.0 : -1.0;
-        if constexpr (MODE == 1) {
-            const double S = (L.u1 * t.x + L.u2 * t.y) * L.sb;
-            jvp_fluxdiff(L, erf(S), exp(-(S * S)), U[i], t.x, t.y, sg, dv, gamma,
-                         1.0 / (gamma - 1.0), J);
-        } else {
-            const T S = (L.u1 * T(t.x) + L.u2 * T(t.y)) * L.sb;
-            jvp_exact<T>(L, erf(S), exp(-(S * S)), T(t.x), T(t.y), T(sg), dv, gm1, inv_gm1, J);
+    if (cd & kSwWall) {
+        // wall-frame directions: erf/exp at the neighbour state are formed here
+        if (cd & kSwA) {
+            const double sg = (cd & kSwNegA) ? 1.0 : -1.0;
+            if constexpr (MODE == 1) {
+                const double S = (L.u1 * t.x + L.u2 * t.y) * L.sb;
+                jvp_fluxdiff(L, erf(S), exp(-(S * S)), U[i], t.x, t.y, sg, dv, gamma,
+                             1.0 / (gamma - 1.0), J);
+            } else {
+                const T S = (L.u1 * T(t.x) + L.u2 * T(t.y)) * L.sb;
+                jvp_exact<T>(L, erf(S), exp(-(S * S)), T(t.x), T(t.y), T(sg), dv, gm1, inv_gm1, J);
+            }
+            const T wa = T(w.x);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += wa * J[v];
         }
+        if (cd & kSwB) {
+            const double sg = (cd & kSwNegB) ? 1.0 : -1.0;
+            if constexpr (MODE == 1) {
+                const double S = (-L.u1 * t.y + L.u2 * t.x) * L.sb;
+                jvp_fluxdiff(L, erf(S), exp(-(S * S)), U[i], -t.y, t.x, sg, dv, gamma,
+                             1.0 / (gamma - 1.0), J);
+            } else {
+                const T S = (-L.u1 * T(t.y) + L.u2 * T(t.x)) * L.sb;
+                jvp_exact<T>(L, erf(S), exp(-(S * S)), T(-t.y), T(t.x), T(sg), dv, gm1, inv_gm1, J);
+            }
+            const T wb = T(w.y);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += wb * J[v];
+        }
+        return;
+    }
+    if (cd & kSwA) {
+        const T sg = (cd & kSwNegA) ? T(1) : T(-1);
+        if constexpr (MODE == 1)
+            jvp_fluxdiff(L, k2.x, k2.y, U[i], 1.0, 0.0, sg, dv, gamma, 1.0 / (gamma - 1.0), J);
+        else
+            jvp_exact<T>(L, k2.x, k2.y, T(1), T(0), sg, dv, gm1, inv_gm1, J);
         const T wa = T(w.x);
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] += wa * J[v];
     }
     if (cd & kSwB) {
-        const double sg = (cd & kSwNegB) ? 1.0 : -1.0;
-        if constexpr (MODE == 1) {
-            const double S = (-L.u1 * t.y + L.u2 * t.x) * L.sb;
-            jvp_fluxdiff(L, erf(S), exp(-(S * S)), U[i], -t.y, t.x, sg, dv, gamma,
-                         1.0 / (gamma - 1.0), J);
-        } else {
-            const T S = (-L.u1 * T(t.y) + L.u2 * T(t.x)) * L.sb;
-            jvp_exact<T>(L, erf(S), exp(-(S * S)), T(-t.y), T(t.x), T(sg), dv, gm1, inv_gm1, J);
-        }
+        const T sg = (cd & kSwNegB) ? T(1) : T(-1);
+        if constexpr (MODE == 1)
+            jvp_fluxdiff(L, k2.z, k2.w, U[i], 0.0, 1.0, sg, dv, gamma, 1.0 / (gamma - 1.0), J);
+        else
+            jvp_exact<T>(L, k2.z, k2.w, T(0), T(1), sg, dv, gm1, inv_gm1, J);
         const T wb = T(w.y);
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] += wb * J[v];
-    }
-}
-
-// The four products of point p (split_product) from its final increment,
-// written as one 4-record row: with LANES >= 4 lane k forms product k, with
-// fewer lanes each lane forms every LANES-th one.
-template <class T, int MODE, int LANES>
-__device__ __forceinline__ void write_products(int lane, int64_t p, const Lin<T>& L,
-                                               const Vec4<T>& k2, const D4& u, const T out[4],
-                                               double gamma, Vec4<T>* __restrict__ Pr) {
-#pragma unroll
-    for (int k0 = 0; k0 < 4; k0 += LANES) {
-        const int k = k0 + lane;
-        if (k < 4) {
-            T J[4];
-            split_product<T, MODE>(k, L, k2, u, out, gamma, J);
-            Pr[4 * p + k] = {J[0], J[1], J[2], J[3]};
-        }
     }
 }
 
@@ -1302,42 +1240,33 @@ __device__ __forceinline__ void write_products(int lane, int64_t p, const Lin<T>
 // 1 flux difference.  T is the arithmetic of the products and increments.
 // LANES consecutive lanes share one point: each walks every LANES-th entry of
 // the point's lower (forward) or upper (backward) list, and the partial sums
-// are combined with a cross-lane butterfly (every lane ends with the same,
-// bitwise identical sum).  The phase's points are colour-sorted positions,
-// their lists contiguous: [a0, a0 + n0) followed by [a1, a1 + n1).
-// FRAME kernels take the frame points (wall, and outer points under the
-// kinetic far field), whose products are formed per entry with erf/exp at
-// the neighbour; the others take interior points (and outer points held at
-// the free stream), which only read their neighbours' products -- the two
-// kinds run as separate kernels so that the light interior one is not held
-// to the register budget of the frame one.  With PRODUCE the point's split
-// products (split_product) follow its increment into Pr, for the later
-// phases whose points have it as an interior neighbour.
-template <class T, bool FWD, int MODE, int LANES, bool FRAME>
+// are combined with cross-lane shuffles.  The phase's points are the
+// colour-sorted positions [start, start + count) and their lists one
+// contiguous block.
+template <class T, bool FWD, int MODE, int LANES>
 __global__ void __launch_bounds__(kBlock) k_sweep(
-    int32_t a0, int32_t n0, int32_t a1, int32_t n1, const int32_t* __restrict__ col_perm,
+    int32_t start, int32_t count, const int32_t* __restrict__ col_perm,
     const D2* __restrict__ frame, const int8_t* __restrict__ type,
     const int32_t* __restrict__ loff, const int32_t* __restrict__ lidx,
     const W2<T>* __restrict__ lw, const uint8_t* __restrict__ lcode,
     const int32_t* __restrict__ comp, const int32_t* __restrict__ active,
     const Vec4<T>* __restrict__ jv0, const Vec4<T>* __restrict__ jv2,
     const D4* __restrict__ U, const D4* __restrict__ R,
-    const T* __restrict__ Dg, Vec4<T>* __restrict__ dU, Vec4<T>* __restrict__ Pr,
-    double gamma, int farfield, int produce) {
+    const T* __restrict__ Dg, Vec4<T>* __restrict__ dU, double gamma, int farfield) {
     const int gt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int pt = gt / LANES, lane = gt % LANES;
-    if (pt >= n0 + n1) return;  // uniform over the lanes of a point
+    if (pt >= count) return;  // uniform over the lanes of a point
     // A phase is short and latency-bound, so its loads are ordered to form as
     // few dependent levels as possible: q-indexed offsets and permutation;
-    // then the point's own records and the list entries together; then the
-    // neighbours' products.  Nothing waits on the point type before the list
-    // walk (an outer point's sums are formed and discarded).
-    const int32_t q = pt < n0 ? a0 + pt : a1 + (pt - n0);
+    // then the point's own record and the list entries together; then the
+    // neighbours' data.  Nothing waits on the point type before the list walk
+    // (an outer point's products are formed and discarded).
+    const int32_t q = start + pt;
     const int32_t p = col_perm[q];
     const int32_t e0 = loff[q], e1 = loff[q + 1];
     if (comp && !active[comp[p]]) return;  // retired component of a batch (uniform per point)
     if (!comp && !active[0]) return;
-    // the lane's first list entry, requested before the point's own records
+    // the lane's first list entry, requested before the point's own record
     int32_t e = e0 + lane;
     uint8_t cd = 0;
     W2<T> w = {T(0), T(0)};
@@ -1348,23 +1277,17 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
         i = lidx[e];
     }
     const int8_t ty = type[p];
-    const D2 t = FRAME ? frame[p] : D2{1.0, 0.0};
-    // every lane loads the point's own records (one address per point): all
-    // lanes finish the point, and the product lanes need its linearisation
-    const T dg = Dg[p];
-    Vec4<T> own;
-    if (FWD) {
-        const D4 r = R[p];
-        own = {T(r.x), T(r.y), T(r.z), T(r.w)};
-    } else {
-        own = dU[p];
-    }
-    Vec4<T> lin0 = {T(0), T(0), T(0), T(0)}, k2 = lin0;
-    D4 u = {0.0, 0.0, 0.0, 0.0};
-    if (produce && lane < 4) {
-        lin0 = jv0[p];
-        k2 = jv2[p];
-        if (MODE == 1) u = U[p];
+    const D2 t = frame[p];
+    T dg = T(1);
+    Vec4<T> own = {T(0), T(0), T(0), T(0)};
+    if (lane == 0) {  // used after the list walk; the division waits until then
+        dg = Dg[p];
+        if (FWD) {
+            const D4 r = R[p];
+            own = {T(r.x), T(r.y), T(r.z), T(r.w)};
+        } else {
+            own = dU[p];
+        }
     }
     T acc[4] = {T(0), T(0), T(0), T(0)};
     while (e < e1) {
@@ -1375,7 +1298,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
         const uint8_t cdn = lcode[ec];
         const W2<T> wn = lw[ec];
         const int32_t in = lidx[ec];
-        sweep_contrib<T, MODE, FRAME>(cd, t, w, i, jv0, Pr, U, dU, gamma, acc);
+        sweep_contrib<T, MODE>(cd, t, w, i, jv0, jv2, U, dU, gamma, acc);
         cd = cdn;
         w = wn;
         i = in;
@@ -1385,31 +1308,31 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
     for (int o = LANES / 2; o > 0; o >>= 1)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] += __shfl_xor(acc[v], o, 64);
-    T out[4] = {T(0), T(0), T(0), T(0)};
-    if (ty != kOuter || farfield) {
-        const T iD = T(1) / dg;
-        if (FWD) {
-            out[0] = -(own.x + acc[0]) * iD;
-            out[1] = -(own.y + acc[1]) * iD;
-            out[2] = -(own.z + acc[2]) * iD;
-            out[3] = -(own.w + acc[3]) * iD;
-        } else {
-            out[0] = own.x - acc[0] * iD;
-            out[1] = own.y - acc[1] * iD;
-            out[2] = own.z - acc[2] * iD;
-            out[3] = own.w - acc[3] * iD;
-        }
-        if (FRAME && ty == kWall) {
-            const T nx = T(-t.y), ny = T(t.x);
-            const T mn = out[1] * nx + out[2] * ny;
-            out[1] -= mn * nx;
-            out[2] -= mn * ny;
-        }
-    } else if (!FWD) {
-        return;  // an outer point under the Dirichlet far field keeps dU = 0
+    if (lane != 0) return;
+    if (ty == kOuter && !farfield) {
+        if (FWD) dU[p] = {T(0), T(0), T(0), T(0)};
+        return;
     }
-    if (lane == 0) dU[p] = {out[0], out[1], out[2], out[3]};
-    if (produce) write_products<T, MODE, LANES>(lane, p, lin_of(lin0), k2, u, out, gamma, Pr);
+    const T iD = T(1) / dg;
+    T out[4];
+    if (FWD) {
+        out[0] = -(own.x + acc[0]) * iD;
+        out[1] = -(own.y + acc[1]) * iD;
+        out[2] = -(own.z + acc[2]) * iD;
+        out[3] = -(own.w + acc[3]) * iD;
+    } else {
+        out[0] = own.x - acc[0] * iD;
+        out[1] = own.y - acc[1] * iD;
+        out[2] = own.z - acc[2] * iD;
+        out[3] = own.w - acc[3] * iD;
+    }
+    if (ty == kWall) {
+        const T nx = T(-t.y), ny = T(t.x);
+        const T mn = out[1] * nx + out[2] * ny;
+        out[1] -= mn * nx;
+        out[2] -= mn * ny;
+    }
+    dU[p] = {out[0], out[1], out[2], out[3]};
 }
 
 // U += dU (Section 3) and the q-variables of the new state (eq. 14).
@@ -1678,7 +1601,7 @@ static void residual_lanes(State& s, bool in_step) {
                        s.prm.limiter ? s.qyl : s.qy[s.qsel], s.R, s.D, s.jv0, s.jv2, s.jv0f,
                        s.jv2f, s.Df, s.rr, s.flags, s.prm.variant,
                        s.prm.jvp_mode, s.dU, s.dUf, s.Rs, c.colour,
-                       in_step && fused_first_colour(s), s.prm.farfield, s.vinf, s.Pr, s.Prf);
+                       in_step && fused_first_colour(s), s.prm.farfield, s.vinf);
 }
 
 template <bool MIXED>
@@ -1717,36 +1640,26 @@ hipError_t launch_reset_components(State& s) {
     return hipGetLastError();
 }
 
-// The phases of a sweep: one per colour (Algorithm 6), or per (point type,
-// colour) with wall, interior and outer points in turn (Algorithm 5); colours
-// ascending forward, descending backward.  Each phase lists its frame points
-// (wall; outer under the kinetic far field) as up to two colour-sorted ranges
-// and its other points as one range.
-struct Phase {
-    int32_t f0, nf0, f1, nf1;  // frame points
-    int32_t i0, ni;            // interior points (and outer points at the free stream)
-};
-
-static std::vector<Phase> sweep_phases(const State& s, bool forward) {
+// The phases of a sweep as ranges of the colour-sorted points: one per
+// colour (Algorithm 6), or per (point type, colour) with wall, interior and
+// outer points in turn (Algorithm 5); colours ascending forward, descending
+// backward.
+static std::vector<std::pair<int32_t, int32_t>> sweep_phases(const State& s, bool forward) {
     const Cloud& c = *s.cloud;
-    std::vector<Phase> ph;
+    std::vector<std::pair<int32_t, int32_t>> ph;
     const int C = c.ncolour;
-    const bool ff = s.prm.farfield != 0;
-    auto grp = [&](int col, int g) { return c.h_grp_off[3 * col + g]; };
     if (s.prm.order == 0) {
         for (int k = fused_first_colour(s) ? 1 : 0; k < C; ++k) {
             const int col = forward ? k : C - 1 - k;
-            const int32_t g0 = grp(col, 0), g1 = grp(col, 1), g2 = grp(col, 2), g3 = grp(col, 3);
-            ph.push_back({g0, g1 - g0, g2, ff ? g3 - g2 : 0, g1, (ff ? g2 : g3) - g1});
+            ph.emplace_back(c.h_col_off[col], c.h_col_off[col + 1] - c.h_col_off[col]);
         }
         return ph;
     }
     for (int g = 0; g < 3; ++g)
         for (int k = 0; k < C; ++k) {
             const int col = forward ? k : C - 1 - k;
-            const int32_t a = grp(col, g), n = grp(col, g + 1) - a;
-            if (g == 0 || (g == 2 && ff)) ph.push_back({a, n, a + n, 0, a, 0});
-            else ph.push_back({a, 0, a, 0, a, n});
+            const int32_t a = c.h_grp_off[3 * col + g], b = c.h_grp_off[3 * col + g + 1];
+            ph.emplace_back(a, b - a);
         }
     return ph;
 }
@@ -1758,67 +1671,36 @@ static const W2<T>* list_weights(const D2* w, const F2* wf) {
     else return w;
 }
 
-template <class T, int MODE, int LANES, bool FRAME>
-static void sweep_launch(State& s, bool forward, hipStream_t st, int32_t a0, int32_t n0,
-                         int32_t a1, int32_t n1, const Vec4<T>* jv0, const Vec4<T>* jv2,
-                         const T* Dg, Vec4<T>* dU, Vec4<T>* Pr, int produce) {
-    const Cloud& c = *s.cloud;
-    const dim3 g(grid_for((int64_t)(n0 + n1) * LANES)), b(kBlock);
-    if (forward)
-        hipLaunchKernelGGL((k_sweep<T, true, MODE, LANES, FRAME>), g, b, 0, st, a0, n0, a1, n1,
-                           c.col_perm, c.frame, c.type, c.lo_off, c.lo_idx,
-                           list_weights<T>(c.lo_w, c.lo_wf), c.lo_code, c.comp, s.active, jv0,
-                           jv2, s.U, s.prm.variant ? s.Rs : s.R, Dg, dU, Pr, s.prm.gamma,
-                           s.prm.farfield, produce);
-    else
-        hipLaunchKernelGGL((k_sweep<T, false, MODE, LANES, FRAME>), g, b, 0, st, a0, n0, a1, n1,
-                           c.col_perm, c.frame, c.type, c.up_off, c.up_idx,
-                           list_weights<T>(c.up_w, c.up_wf), c.up_code, c.comp, s.active, jv0,
-                           jv2, s.U, s.R, Dg, dU, Pr, s.prm.gamma, s.prm.farfield, produce);
-}
-
-// Every phase forms its points' split products except, in colour order, the
-// last backward phase: no later phase of the iteration reads them (the next
-// forward sweep forms its own before any is read).  A phase's frame points
-// run on the state's side stream, forked from and joined back to its stream,
-// beside its interior points (a parallel branch when captured in a graph).
 template <class T, int MODE, int LANES>
-static hipError_t sweep_lanes(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv2,
-                              const T* Dg, Vec4<T>* dU, Vec4<T>* Pr) {
-    const auto phases = sweep_phases(s, forward);
-    for (size_t k = 0; k < phases.size(); ++k) {
-        const Phase& f = phases[k];
-        const int produce = forward || s.prm.order != 0 || k + 1 < phases.size();
-        const bool frame = f.nf0 + f.nf1 > 0;
-        if (frame) {
-            hipError_t e = hipEventRecord(s.fork_ev, s.stream);
-            if (e == hipSuccess) e = hipStreamWaitEvent(s.side, s.fork_ev, 0);
-            if (e != hipSuccess) return e;
-            sweep_launch<T, MODE, LANES, true>(s, forward, s.side, f.f0, f.nf0, f.f1, f.nf1, jv0,
-                                               jv2, Dg, dU, Pr, produce);
-            e = hipEventRecord(s.join_ev, s.side);
-            if (e != hipSuccess) return e;
-        }
-        if (f.ni)
-            sweep_launch<T, MODE, LANES, false>(s, forward, s.stream, f.i0, f.ni, f.i0 + f.ni, 0,
-                                                jv0, jv2, Dg, dU, Pr, produce);
-        if (frame) {
-            hipError_t e = hipStreamWaitEvent(s.stream, s.join_ev, 0);
-            if (e != hipSuccess) return e;
-        }
+static void sweep_lanes(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv2,
+                        const T* Dg, Vec4<T>* dU) {
+    const Cloud& c = *s.cloud;
+    for (const auto& [start, cnt] : sweep_phases(s, forward)) {
+        if (!cnt) continue;
+        const dim3 g(grid_for((int64_t)cnt * LANES)), b(kBlock);
+        if (forward)
+            hipLaunchKernelGGL((k_sweep<T, true, MODE, LANES>), g, b, 0, s.stream, start, cnt,
+                               c.col_perm, c.frame, c.type, c.lo_off, c.lo_idx,
+                               list_weights<T>(c.lo_w, c.lo_wf), c.lo_code, c.comp, s.active,
+                               jv0, jv2, s.U, s.prm.variant ? s.Rs : s.R, Dg, dU,
+                               s.prm.gamma, s.prm.farfield);
+        else
+            hipLaunchKernelGGL((k_sweep<T, false, MODE, LANES>), g, b, 0, s.stream, start, cnt,
+                               c.col_perm, c.frame, c.type, c.up_off, c.up_idx,
+                               list_weights<T>(c.up_w, c.up_wf), c.up_code, c.comp, s.active,
+                               jv0, jv2, s.U, s.R, Dg, dU, s.prm.gamma, s.prm.farfield);
     }
-    return hipGetLastError();
 }
 
 template <class T, int MODE>
-static hipError_t sweep_t(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv2,
-                          const T* Dg, Vec4<T>* dU, Vec4<T>* Pr) {
+static void sweep_t(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv2,
+                    const T* Dg, Vec4<T>* dU) {
     switch (s.sweep_lanes) {
-        case 1: return sweep_lanes<T, MODE, 1>(s, forward, jv0, jv2, Dg, dU, Pr);
-        case 2: return sweep_lanes<T, MODE, 2>(s, forward, jv0, jv2, Dg, dU, Pr);
-        case 8: return sweep_lanes<T, MODE, 8>(s, forward, jv0, jv2, Dg, dU, Pr);
-        case 16: return sweep_lanes<T, MODE, 16>(s, forward, jv0, jv2, Dg, dU, Pr);
-        default: return sweep_lanes<T, MODE, 4>(s, forward, jv0, jv2, Dg, dU, Pr);
+        case 1: sweep_lanes<T, MODE, 1>(s, forward, jv0, jv2, Dg, dU); break;
+        case 2: sweep_lanes<T, MODE, 2>(s, forward, jv0, jv2, Dg, dU); break;
+        case 8: sweep_lanes<T, MODE, 8>(s, forward, jv0, jv2, Dg, dU); break;
+        case 16: sweep_lanes<T, MODE, 16>(s, forward, jv0, jv2, Dg, dU); break;
+        default: sweep_lanes<T, MODE, 4>(s, forward, jv0, jv2, Dg, dU); break;
     }
 }
 
@@ -1830,25 +1712,23 @@ __global__ void __launch_bounds__(kBlock) k_zero4(int64_t n, Vec4<T>* __restrict
 
 hipError_t launch_sweep_dir(State& s, bool forward) {
     const Cloud& c = *s.cloud;
-    // Algorithm 5 reads increments (and their products) of points not yet
-    // visited in the forward sweep: they start the sweep at zero (kernels, so
-    // that graphs replay them)
+    // Algorithm 5 reads increments of points not yet visited in the forward
+    // sweep: they start the sweep at zero (a kernel, so that graphs replay it)
     if (forward && s.prm.order == 1) {
-        if (s.prm.precision == 1) {
+        if (s.prm.precision == 1)
             hipLaunchKernelGGL(k_zero4<float>, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream, c.n,
                                s.dUf);
-            hipLaunchKernelGGL(k_zero4<float>, dim3(grid_for(4 * c.n)), dim3(kBlock), 0, s.stream,
-                               4 * c.n, s.Prf);
-        } else {
+        else
             hipLaunchKernelGGL(k_zero4<double>, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream,
                                c.n, s.dU);
-            hipLaunchKernelGGL(k_zero4<double>, dim3(grid_for(4 * c.n)), dim3(kBlock), 0,
-                               s.stream, 4 * c.n, s.Pr);
-        }
     }
-    if (s.prm.precision == 1) return sweep_t<float, 0>(s, forward, s.jv0f, s.jv2f, s.Df, s.dUf, s.Prf);
-    if (s.prm.jvp_mode == 1) return sweep_t<double, 1>(s, forward, s.jv0, s.jv2, s.D, s.dU, s.Pr);
-    return sweep_t<double, 0>(s, forward, s.jv0, s.jv2, s.D, s.dU, s.Pr);
+    if (s.prm.precision == 1)
+        sweep_t<float, 0>(s, forward, s.jv0f, s.jv2f, s.Df, s.dUf);
+    else if (s.prm.jvp_mode == 1)
+        sweep_t<double, 1>(s, forward, s.jv0, s.jv2, s.D, s.dU);
+    else
+        sweep_t<double, 0>(s, forward, s.jv0, s.jv2, s.D, s.dU);
+    return hipGetLastError();
 }
 
 hipError_t launch_sweeps(State& s) {

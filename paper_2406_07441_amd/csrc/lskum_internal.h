@@ -164,10 +164,6 @@ struct State {
     double* rr = nullptr;                  // per point R_rho^2 (0 at outer points)
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    // side stream of the sweeps' frame-point kernels, forked from and joined
-    // back to `stream` in every colour phase (default priority)
-    hipStream_t side = nullptr;
-    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     int sweep_lanes = 4;         // lanes per point in the sweep kernels (1, 2, 4 or 8)
     int residual_lanes = 4;      // lanes per point in the residual kernel (1, 2, 4 or 8)
     int qgrad_lanes = 4;         // lanes per point in the q-derivative kernels
@@ -185,15 +181,11 @@ struct State {
     D4* jv0 = nullptr;   // (rho, u1, u2, p) at the state the sweeps linearise about
     D4* jv2 = nullptr;   // (erf(Sx), exp(-Sx^2), erf(Sy), exp(-Sy^2))
     double* D = nullptr; // scalar diagonal
-    // split-flux products A_k(U_p) dU_p of each point, 4 records per point
-    // (x G+, x G-, y G+, y G-), formed when its increment is final in a sweep
-    D4* Pr = nullptr;
     // fp32 copies for the mixed-precision sweeps
     F4* jv0f = nullptr;
     F4* jv2f = nullptr;
     F4* dUf = nullptr;
     float* Df = nullptr;
-    F4* Prf = nullptr;
     // reductions
     double* fsum = nullptr;      // 2 doubles per component: pressure force
     double* partial = nullptr;   // one partial sum of R_rho^2 per reduction chunk
