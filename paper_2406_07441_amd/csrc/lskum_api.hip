@@ -375,8 +375,8 @@ void free_state(lskum::State& s) {
     if (s.have_events)
         for (hipEvent_t ev : s.ev) (void)hipEventDestroy(ev);
     void* ptrs[] = {s.U,    s.q,      s.qx[0], s.qx[1],  s.qy[0],   s.qy[1],    s.qxl, s.Rs,
-                    s.qyl,  s.R,      s.dU,    s.swr,    s.D,
-                    s.swrf,  s.dUf,    s.Df,      s.rr,       s.fsum, s.partial,
+                    s.qyl,  s.R,      s.dU,    s.jv0,    s.jv2,      s.D,
+                    s.jv0f, s.jv2f,  s.dUf,    s.Df,      s.rr,       s.fsum, s.partial,
                     s.res_hist, s.flags, s.active, s.status, s.iters, s.res_last, s.tol_abs, s.cfl,
                     s.vinf};
     for (void* p : ptrs) (void)hipFree(p);
@@ -517,9 +517,11 @@ int init_state(lskum::State& s, const lskum::Cloud& c, const lskum_params* prm,
     chk(dalloc(&s.R, n));
     chk(dalloc(&s.Rs, n));
     chk(dalloc(&s.dU, n));
-    chk(dalloc(&s.swr, 2 * n));
+    chk(dalloc(&s.jv0, n));
+    chk(dalloc(&s.jv2, n));
     chk(dalloc(&s.D, n));
-    chk(dalloc(&s.swrf, 2 * n));
+    chk(dalloc(&s.jv0f, n));
+    chk(dalloc(&s.jv2f, n));
     chk(dalloc(&s.dUf, n));
     chk(dalloc(&s.Df, n));
     chk(dalloc(&s.rr, n));
@@ -1081,7 +1083,8 @@ int lskum_residual_noalloc(const lskum_cloud* cl, double mach, double aoa_deg,
     s.qxl = cv.take<lskum::D4>(n);
     s.qyl = cv.take<lskum::D4>(n);
     s.R = cv.take<lskum::D4>(n);
-    s.swr = cv.take<lskum::D4>(2 * n);
+    s.jv0 = cv.take<lskum::D4>(n);
+    s.jv2 = cv.take<lskum::D4>(n);
     s.D = cv.take<double>(n);
     s.rr = cv.take<double>(n);
     s.partial = cv.take<double>(c.nchunk);

@@ -705,7 +705,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(
     const int32_t* __restrict__ comp, const int32_t* __restrict__ active,
     const D4* __restrict__ U, const D4* __restrict__ q, const D4* __restrict__ qx,
     const D4* __restrict__ qy, D4* __restrict__ R, double* __restrict__ Dg,
-    D4* __restrict__ swr, F4* __restrict__ swrf,
+    D4* __restrict__ jv0, D4* __restrict__ jv2, F4* __restrict__ jv0f, F4* __restrict__ jv2f,
     float* __restrict__ Df,
     double* __restrict__ rr_out, int32_t* __restrict__ flags, int variant, int fd,
     D4* dUio, F4* dUfio, D4* __restrict__ Rs, const int32_t* __restrict__ colour, int sweep0,
@@ -791,7 +791,11 @@ __global__ void __launch_bounds__(kBlock) k_residual(
             const double u1 = u.y * irho, u2 = u.z * irho;
             const double usq = u1 * u1 + u2 * u2;
             const double pr = (gamma - 1.0) * (u.w - 0.5 * rho * usq);
+            const double beta = 0.5 * rho / pr;
+            const double sb = sqrt(beta);
+            const double sx = u1 * sb, sy = u2 * sb;
             const D4 j0 = {rho, u1, u2, pr};
+            const D4 j2 = {erf(sx), exp(-(sx * sx)), erf(sy), exp(-(sy * sy))};
             const double a = sqrt(gamma * pr / rho);
             const PointGeom& G = geom[p];
             const double dt = cfl[comp ? comp[p] : 0] * G.lsq.w / (sqrt(usq) + a);
@@ -879,10 +883,12 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                     for (int v = 0; v < 4; ++v) Sv[v] = Rp[v] - Sv[v];
             }
             if (MIXED) {
-                swrf[2 * p] = {(float)j0.x, (float)j0.y, (float)j0.z, (float)j0.w};
+                jv0f[p] = {(float)j0.x, (float)j0.y, (float)j0.z, (float)j0.w};
+                jv2f[p] = {(float)j2.x, (float)j2.y, (float)j2.z, (float)j2.w};
                 Df[p] = (float)Dp;
             } else {
-                swr[2 * p] = j0;
+                jv0[p] = j0;
+                jv2[p] = j2;
                 Dg[p] = Dp;
             }
             // the forward sweep's first colour phase: its points have no lower
@@ -908,7 +914,6 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                         }
                     }
                     dUfio[p] = {o[0], o[1], o[2], o[3]};
-                    swrf[2 * p + 1] = {o[0], o[1], o[2], o[3]};
                 } else {
                     double o[4] = {0, 0, 0, 0};
                     if (part) {
@@ -923,7 +928,6 @@ __global__ void __launch_bounds__(kBlock) k_residual(
                         }
                     }
                     dUio[p] = {o[0], o[1], o[2], o[3]};
-                    swr[2 * p + 1] = {o[0], o[1], o[2], o[3]};
                 }
             }
             if (bad || !(rho > 0.0) || !(pr > 0.0)) flags[0] = 1;
@@ -1082,7 +1086,8 @@ __device__ __forceinline__ void jvp_fluxdiff(const Lin<double>& L, double er, do
 // One reciprocal, of rho p, gives both 1/rho and 1/p; the fp32 sweeps use
 // the hardware reciprocal and square root (about 1 ulp).
 template <class T>
-__device__ __forceinline__ Lin<T> lin_of(const Vec4<T>& a) {
+__device__ __forceinline__ Lin<T> load_lin(const Vec4<T>* jv0, int32_t i) {
+    const Vec4<T> a = jv0[i];
     T r, sb;
     if constexpr (std::is_same_v<T, float>) {
         r = __builtin_amdgcn_rcpf(a.x * a.w);
@@ -1162,34 +1167,22 @@ __global__ void __launch_bounds__(kBlock) k_sweep_weights(int64_t n,
 // sum (eq. 22-27) from the entry's weights and split bits: interior points
 // use the x and y split the neighbour falls in, frame points the t split and
 // the normal split (n- at a wall, n+ at a far-field outer point) in the frame
-// t of point p.  The neighbour's sweep record is one 2-record row: its
-// linearisation state (rho, u1, u2, p) and its current increment, one
-// contiguous gather; erf and exp of the split's S are formed here, which
-// costs arithmetic the sweeps have to spare and saves a third record per
-// neighbour on a path bound by the bytes it gathers.
-template <class T>
-__device__ __forceinline__ void split_erf_exp(T S, T& er, T& g) {
-    if constexpr (std::is_same_v<T, float>) {
-        er = erff(S);
-        g = expf(-(S * S));
-    } else {
-        er = erf(S);
-        g = exp(-(S * S));
-    }
-}
-
+// t of point p.
 template <class T, int MODE>
 __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<T>& w, int32_t i,
-                                              const Vec4<T>* __restrict__ swr,
-                                              const D4* __restrict__ U, double gamma, T acc[4]) {
+                                              const Vec4<T>* __restrict__ jv0,
+                                              const Vec4<T>* __restrict__ jv2,
+                                              const D4* __restrict__ U,
+                                              const Vec4<T>* __restrict__ dU, double gamma,
+                                              T acc[4]) {
     const T gm1 = T(gamma - 1.0), inv_gm1 = T(1.0 / (gamma - 1.0));
-    const Vec4<T> a = swr[2 * (int64_t)i];
-    const Vec4<T> di = swr[2 * (int64_t)i + 1];
+    const Vec4<T> di = dU[i];
     const T dv[4] = {di.x, di.y, di.z, di.w};
-    const Lin<T> L = lin_of(a);
+    const Lin<T> L = load_lin(jv0, i);
+    const Vec4<T> k2 = jv2[i];  // interior entries only; loaded with the rest
     T J[4];
     if (cd & kSwWall) {
-        // wall-frame directions
+        // wall-frame directions: erf/exp at the neighbour state are formed here
         if (cd & kSwA) {
             const double sg = (cd & kSwNegA) ? 1.0 : -1.0;
             if constexpr (MODE == 1) {
@@ -1198,9 +1191,7 @@ __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<
                              1.0 / (gamma - 1.0), J);
             } else {
                 const T S = (L.u1 * T(t.x) + L.u2 * T(t.y)) * L.sb;
-                T er, g;
-                split_erf_exp(S, er, g);
-                jvp_exact<T>(L, er, g, T(t.x), T(t.y), T(sg), dv, gm1, inv_gm1, J);
+                jvp_exact<T>(L, erf(S), exp(-(S * S)), T(t.x), T(t.y), T(sg), dv, gm1, inv_gm1, J);
             }
             const T wa = T(w.x);
 #pragma unroll
@@ -1214,9 +1205,7 @@ __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<
                              1.0 / (gamma - 1.0), J);
             } else {
                 const T S = (-L.u1 * T(t.y) + L.u2 * T(t.x)) * L.sb;
-                T er, g;
-                split_erf_exp(S, er, g);
-                jvp_exact<T>(L, er, g, T(-t.y), T(t.x), T(sg), dv, gm1, inv_gm1, J);
+                jvp_exact<T>(L, erf(S), exp(-(S * S)), T(-t.y), T(t.x), T(sg), dv, gm1, inv_gm1, J);
             }
             const T wb = T(w.y);
 #pragma unroll
@@ -1226,24 +1215,20 @@ __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<
     }
     if (cd & kSwA) {
         const T sg = (cd & kSwNegA) ? T(1) : T(-1);
-        T er, g;
-        split_erf_exp(L.u1 * L.sb, er, g);
         if constexpr (MODE == 1)
-            jvp_fluxdiff(L, er, g, U[i], 1.0, 0.0, sg, dv, gamma, 1.0 / (gamma - 1.0), J);
+            jvp_fluxdiff(L, k2.x, k2.y, U[i], 1.0, 0.0, sg, dv, gamma, 1.0 / (gamma - 1.0), J);
         else
-            jvp_exact<T>(L, er, g, T(1), T(0), sg, dv, gm1, inv_gm1, J);
+            jvp_exact<T>(L, k2.x, k2.y, T(1), T(0), sg, dv, gm1, inv_gm1, J);
         const T wa = T(w.x);
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] += wa * J[v];
     }
     if (cd & kSwB) {
         const T sg = (cd & kSwNegB) ? T(1) : T(-1);
-        T er, g;
-        split_erf_exp(L.u2 * L.sb, er, g);
         if constexpr (MODE == 1)
-            jvp_fluxdiff(L, er, g, U[i], 0.0, 1.0, sg, dv, gamma, 1.0 / (gamma - 1.0), J);
+            jvp_fluxdiff(L, k2.z, k2.w, U[i], 0.0, 1.0, sg, dv, gamma, 1.0 / (gamma - 1.0), J);
         else
-            jvp_exact<T>(L, er, g, T(0), T(1), sg, dv, gm1, inv_gm1, J);
+            jvp_exact<T>(L, k2.z, k2.w, T(0), T(1), sg, dv, gm1, inv_gm1, J);
         const T wb = T(w.y);
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] += wb * J[v];
@@ -1265,7 +1250,8 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
     const int32_t* __restrict__ loff, const int32_t* __restrict__ lidx,
     const W2<T>* __restrict__ lw, const uint8_t* __restrict__ lcode,
     const int32_t* __restrict__ comp, const int32_t* __restrict__ active,
-    Vec4<T>* __restrict__ swr, const D4* __restrict__ U, const D4* __restrict__ R,
+    const Vec4<T>* __restrict__ jv0, const Vec4<T>* __restrict__ jv2,
+    const D4* __restrict__ U, const D4* __restrict__ R,
     const T* __restrict__ Dg, Vec4<T>* __restrict__ dU, double gamma, int farfield) {
     const int gt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int pt = gt / LANES, lane = gt % LANES;
@@ -1312,7 +1298,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
         const uint8_t cdn = lcode[ec];
         const W2<T> wn = lw[ec];
         const int32_t in = lidx[ec];
-        sweep_contrib<T, MODE>(cd, t, w, i, swr, U, gamma, acc);
+        sweep_contrib<T, MODE>(cd, t, w, i, jv0, jv2, U, dU, gamma, acc);
         cd = cdn;
         w = wn;
         i = in;
@@ -1324,10 +1310,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
         for (int v = 0; v < 4; ++v) acc[v] += __shfl_xor(acc[v], o, 64);
     if (lane != 0) return;
     if (ty == kOuter && !farfield) {
-        if (FWD) {
-            dU[p] = {T(0), T(0), T(0), T(0)};
-            swr[2 * (int64_t)p + 1] = {T(0), T(0), T(0), T(0)};
-        }
+        if (FWD) dU[p] = {T(0), T(0), T(0), T(0)};
         return;
     }
     const T iD = T(1) / dg;
@@ -1350,7 +1333,6 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
         out[2] -= mn * ny;
     }
     dU[p] = {out[0], out[1], out[2], out[3]};
-    swr[2 * (int64_t)p + 1] = {out[0], out[1], out[2], out[3]};
 }
 
 // U += dU (Section 3) and the q-variables of the new state (eq. 14).
@@ -1616,8 +1598,8 @@ static void residual_lanes(State& s, bool in_step) {
     hipLaunchKernelGGL((k_residual<MIXED, LANES>), dim3(nb), dim3(kBlock), 0, s.stream, c.n,
                        s.prm.gamma, s.cfl, c.xy, c.frame, c.type, c.off, c.idx, c.geom, c.comp,
                        s.active, s.U, s.q, s.prm.limiter ? s.qxl : s.qx[s.qsel],
-                       s.prm.limiter ? s.qyl : s.qy[s.qsel], s.R, s.D, s.swr, s.swrf, s.Df,
-                       s.rr, s.flags, s.prm.variant,
+                       s.prm.limiter ? s.qyl : s.qy[s.qsel], s.R, s.D, s.jv0, s.jv2, s.jv0f,
+                       s.jv2f, s.Df, s.rr, s.flags, s.prm.variant,
                        s.prm.jvp_mode, s.dU, s.dUf, s.Rs, c.colour,
                        in_step && fused_first_colour(s), s.prm.farfield, s.vinf);
 }
@@ -1690,7 +1672,8 @@ static const W2<T>* list_weights(const D2* w, const F2* wf) {
 }
 
 template <class T, int MODE, int LANES>
-static void sweep_lanes(State& s, bool forward, Vec4<T>* swr, const T* Dg, Vec4<T>* dU) {
+static void sweep_lanes(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv2,
+                        const T* Dg, Vec4<T>* dU) {
     const Cloud& c = *s.cloud;
     for (const auto& [start, cnt] : sweep_phases(s, forward)) {
         if (!cnt) continue;
@@ -1699,35 +1682,32 @@ static void sweep_lanes(State& s, bool forward, Vec4<T>* swr, const T* Dg, Vec4<
             hipLaunchKernelGGL((k_sweep<T, true, MODE, LANES>), g, b, 0, s.stream, start, cnt,
                                c.col_perm, c.frame, c.type, c.lo_off, c.lo_idx,
                                list_weights<T>(c.lo_w, c.lo_wf), c.lo_code, c.comp, s.active,
-                               swr, s.U, s.prm.variant ? s.Rs : s.R, Dg, dU,
+                               jv0, jv2, s.U, s.prm.variant ? s.Rs : s.R, Dg, dU,
                                s.prm.gamma, s.prm.farfield);
         else
             hipLaunchKernelGGL((k_sweep<T, false, MODE, LANES>), g, b, 0, s.stream, start, cnt,
                                c.col_perm, c.frame, c.type, c.up_off, c.up_idx,
                                list_weights<T>(c.up_w, c.up_wf), c.up_code, c.comp, s.active,
-                               swr, s.U, s.R, Dg, dU, s.prm.gamma, s.prm.farfield);
+                               jv0, jv2, s.U, s.R, Dg, dU, s.prm.gamma, s.prm.farfield);
     }
 }
 
 template <class T, int MODE>
-static void sweep_t(State& s, bool forward, Vec4<T>* swr, const T* Dg, Vec4<T>* dU) {
+static void sweep_t(State& s, bool forward, const Vec4<T>* jv0, const Vec4<T>* jv2,
+                    const T* Dg, Vec4<T>* dU) {
     switch (s.sweep_lanes) {
-        case 1: sweep_lanes<T, MODE, 1>(s, forward, swr, Dg, dU); break;
-        case 2: sweep_lanes<T, MODE, 2>(s, forward, swr, Dg, dU); break;
-        case 8: sweep_lanes<T, MODE, 8>(s, forward, swr, Dg, dU); break;
-        case 16: sweep_lanes<T, MODE, 16>(s, forward, swr, Dg, dU); break;
-        default: sweep_lanes<T, MODE, 4>(s, forward, swr, Dg, dU); break;
+        case 1: sweep_lanes<T, MODE, 1>(s, forward, jv0, jv2, Dg, dU); break;
+        case 2: sweep_lanes<T, MODE, 2>(s, forward, jv0, jv2, Dg, dU); break;
+        case 8: sweep_lanes<T, MODE, 8>(s, forward, jv0, jv2, Dg, dU); break;
+        case 16: sweep_lanes<T, MODE, 16>(s, forward, jv0, jv2, Dg, dU); break;
+        default: sweep_lanes<T, MODE, 4>(s, forward, jv0, jv2, Dg, dU); break;
     }
 }
 
-// zero increments, both the array and the copy in the sweep records
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_zero_increment(int64_t n, Vec4<T>* __restrict__ dU,
-                                                           Vec4<T>* __restrict__ swr) {
+__global__ void __launch_bounds__(kBlock) k_zero4(int64_t n, Vec4<T>* __restrict__ v) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    dU[p] = {T(0), T(0), T(0), T(0)};
-    swr[2 * p + 1] = {T(0), T(0), T(0), T(0)};
+    if (p < n) v[p] = {T(0), T(0), T(0), T(0)};
 }
 
 hipError_t launch_sweep_dir(State& s, bool forward) {
@@ -1736,18 +1716,18 @@ hipError_t launch_sweep_dir(State& s, bool forward) {
     // sweep: they start the sweep at zero (a kernel, so that graphs replay it)
     if (forward && s.prm.order == 1) {
         if (s.prm.precision == 1)
-            hipLaunchKernelGGL(k_zero_increment<float>, dim3(grid_for(c.n)), dim3(kBlock), 0,
-                               s.stream, c.n, s.dUf, s.swrf);
+            hipLaunchKernelGGL(k_zero4<float>, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream, c.n,
+                               s.dUf);
         else
-            hipLaunchKernelGGL(k_zero_increment<double>, dim3(grid_for(c.n)), dim3(kBlock), 0,
-                               s.stream, c.n, s.dU, s.swr);
+            hipLaunchKernelGGL(k_zero4<double>, dim3(grid_for(c.n)), dim3(kBlock), 0, s.stream,
+                               c.n, s.dU);
     }
     if (s.prm.precision == 1)
-        sweep_t<float, 0>(s, forward, s.swrf, s.Df, s.dUf);
+        sweep_t<float, 0>(s, forward, s.jv0f, s.jv2f, s.Df, s.dUf);
     else if (s.prm.jvp_mode == 1)
-        sweep_t<double, 1>(s, forward, s.swr, s.D, s.dU);
+        sweep_t<double, 1>(s, forward, s.jv0, s.jv2, s.D, s.dU);
     else
-        sweep_t<double, 0>(s, forward, s.swr, s.D, s.dU);
+        sweep_t<double, 0>(s, forward, s.jv0, s.jv2, s.D, s.dU);
     return hipGetLastError();
 }
 

@@ -178,13 +178,12 @@ struct State {
     D4* R = nullptr;
     D4* Rs = nullptr;    // forward-sweep right-hand side R - S (Manish variant)
     D4* dU = nullptr;    // increment; kept between iterations (zero after a new U)
-    // sweep records, two per point: [2p] (rho, u1, u2, p) at the state the
-    // sweeps linearise about, [2p+1] the point's increment as the sweeps
-    // leave it (a copy of dU that a neighbour gathers with the state)
-    D4* swr = nullptr;
+    D4* jv0 = nullptr;   // (rho, u1, u2, p) at the state the sweeps linearise about
+    D4* jv2 = nullptr;   // (erf(Sx), exp(-Sx^2), erf(Sy), exp(-Sy^2))
     double* D = nullptr; // scalar diagonal
     // fp32 copies for the mixed-precision sweeps
-    F4* swrf = nullptr;
+    F4* jv0f = nullptr;
+    F4* jv2f = nullptr;
     F4* dUf = nullptr;
     float* Df = nullptr;
     // reductions
