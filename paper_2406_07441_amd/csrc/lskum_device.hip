@@ -477,20 +477,37 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad_tiled(
     const D4* __restrict__ q, const D4* __restrict__ qx_in, const D4* __restrict__ qy_in,
     D4* __restrict__ qx_out, D4* __restrict__ qy_out, D4* __restrict__ qxl,
     D4* __restrict__ qyl) {
-    extern __shared__ D4 smem[];
-    D4* s_q = smem;
-    D4* s_gx = s_q + hmax;
-    D4* s_gy = s_gx + (INNER ? hmax : 0);
-    D2* s_r = reinterpret_cast<D2*>(s_gy + (INNER ? hmax : 0));
+    // one double array per field component (structure of arrays): the lanes
+    // of a wave read consecutive list positions, so 8-byte reads fall in
+    // distinct banks, where 32-byte records would put lanes four records
+    // apart into the same bank
+    extern __shared__ double smem[];
+    double* s_x = smem;
+    double* s_y = s_x + hmax;
+    double* s_q = s_y + hmax;                  // 4 components
+    double* s_g = s_q + 4 * hmax;              // 8 components (x then y derivatives)
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     const int32_t h0 = tile_off[tile], nh = tile_off[tile + 1] - h0;
     for (int32_t k = threadIdx.x; k < nh; k += kBlock) {
         const int32_t i = tile_idx[h0 + k];
-        s_r[k] = xy[i];
-        s_q[k] = q[i];
+        const D2 r = xy[i];
+        const D4 qi = q[i];
+        s_x[k] = r.x;
+        s_y[k] = r.y;
+        s_q[k] = qi.x;
+        s_q[hmax + k] = qi.y;
+        s_q[2 * hmax + k] = qi.z;
+        s_q[3 * hmax + k] = qi.w;
         if (INNER) {
-            s_gx[k] = qx_in[i];
-            s_gy[k] = qy_in[i];
+            const D4 gx = qx_in[i], gy = qy_in[i];
+            s_g[k] = gx.x;
+            s_g[hmax + k] = gx.y;
+            s_g[2 * hmax + k] = gx.z;
+            s_g[3 * hmax + k] = gx.w;
+            s_g[4 * hmax + k] = gy.x;
+            s_g[5 * hmax + k] = gy.y;
+            s_g[6 * hmax + k] = gy.z;
+            s_g[7 * hmax + k] = gy.w;
         }
     }
     __syncthreads();
@@ -510,9 +527,8 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad_tiled(
     const int32_t e0 = off[p], e1 = off[p + 1];
     for (int32_t e = e0 + lane; e < e1; e += 4) {
         const int li = lnbr[e];
-        const D2 ri = s_r[li];
-        const double dx = ri.x - r0.x, dy = ri.y - r0.y;
-        const D4 qi = s_q[li];
+        const double dx = s_x[li] - r0.x, dy = s_y[li] - r0.y;
+        const D4 qi = {s_q[li], s_q[hmax + li], s_q[2 * hmax + li], s_q[3 * hmax + li]};
         double dq[4] = {qi.x - qv[0], qi.y - qv[1], qi.z - qv[2], qi.w - qv[3]};
         if (LIMIT) {
 #pragma unroll
@@ -522,7 +538,9 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad_tiled(
             }
         }
         if (INNER) {
-            const D4 gxi = s_gx[li], gyi = s_gy[li];
+            const D4 gxi = {s_g[li], s_g[hmax + li], s_g[2 * hmax + li], s_g[3 * hmax + li]};
+            const D4 gyi = {s_g[4 * hmax + li], s_g[5 * hmax + li], s_g[6 * hmax + li],
+                            s_g[7 * hmax + li]};
             dq[0] -= 0.5 * (dx * (gxi.x - gx0.x) + dy * (gyi.x - gy0.x));
             dq[1] -= 0.5 * (dx * (gxi.y - gx0.y) + dy * (gyi.y - gy0.y));
             dq[2] -= 0.5 * (dx * (gxi.z - gx0.z) + dy * (gyi.z - gy0.z));
@@ -562,8 +580,8 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad_tiled(
     const double eps2 = kh * kh * kh;
     double fn[4] = {1, 1, 1, 1}, fd[4] = {1, 1, 1, 1};  // running minimum fn/fd
     for (int32_t e = e0 + lane; e < e1; e += 4) {
-        const D2 ri = s_r[lnbr[e]];
-        const double dx = ri.x - r0.x, dy = ri.y - r0.y;
+        const int li = lnbr[e];
+        const double dx = s_x[li] - r0.x, dy = s_y[li] - r0.y;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const double d2 = -0.5 * (dx * gx[v] + dy * gy[v]);
@@ -1545,8 +1563,8 @@ static void qgrad_tiled(State& s) {
     const double K = s.prm.limiter_k;
     const int m = s.prm.inner_iters;
     const bool lim = s.prm.limiter != 0;
-    const size_t lds0 = (size_t)c.tile_hmax * (sizeof(D4) + sizeof(D2));
-    const size_t lds1 = (size_t)c.tile_hmax * (3 * sizeof(D4) + sizeof(D2));
+    const size_t lds0 = (size_t)c.tile_hmax * 6 * sizeof(double);
+    const size_t lds1 = (size_t)c.tile_hmax * 14 * sizeof(double);
     if (m == 0 && lim)
         hipLaunchKernelGGL((k_qgrad_tiled<false, true>), g, b, lds0, s.stream, c.n, K, c.xy, c.off,
                            c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom, c.comp, s.active,
