@@ -350,44 +350,55 @@ MLP_FLOP_PER_ROW = 2 * (5 * 128 + 2 * 128 * 128 + 128 * 4)   # 67,840
 PEAK_BF16_TFLOPS = 2500.0
 
 
-def warm_start_run(lk, cloudgen, train_steps: int, held_out: int):
-    """Learned warm start, scaled down from the 640k-point / 512-field recipe:
-    converged fields of 32 conditions on 4 clouds of 20k-60k points (mixed
-    precision, to 1e-6) train the network; `held_out` conditions on a held-out
-    640 x 256 cloud are then solved to 1e-8 of each condition's free-stream
-    residual three ways: the plain FP64 solver one condition at a time from the
-    free stream (baseline); the mixed-precision batch from the free stream; the
-    mixed-precision batch from the warm start."""
+# Warm-start leg sizes, scaled down from the recipe's 512 training fields and 32
+# held-out conditions on a 640,000-point cloud to fit a benchmark job:
+# (training conditions, training clouds, their size range, held-out cloud).
+WARM_SCALES = {
+    "default": (32, 4, 20_000, 60_000, (640, 256)),
+    "large": (64, 8, 40_000, 80_000, (1280, 500)),
+}
+
+
+def warm_start_run(lk, cloudgen, train_steps: int, held_out: int, scale: str = "default"):
+    """Learned warm start, scaled down from the 640k-point / 512-field recipe
+    (WARM_SCALES): converged fields of the training conditions on small clouds
+    (the batched solver in mixed precision, to 1e-6) train the network;
+    `held_out` conditions on a held-out cloud are then solved to 1e-8 of each
+    condition's free-stream residual three ways: the plain FP64 solver one
+    condition at a time from the free stream (baseline); the mixed-precision
+    batch from the free stream; the mixed-precision batch from the warm start."""
     import numpy as np
     import torch
-    clouds = cloudgen.batch_clouds(seed=40, count=4, nmin=20_000, nmax=60_000)
+    n_train, n_clouds, nmin, nmax, (hw, hk) = WARM_SCALES[scale]
+    clouds = cloudgen.batch_clouds(seed=40, count=n_clouds, nmin=nmin, nmax=nmax)
     gcs = [lk.Cloud(c) for c in clouds]
-    mach, aoa = cloudgen.batch_conditions(seed=41, count=32)
+    mach, aoa = cloudgen.batch_conditions(seed=41, count=n_train)
     prm = lk.default_params(cfl=CFL, inner_iters=INNER, precision=lk.MIXED, limiter=LIMITER,
                             limiter_k=LIMITER_K, check_every=50, tol_rel=1e-6, max_iters=40000)
     t0 = time.perf_counter()
-    b = lk.Batch(gcs, np.arange(32) % 4, mach, aoa, prm)
+    b = lk.Batch(gcs, np.arange(n_train) % n_clouds, mach, aoa, prm)
     reps, _ = b.solve()
     ok = [r["status"] == 0 for r in reps]
     X, T = b.features(targets=True)
     # rows of conditions that did not converge are left out of the training set
-    keep = torch.cat([torch.full((b.sizes[k],), bool(ok[k]), device="cuda") for k in range(32)])
+    keep = torch.cat([torch.full((b.sizes[k],), bool(ok[k]), device="cuda")
+                      for k in range(n_train)])
     X, T = X[keep].contiguous(), T[keep].contiguous()
     b.close()
     gen_s = time.perf_counter() - t0
-    print(f"# warm start: {int(sum(ok))}/32 training fields in {gen_s:.1f} s", file=sys.stderr,
-          flush=True)
+    print(f"# warm start: {int(sum(ok))}/{n_train} training fields in {gen_s:.1f} s",
+          file=sys.stderr, flush=True)
     net = lk.MLP(seed=11, max_rows=8192)
     hist, train_s = net.train(X, T, steps=train_steps, batch=8192, lr=3e-3, lr_final=1e-5, seed=13)
     rows = X.shape[0]
     print(f"# warm start: trained {train_steps} steps in {train_s:.1f} s", file=sys.stderr,
           flush=True)
 
-    held = cloudgen.ogrid(640, 256, r=None, t=0.12, name="heldout640x256")
+    held = cloudgen.ogrid(hw, hk, r=None, t=0.12, name=f"heldout{hw}x{hk}")
     gh = lk.Cloud(held)
     hm, ha = cloudgen.batch_conditions(seed=42, count=held_out)
     common = dict(cfl=CFL, inner_iters=INNER, limiter=LIMITER, limiter_k=LIMITER_K,
-                  check_every=50, tol_rel=1e-8, max_iters=60000)
+                  check_every=50, tol_rel=1e-8, max_iters=150000)
     # (a) baseline: plain FP64 solver, one condition at a time, free-stream start
     base = []
     for m, a_ in zip(hm, ha):
@@ -418,7 +429,8 @@ def warm_start_run(lk, cloudgen, train_steps: int, held_out: int):
     bw.close()
     net.close()
     return {
-        "training": {"clouds": [c.n for c in clouds], "conditions": 32,
+        "scale": scale,
+        "training": {"clouds": [c.n for c in clouds], "conditions": n_train,
                      "converged": int(sum(ok)), "rows": rows, "field_gen_s": gen_s,
                      "steps": train_steps, "batch": 8192, "train_s": train_s,
                      "loss_first": float(hist[:10].mean()), "loss_last": float(hist[-50:].mean()),
@@ -577,6 +589,8 @@ def parse_args(argv=None):
                     help="training steps of the warm-start leg (0 skips it)")
     ap.add_argument("--warm-held-out", type=int, default=4,
                     help="held-out conditions of the warm-start leg")
+    ap.add_argument("--warm-scale", default="default", choices=sorted(WARM_SCALES),
+                    help="training and held-out sizes of the warm-start leg")
     ap.add_argument("--batch-converge-iters", type=int, default=0,
                     help="solve the 64-condition batch to 1e-8 with this cap (0 skips)")
     ap.add_argument("--batch-converge-seconds", type=float, default=0.0,
@@ -701,7 +715,8 @@ def main(argv=None):
         leg("cloud_2621440_to_1e-8", config3_run, lk, cloudgen, args.config3_iters,
             args.config3_precisions.split(","))
     if args.warm_steps > 0:
-        leg("warm_start", warm_start_run, lk, cloudgen, args.warm_steps, args.warm_held_out)
+        leg("warm_start", warm_start_run, lk, cloudgen, args.warm_steps, args.warm_held_out,
+            args.warm_scale)
     cpu = None
     if args.cpu_seconds > 0:
         t = time.perf_counter()
