@@ -233,7 +233,7 @@ def batch_run(lk, cloudgen, iters):
            "colour_phases": b.n_colours, "iters": iters, "seconds": tot,
            "point_iters_per_s": pts / tot, "iteration_gbs": moved / tot / 1e9,
            "iteration_frac_hbm": moved / tot / 1e9 / PEAK_HBM_GBS,
-           "lanes": {"sweep": lanes[0], "residual": lanes[1]},
+           "lanes": {"sweep": lanes[0], "residual": lanes[1], "qgrad": lanes[2]},
            "failed": int(sum(r["status"] == lk.ERR_NONPHYSICAL for r in reps)),
            "median_res_drop": float(np.median([r["res_final"] / r["res_fs"] for r in reps]))}
     b.close()
@@ -300,7 +300,7 @@ def batch_converge(lk, cloudgen, max_iters, max_seconds=0.0):
                             limiter_k=LIMITER_K, check_every=100, tol_rel=1e-8)
     b = lk.Batch(gcs, np.arange(64) % 8, mach, aoa, prm)
     lanes = b.autotune(2)
-    prm.sweep_lanes, prm.residual_lanes = lanes[0], lanes[1]
+    prm.sweep_lanes, prm.residual_lanes, prm.qgrad_lanes = lanes
     b.set_cfl_control(CFL_WINDOW, CFL_FACTOR, CFL_MIN)
     done, tot = solve_chunked(b, prm, max_iters, 64, "batch to 1e-8", max_seconds)
     pts = sum(d["iters"] * b.sizes[k] for k, d in enumerate(done))
@@ -309,7 +309,8 @@ def batch_converge(lk, cloudgen, max_iters, max_seconds=0.0):
            "cfl_control": {"window": CFL_WINDOW, "factor": CFL_FACTOR, "cfl_min": CFL_MIN},
            "seconds_until_all_retired": max(conv) if len(conv) == 64 else None,
            "seconds_run": tot, "converged": len(conv),
-           "point_iters_per_s": pts / tot, "lanes": {"sweep": lanes[0], "residual": lanes[1]},
+           "point_iters_per_s": pts / tot,
+           "lanes": {"sweep": lanes[0], "residual": lanes[1], "qgrad": lanes[2]},
            "iters": [d["iters"] for d in done],
            "final_cfl": [float(f"{c:.3g}") for c in b.get_cfl()],
            "res_drop": [float(f"{d['res_drop']:.3e}") for d in done],

@@ -125,6 +125,13 @@ typedef struct {
                                (eq. 34-35; Anandhanarayanan variant); outer
                                points are then swept and updated like the
                                others and stay out of the residual norm */
+    int32_t qgrad_lanes;    /* q-derivative kernels: 0 = library choice (each
+                               64-point tile stages its points' neighbours in
+                               LDS, four lanes per point, when every tile's
+                               neighbour list fits; direct gathers otherwise);
+                               1, 2, 4, 8 = direct gathers with that many
+                               lanes per point.  0 and 4 give the same results
+                               bit for bit. */
 } lskum_params;
 
 typedef struct {
@@ -310,10 +317,13 @@ int lskum_batch_set_U(lskum_batch* b, int32_t cond, const double* U, int on_devi
 
 /* Autotuner: times `iters` iterations with 1, 2, 4, 8 (and, for the sweeps,
  * 16) lanes per point and keeps the fastest lane count for the sweep and for
- * the residual kernels (written to *sweep_lanes, *residual_lanes).  The batch's state is
- * restored afterwards. */
+ * the residual kernels, and times the q-derivative passes in their LDS-tiled
+ * form and with direct gathers at 1, 2, 4, 8 lanes and keeps the fastest
+ * (written to *sweep_lanes, *residual_lanes, *qgrad_lanes as lskum_params
+ * values; any of the three may be NULL).  The batch's state is restored
+ * afterwards. */
 int lskum_batch_autotune(lskum_batch* b, int32_t iters, int32_t* sweep_lanes,
-                         int32_t* residual_lanes);
+                         int32_t* residual_lanes, int32_t* qgrad_lanes);
 
 void lskum_batch_destroy(lskum_batch* b);
 

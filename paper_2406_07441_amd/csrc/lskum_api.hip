@@ -406,6 +406,8 @@ int check_params(const lskum_params* p) {
         return fail(LSKUM_ERR_ARG, "variant must be LSKUM_ANANDH or LSKUM_MANISH");
     if (p->precision == 1 && p->jvp_mode == 1)
         return fail(LSKUM_ERR_ARG, "mixed precision supports the exact Jacobian products only");
+    if (!lanes_ok(p->qgrad_lanes))
+        return fail(LSKUM_ERR_ARG, "qgrad_lanes must be 0, 1, 2, 4 or 8");
     if (p->farfield != 0 && p->farfield != 1)
         return fail(LSKUM_ERR_ARG,
                     "farfield must be LSKUM_FARFIELD_DIRICHLET or LSKUM_FARFIELD_KINETIC");
@@ -416,7 +418,8 @@ lskum::Params to_params(const lskum_params* p) {
     return lskum::Params{p->gamma,       p->cfl,            p->inner_iters, p->jvp_mode,
                          p->precision,   p->check_every,    p->tol_rel,     p->max_iters,
                          p->sweep_lanes, p->residual_lanes, p->limiter,     p->limiter_k,
-                         p->variant,     p->scheme,         p->order,       p->farfield};
+                         p->variant,     p->scheme,         p->order,       p->farfield,
+                         p->qgrad_lanes};
 }
 
 // Lanes per point: the caller's choice, else 8 for the latency-bound sweeps
@@ -425,6 +428,8 @@ lskum::Params to_params(const lskum_params* p) {
 void apply_lanes(lskum::State& s) {
     s.sweep_lanes = s.prm.sweep_lanes ? s.prm.sweep_lanes : 8;
     s.residual_lanes = s.prm.residual_lanes ? s.prm.residual_lanes : 2;
+    s.qgrad_tiled = s.prm.qgrad_lanes == 0;
+    s.qgrad_lanes = s.prm.qgrad_lanes ? s.prm.qgrad_lanes : 4;
 }
 
 int read_flags(lskum::State& s, int32_t* h) {
@@ -934,7 +939,8 @@ int lskum_state_set_params(lskum_state* so, const lskum_params* prm) {
                               np.sweep_lanes == s.prm.sweep_lanes &&
                               np.residual_lanes == s.prm.residual_lanes &&
                               np.variant == s.prm.variant && np.scheme == s.prm.scheme &&
-                              np.order == s.prm.order && np.farfield == s.prm.farfield;
+                              np.order == s.prm.order && np.farfield == s.prm.farfield &&
+                              np.qgrad_lanes == s.prm.qgrad_lanes;
     if (s.graph && !same_kernels) {
         (void)hipGraphExecDestroy(s.graph);
         s.graph = nullptr;
@@ -1399,7 +1405,7 @@ int lskum_batch_set_U(lskum_batch* b, int32_t cond, const double* U, int on_devi
 // and the residual kernels on the batch itself and keeps the fastest of each.
 // The batch's state is saved before and restored after the trial steps.
 int lskum_batch_autotune(lskum_batch* b, int32_t iters, int32_t* sweep_lanes,
-                         int32_t* residual_lanes) {
+                         int32_t* residual_lanes, int32_t* qgrad_lanes) {
     if (!b || iters < 1) return fail(LSKUM_ERR_ARG, "invalid argument");
     lskum::State& s = b->s;
     std::vector<lskum::D4> saved(b->c.n);
@@ -1407,24 +1413,31 @@ int lskum_batch_autotune(lskum_batch* b, int32_t iters, int32_t* sweep_lanes,
                           s.stream));
     HIPCHK(hipStreamSynchronize(s.stream));
     const lskum::Params keep = s.prm;
+    // candidate k: sweep lanes cands[k], residual and direct q-derivative
+    // lanes cands[k] (k < 4); the LDS-tiled q-derivative form is a sixth
+    // candidate of its own
     const int cands[5] = {1, 2, 4, 8, 16};
-    double best_sw = 1e300, best_rs = 1e300;
-    int bsw = 8, brs = 2;
+    double best_sw = 1e300, best_rs = 1e300, best_qg = 1e300;
+    int bsw = 8, brs = 2, bqg = 0;
     lskum_state tmp;
     std::swap(tmp.s, b->s);
     int rc = LSKUM_OK;
-    for (int li = 0; li < 5 && rc == LSKUM_OK; ++li) {
-        tmp.s.prm.sweep_lanes = cands[li];
-        tmp.s.prm.residual_lanes = li < 4 ? cands[li] : 8;
+    for (int li = 0; li < 6 && rc == LSKUM_OK; ++li) {
+        const bool tiles = li == 5;
+        if (tiles && b->c.ntile == 0) break;
+        tmp.s.prm.sweep_lanes = li < 5 ? cands[li] : bsw;
+        tmp.s.prm.residual_lanes = li < 4 ? cands[li] : brs;
+        tmp.s.prm.qgrad_lanes = tiles ? 0 : (li < 4 ? cands[li] : 4);
         apply_lanes(tmp.s);
-        double ms[6], sw = 0, rs = 0;
+        double ms[6], sw = 0, rs = 0, qg = 0;
         for (int it = 0; it < iters + 1 && rc == LSKUM_OK; ++it) {
             rc = lskum_step_timed(&tmp, ms);
             if (it == 0) continue;  // warm-up
-            sw += ms[3] + ms[4];
+            qg += ms[0];
             rs += ms[1];
+            sw += ms[3] + ms[4];
         }
-        if (sw < best_sw) {
+        if (li < 5 && sw < best_sw) {
             best_sw = sw;
             bsw = cands[li];
         }
@@ -1432,11 +1445,16 @@ int lskum_batch_autotune(lskum_batch* b, int32_t iters, int32_t* sweep_lanes,
             best_rs = rs;
             brs = cands[li];
         }
+        if ((li < 4 || tiles) && qg < best_qg) {
+            best_qg = qg;
+            bqg = tiles ? 0 : cands[li];
+        }
     }
     std::swap(tmp.s, b->s);
     s.prm = keep;
     s.prm.sweep_lanes = bsw;
     s.prm.residual_lanes = brs;
+    s.prm.qgrad_lanes = bqg;
     apply_lanes(s);
     if (s.graph) {
         (void)hipGraphExecDestroy(s.graph);
@@ -1449,6 +1467,7 @@ int lskum_batch_autotune(lskum_batch* b, int32_t iters, int32_t* sweep_lanes,
     if (rc) return rc;
     if (sweep_lanes) *sweep_lanes = bsw;
     if (residual_lanes) *residual_lanes = brs;
+    if (qgrad_lanes) *qgrad_lanes = bqg;
     return LSKUM_OK;
 }
 

@@ -1591,7 +1591,7 @@ static void qgrad_tiled(State& s) {
 }
 
 hipError_t launch_q_derivatives(State& s) {
-    if (s.cloud->ntile > 0 && s.qgrad_lanes == 4) {
+    if (s.qgrad_tiled && s.cloud->ntile > 0) {
         qgrad_tiled(s);
         return hipGetLastError();
     }

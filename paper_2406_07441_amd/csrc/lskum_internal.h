@@ -140,6 +140,7 @@ struct Params {
     int scheme;   // 0 implicit (LU-SGS), 1 explicit
     int order;    // 0 colour order (Algorithm 6), 1 wall points first (Algorithm 5)
     int farfield; // 0 outer points at the free stream, 1 kinetic far field
+    int qgrad_lanes;  // 0 LDS tiles (library choice), else direct gathers with these lanes
 };
 
 // Device work arrays of one flow state.
@@ -167,6 +168,7 @@ struct State {
     int sweep_lanes = 4;         // lanes per point in the sweep kernels (1, 2, 4 or 8)
     int residual_lanes = 4;      // lanes per point in the residual kernel (1, 2, 4 or 8)
     int qgrad_lanes = 4;         // lanes per point in the q-derivative kernels
+    bool qgrad_tiled = true;     // LDS-tiled q-derivative passes when the cloud has tiles
     double res_fs = 0.0;
     // fp64
     D4* U = nullptr;

@@ -40,7 +40,7 @@ class Params(C.Structure):
                 ("tol_rel", C.c_double), ("max_iters", C.c_int32), ("sweep_lanes", C.c_int32),
                 ("residual_lanes", C.c_int32), ("limiter", C.c_int32), ("limiter_k", C.c_double),
                 ("variant", C.c_int32), ("scheme", C.c_int32), ("order", C.c_int32),
-                ("farfield", C.c_int32)]
+                ("farfield", C.c_int32), ("qgrad_lanes", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -86,7 +86,8 @@ _SIGS = {
     "lskum_batch_step_timed": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lskum_batch_get_U": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int]),
     "lskum_batch_set_U": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int]),
-    "lskum_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "lskum_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                       C.c_void_p]),
     "lskum_batch_destroy": (None, [C.c_void_p]),
     "lskum_mlp_create": (C.c_int, [C.c_uint64, C.c_int64, C.c_void_p, C.c_void_p]),
     "lskum_mlp_destroy": (None, [C.c_void_p]),
@@ -401,10 +402,14 @@ class Batch:
         _check(lib().lskum_batch_set_U(self.h, int(k), _ptr(U), 0))
 
     def autotune(self, iters: int = 3):
-        sl, rl = C.c_int32(), C.c_int32()
-        _check(lib().lskum_batch_autotune(self.h, int(iters), C.byref(sl), C.byref(rl)))
+        """Times the lane counts and the q-derivative kernel form and keeps the
+        fastest; returns (sweep_lanes, residual_lanes, qgrad_lanes)."""
+        sl, rl, ql = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().lskum_batch_autotune(self.h, int(iters), C.byref(sl), C.byref(rl),
+                                          C.byref(ql)))
         self.params.sweep_lanes, self.params.residual_lanes = sl.value, rl.value
-        return sl.value, rl.value
+        self.params.qgrad_lanes = ql.value
+        return sl.value, rl.value, ql.value
 
     def features(self, targets: bool = False):
         """Features [n_points][5] (and targets [n_points][4]) of all conditions."""

@@ -100,8 +100,8 @@ def test_batch_autotune_keeps_state(lk, setup):
     prm = lk.default_params(cfl=50.0)
     bat = lk.Batch([ga, gb], [0, 1], [0.5, 0.6], [1.0, 2.0], prm)
     U0 = [bat.get_U(0), bat.get_U(1)]
-    sl, rl = bat.autotune(iters=2)
-    assert sl in (1, 2, 4, 8, 16) and rl in (1, 2, 4, 8)
+    sl, rl, ql = bat.autotune(iters=2)
+    assert sl in (1, 2, 4, 8, 16) and rl in (1, 2, 4, 8) and ql in (0, 1, 2, 4, 8)
     assert np.array_equal(bat.get_U(0), U0[0]) and np.array_equal(bat.get_U(1), U0[1])
 
 
