@@ -66,32 +66,6 @@ __device__ __forceinline__ double dot_nc(double ax, double ay, double bx, double
     return r + s;
 }
 
-// erf of a split flux's S = u_d sqrt(beta).  In these flows |S| stays below
-// about 1.3 (S is the velocity component over sqrt(2 p / rho), i.e. about
-// 0.84 times a Mach number): there erf is evaluated by its Maclaurin series
-// (Abramowitz and Stegun 7.1.5), 2/sqrt(pi) sum_n (-1)^n x^(2n+1) / (n! (2n+1)),
-// 23 terms in Horner form -- truncation below 1e-17, rounding within 2 ulp,
-// and no branches, where the library erf switches between three
-// approximations (two with a division) that diverge within a wavefront.
-// Larger |S| goes to the library erf.
-__device__ __forceinline__ double erf_split(double x) {
-    constexpr double c[23] = {
-        1.12837916709551256e+00,  -3.76126389031837483e-01, 1.12837916709551261e-01,
-        -2.68661706451312488e-02, 5.22397762544218706e-03,  -8.54832702345085225e-04,
-        1.20553329817896636e-04,  -1.49256503584062520e-05, 1.64621143658892463e-06,
-        -1.63658446912349245e-07, 1.48071928158792176e-08,  -1.22905553017179263e-09,
-        9.42275906465041125e-11,  -6.71136685516411048e-12, 4.46322426328647698e-13,
-        -2.78351620721092150e-14, 1.63426140953671520e-15,  -9.06397084280867155e-17,
-        4.76334804051506831e-18,  -2.37845988527742927e-19, 1.13121872592463106e-20,
-        -5.13620905458581091e-22, 2.23087868027464496e-23};
-    if (!(fabs(x) < 1.3)) return erf(x);
-    const double x2 = x * x;
-    double p = c[22];
-#pragma unroll
-    for (int n = 21; n >= 0; --n) p = fma(p, x2, c[n]);
-    return x * p;
-}
-
 struct Prim {
     double rho, u1, u2, p, sb, isb, rhoE;  // sb = sqrt(beta), isb = 1/sqrt(beta)
 };
@@ -126,7 +100,7 @@ __device__ __forceinline__ void split_flux(const Prim& w, double dx, double dy, 
     (void)inv_gm1;
     const double ud = DIR == 0 ? w.u1 : (DIR == 1 ? w.u2 : w.u1 * dx + w.u2 * dy);
     const double S = ud * w.sb;
-    const double A = 0.5 * (1.0 + sg * erf_split(S));
+    const double A = 0.5 * (1.0 + sg * erf(S));
     const double B = exp(-(S * S)) * (0.5 * kInvSqrtPi) * w.isb;
     const double mass = w.rho * (ud * A + sg * B);
     const double pA = w.p * A;
@@ -839,7 +813,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(
             const double sb = sqrt(beta);
             const double sx = u1 * sb, sy = u2 * sb;
             const D4 j0 = {rho, u1, u2, pr};
-            const D4 j2 = {erf_split(sx), exp(-(sx * sx)), erf_split(sy), exp(-(sy * sy))};
+            const D4 j2 = {erf(sx), exp(-(sx * sx)), erf(sy), exp(-(sy * sy))};
             const double a = sqrt(gamma * pr / rho);
             const PointGeom& G = geom[p];
             const double dt = cfl[comp ? comp[p] : 0] * G.lsq.w / (sqrt(usq) + a);
@@ -1118,7 +1092,7 @@ __device__ __forceinline__ void jvp_fluxdiff(const Lin<double>& L, double er, do
     W.sb = sqrt(W.beta);
     const double S = (W.u1 * dx + W.u2 * dy) * W.sb;
     double Ga[4], Gb[4];
-    flux_lin(W, erf_split(S), exp(-(S * S)), dx, dy, sg, inv_gm1, Ga);
+    flux_lin(W, erf(S), exp(-(S * S)), dx, dy, sg, inv_gm1, Ga);
     flux_lin(L, er, g, dx, dy, sg, inv_gm1, Gb);
 #pragma unroll
     for (int v = 0; v < 4; ++v) J[v] = Ga[v] - Gb[v];
@@ -1231,7 +1205,7 @@ __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<
             const double sg = (cd & kSwNegA) ? 1.0 : -1.0;
             if constexpr (MODE == 1) {
                 const double S = (L.u1 * t.x + L.u2 * t.y) * L.sb;
-                jvp_fluxdiff(L, erf_split(S), exp(-(S * S)), U[i], t.x, t.y, sg, dv, gamma,
+                jvp_fluxdiff(L, erf(S), exp(-(S * S)), U[i], t.x, t.y, sg, dv, gamma,
                              1.0 / (gamma - 1.0), J);
             } else {
                 const T S = (L.u1 * T(t.x) + L.u2 * T(t.y)) * L.sb;
@@ -1245,7 +1219,7 @@ __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<
             const double sg = (cd & kSwNegB) ? 1.0 : -1.0;
             if constexpr (MODE == 1) {
                 const double S = (-L.u1 * t.y + L.u2 * t.x) * L.sb;
-                jvp_fluxdiff(L, erf_split(S), exp(-(S * S)), U[i], -t.y, t.x, sg, dv, gamma,
+                jvp_fluxdiff(L, erf(S), exp(-(S * S)), U[i], -t.y, t.x, sg, dv, gamma,
                              1.0 / (gamma - 1.0), J);
             } else {
                 const T S = (-L.u1 * T(t.y) + L.u2 * T(t.x)) * L.sb;
