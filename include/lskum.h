@@ -130,8 +130,8 @@ typedef struct {
                                LDS, four lanes per point, when every tile's
                                neighbour list fits; direct gathers otherwise);
                                1, 2, 4, 8 = direct gathers with that many
-                               lanes per point.  0 and 4 give the same results
-                               bit for bit. */
+                               lanes per point (the same sums; the forms can
+                               differ in the last bits). */
 } lskum_params;
 
 typedef struct {
