@@ -407,6 +407,8 @@ def warm_start_run(lk, cloudgen, train_steps: int, held_out: int, scale: str = "
         r = st.solve()
         base.append(r.as_dict())
         st.close()
+        print(f"# warm start: FP64 baseline M {float(m):.3f} AoA {float(a_):.2f}: {r.iters} "
+              f"iterations, {r.seconds:.1f} s", file=sys.stderr, flush=True)
     base_s = sum(r["seconds"] for r in base)
     print(f"# warm start: FP64 baseline {base_s:.1f} s", file=sys.stderr, flush=True)
     cc = np.zeros(held_out, np.int32)
@@ -415,6 +417,8 @@ def warm_start_run(lk, cloudgen, train_steps: int, held_out: int, scale: str = "
     bf = lk.Batch([gh], cc, hm, ha, prm_mx)
     r_bf, t_bf = bf.solve()
     bf.close()
+    print(f"# warm start: mixed batch from the free stream {t_bf:.1f} s", file=sys.stderr,
+          flush=True)
     # (c) mixed-precision batch, warm start (inference and residual check inside the timing)
     bw = lk.Batch([gh], cc, hm, ha, prm_mx)
     Xh = bw.features()
