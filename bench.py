@@ -264,7 +264,7 @@ def solve_chunked(obj, prm, max_iters, n_cond, label, max_seconds=0.0):
         for k, r in enumerate(reps):
             if done[k] is None and r["status"] == 0:
                 done[k] = {"iters": total_it + r["iters"], "seconds": total_s + r["seconds"],
-                           "status": 0, "cl": r["cl"], "cd": r["cd"],
+                           "status": 0, "cl": r["cl"], "cd": r["cd"], "res_fs": r["res_fs"],
                            "res_drop": r["res_final"] / r["res_fs"]}
         total_it += prm.max_iters
         total_s += secs
@@ -276,7 +276,7 @@ def solve_chunked(obj, prm, max_iters, n_cond, label, max_seconds=0.0):
     for k in range(n_cond):
         if done[k] is None:
             done[k] = {"iters": total_it, "seconds": total_s, "status": last[k]["status"],
-                       "cl": last[k]["cl"], "cd": last[k]["cd"],
+                       "cl": last[k]["cl"], "cd": last[k]["cd"], "res_fs": last[k]["res_fs"],
                        "res_drop": last[k]["res_final"] / last[k]["res_fs"]}
     return done, total_s
 
@@ -415,7 +415,7 @@ def warm_start_run(lk, cloudgen, train_steps: int, held_out: int, scale: str = "
     prm_mx = lk.default_params(precision=lk.MIXED, **common)
     # (b) mixed-precision batch, free-stream start
     bf = lk.Batch([gh], cc, hm, ha, prm_mx)
-    r_bf, t_bf = bf.solve()
+    r_bf, t_bf = solve_chunked(bf, prm_mx, common["max_iters"], held_out, "held-out mixed batch")
     bf.close()
     print(f"# warm start: mixed batch from the free stream {t_bf:.1f} s", file=sys.stderr,
           flush=True)
@@ -430,7 +430,8 @@ def warm_start_run(lk, cloudgen, train_steps: int, held_out: int, scale: str = "
     tw = time.perf_counter()
     fb, res_w = net.warm_start(bw)
     warm_s = time.perf_counter() - tw
-    r_bw, t_bw = bw.solve()
+    r_bw, t_bw = solve_chunked(bw, prm_mx, common["max_iters"], held_out,
+                               "held-out warm-started batch")
     bw.close()
     net.close()
     return {
