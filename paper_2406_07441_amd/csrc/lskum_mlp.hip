@@ -16,7 +16,6 @@
 // bf16 before their products; everything else is fp32.
 #include "lskum_mlp.h"
 
-#include <algorithm>
 #include <cmath>
 
 namespace lskum {
@@ -30,25 +29,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 constexpr float kInvSqrt2 = 0.70710678118654752f;
 constexpr float kInvSqrt2Pi = 0.39894228040143268f;
 
-
-// GELU of the forward pass with erfc from Hastings' rational approximation
-// (Abramowitz and Stegun 7.1.26): erfc(x) = t (a1 + t (a2 + ... + t a5))
-// exp(-x^2), t = 1/(1 + p x), x = |z|/sqrt 2 >= 0; then
-// GELU(z) = z - z erfc(x)/2 for z >= 0 and z erfc(x)/2 for z < 0, so the
-// negative tail keeps its relative accuracy (below 0.07% for z > -4.2, where
-// bfloat16's own spacing is 0.4%; absolute error below 1.5e-7 everywhere).
-// Free of the branches of a full-precision erf, which diverge within a
-// wavefront whose pre-activations fall in different ranges.
-__device__ __forceinline__ float gelu_fwd(float z) {
-    const float x = fabsf(z) * kInvSqrt2;
-    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
-    const float poly =
-        t * (0.254829592f +
-             t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
-    const float h = 0.5f * z * (poly * __expf(-x * x));
-    return z >= 0.0f ? z - h : h;
-}
-
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * kInvSqrt2)); }
 __device__ __forceinline__ float gelu_prime(float z) {
     return 0.5f * (1.0f + erff(z * kInvSqrt2)) + z * expf(-0.5f * z * z) * kInvSqrt2Pi;
 }
@@ -86,7 +67,6 @@ __device__ __forceinline__ f32x4 tile_mma(const __bf16* __restrict__ A, int64_t 
 // loss terms dY, se; otherwise Y.
 constexpr int kLdsW = kWidth + 8;
 constexpr int kFwdWaves = 8;
-constexpr int kFwdBlocks = 256;  // MI355X compute units
 
 template <bool TRAIN>
 __global__ void __launch_bounds__(64 * kFwdWaves) k_mlp_forward(
@@ -108,14 +88,11 @@ __global__ void __launch_bounds__(64 * kFwdWaves) k_mlp_forward(
     }
     __syncthreads();
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int row0 = (blockIdx.x * kFwdWaves + w) * 16;
+    if (row0 >= M) return;  // no barrier follows: the tile's work is wave-local
     const int r = l & 15, g = l >> 4, kq = 8 * g;
-    __bf16* hs = sH[w];
-    // the block walks row tiles of 16 x kFwdWaves rows with the weights staged
-    // once; no barrier follows, a tile's work is wave-local
-    for (int tile = blockIdx.x;; tile += gridDim.x) {
-    const int row0 = (tile * kFwdWaves + w) * 16;
-    if (row0 >= M) return;
     const int64_t m = row0 + r;
+    __bf16* hs = sH[w];
     // ---- layer 1 (5 -> 128) in the A-operand layout
     float x[kIn];
 #pragma unroll
@@ -135,7 +112,7 @@ __global__ void __launch_bounds__(64 * kFwdWaves) k_mlp_forward(
 #pragma unroll
             for (int f = 0; f < kIn; ++f) z += x[f] * (float)W1[n * kIn + f];
             zz[j] = z;
-            a[s][j] = (__bf16)gelu_fwd(z);
+            a[s][j] = (__bf16)gelu(z);
         }
         if (TRAIN) {
             float* z1 = Z1 + m * kWidth + 32 * s + kq;
@@ -170,7 +147,7 @@ __global__ void __launch_bounds__(64 * kFwdWaves) k_mlp_forward(
             for (int t = 0; t < 4; ++t) {
                 const int rr = 4 * g + t;
                 const float z = acc[c][t] + bc;
-                const __bf16 h = (__bf16)gelu_fwd(z);
+                const __bf16 h = (__bf16)gelu(z);
                 acc[c][t] = (float)h;  // keep the rounded activation for layer 4
                 hs[rr * kLdsW + col] = h;
                 if (TRAIN) {
@@ -226,7 +203,6 @@ __global__ void __launch_bounds__(64 * kFwdWaves) k_mlp_forward(
                 }
             }
         }
-    }
     }
 }
 
@@ -538,9 +514,7 @@ hipError_t refresh_weights(Net& net) {
 hipError_t forward(Net& net, const float* X, int M, int Mvalid, const float* T, float* Y) {
     hipStream_t st = net.stream;
     const float* th = net.theta;
-    // one block per compute unit at most: each block stages W2, W3 once and
-    // walks its share of the row tiles
-    const dim3 grid(std::min(nblk(M, 16 * kFwdWaves), (unsigned)kFwdBlocks)), block(64 * kFwdWaves);
+    const dim3 grid(nblk(M, 16 * kFwdWaves)), block(64 * kFwdWaves);
     if (T)
         hipLaunchKernelGGL(k_mlp_forward<true>, grid, block, 0, st, M, Mvalid, X, net.W1b,
                            th + kOffB1, net.W2b, th + kOffB2, net.W3b, th + kOffB3, net.W4b,
