@@ -422,11 +422,13 @@ def warm_start_run(lk, cloudgen, train_steps: int, held_out: int, scale: str = "
     # (c) mixed-precision batch, warm start (inference and residual check inside the timing)
     bw = lk.Batch([gh], cc, hm, ha, prm_mx)
     Xh = bw.features()
+    net.forward(Xh)   # the first call loads the kernel; the timing takes the next five
     torch.cuda.synchronize()
     ti = time.perf_counter()
-    net.forward(Xh)
+    for _ in range(5):
+        net.forward(Xh)
     torch.cuda.synchronize()
-    infer_s = time.perf_counter() - ti
+    infer_s = (time.perf_counter() - ti) / 5
     tw = time.perf_counter()
     fb, res_w = net.warm_start(bw)
     warm_s = time.perf_counter() - tw
