@@ -28,14 +28,19 @@
 //
 // Pins (tests/test_oracle_*.py): split fluxes against quadrature of the
 // half-range Maxwellian moments and G+ + G- = G (eq. 2); tangents against
-// central differences and against the unsplit Jacobian closed form
-// (Listing 3); LS weights reproduce linear fields; the inner iterations keep
-// exact quadratic derivatives; uniform flow gives R == 0; the sweeps equal a
-// dense (D+U)^-1 D (D+L)^-1 (-R) solve; colouring validity; forces vanish for
-// uniform pressure and lift vanishes at zero incidence on the symmetric profile.
-// Parity unpinned (no external value exists): the boundary treatment,
-// the time step rule, the residual norm, the tolerance anchor and the force
-// integration rule are readings, pinned only by invariants.
+// central differences and, summed over the halves, against the complex-step
+// derivative of the unsplit flux (eq. 2); LS weights reproduce linear fields;
+// the inner iterations keep exact quadratic derivatives; uniform flow gives
+// R == 0; the sweeps equal a dense (D+U)^-1 D (D+L)^-1 (-R) solve; colouring
+// validity; the Anandhanarayanan diagonal in closed form at rest and at a
+// supersonic split velocity (eq. 34-35); forces of a linear wall pressure by
+// the divergence theorem (sign and projection), zero lift at zero incidence
+// and positive lift at positive incidence; the kinetic far field: uniform flow
+// a fixed point, the ghost's flux difference exactly, its diagonal in closed
+// form.
+// Parity unpinned (no external value exists): the boundary treatment, the
+// time step rule, the residual norm and the tolerance anchor are readings,
+// pinned only by invariants.
 
 #include <omp.h>
 
