@@ -282,9 +282,15 @@ __global__ void __launch_bounds__(kBlock) k_q_from_U(int64_t n, double gamma,
 //   (d1^2 + eps^2 + 2 d1 d2) / (d1^2 + 2 d2^2 + d1 d2 + eps^2),
 // d2 = -(dx qx + dy qy)/2 the reconstruction increment toward the neighbour,
 // d1 the largest (d2 > 0) or smallest (d2 < 0) neighbour difference,
-// eps^2 = (K h)^3 with h the nearest-neighbour distance; phi clamped to >= 0.
-// The denominator is positive, so the minimum is tracked as a fraction and
-// divided once.  The limited derivatives phi * (qx, qy) go to qxl, qyl.
+// eps^2 = (K h)^3 with h the nearest-neighbour distance, and phi <= 1.
+// With A = d1^2 + eps^2 and d1 d2 >= 0 the ratio is >= 1 for |d2| <= |d1|/2
+// and falls with |d2| beyond (its derivative in d2 > 0 has the sign of
+// d1 A - 4 A d2 - 4 d1 d2^2 <= 0 there; d2 < 0 is the mirror image), so
+// min(1, ratio) is non-increasing in |d2| on each side: the minimum over the
+// neighbours is the ratio at the largest positive and the most negative d2.
+// The walk therefore only keeps the extremes of dx qx + dy qy, and the ratio
+// is formed twice per component.  The limited derivatives phi * (qx, qy) go
+// to qxl, qyl.
 //
 // LANES consecutive lanes share one point and split its neighbours; the LS
 // right-hand sides, the neighbour extrema and the limiter minimum are
@@ -295,6 +301,27 @@ __device__ __forceinline__ double lane_sum(double v) {
 #pragma unroll
     for (int o = LANES / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+
+// The limiter factor of one component from the walk's extremes tlo <= 0 <=
+// thi of dx qx + dy qy (d2 = -t/2): the ratio at d2 = -tlo/2 with d1 = dmax
+// and at d2 = -thi/2 with d1 = dmin, and 1.
+__device__ __forceinline__ double venkat_phi(double tlo, double thi, double dmax, double dmin,
+                                             double eps2) {
+    double phi = 1.0;
+    if (tlo < 0.0) {
+        const double d2 = -0.5 * tlo, d1 = dmax;
+        const double nu = d1 * d1 + eps2 + 2.0 * d1 * d2;
+        const double de = d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2;
+        phi = fmin(phi, nu / de);
+    }
+    if (thi > 0.0) {
+        const double d2 = -0.5 * thi, d1 = dmin;
+        const double nu = d1 * d1 + eps2 + 2.0 * d1 * d2;
+        const double de = d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2;
+        phi = fmin(phi, nu / de);
+    }
+    return fmax(phi, 0.0);
 }
 
 // Neighbour data of the q-derivative sums: position, q and (defect
@@ -410,7 +437,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad(
         }
     const double kh = K * L.w;
     const double eps2 = kh * kh * kh;
-    double fn[4] = {1, 1, 1, 1}, fd[4] = {1, 1, 1, 1};  // running minimum fn/fd
+    double tlo[4] = {0, 0, 0, 0}, thi[4] = {0, 0, 0, 0};  // extremes of dx qx + dy qy
     int k = 0;
     for (int32_t e = e0 + lane; e < e1; e += LANES, ++k) {
         double dx, dy;
@@ -425,48 +452,41 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad(
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const double d2 = -0.5 * (dx * gx[v] + dy * gy[v]);
-            if (d2 == 0.0) continue;
-            const double d1 = d2 > 0.0 ? dmax[v] : dmin[v];
-            const double nu = d1 * d1 + eps2 + 2.0 * d1 * d2;
-            const double de = d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2;
-            if (nu * fd[v] < fn[v] * de) {
-                fn[v] = nu;
-                fd[v] = de;
-            }
+            const double t = dx * gx[v] + dy * gy[v];
+            tlo[v] = fmin(tlo[v], t);
+            thi[v] = fmax(thi[v], t);
         }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int o = LANES / 2; o > 0; o >>= 1) {
-            const double on = __shfl_xor(fn[v], o, 64), od = __shfl_xor(fd[v], o, 64);
-            if (on * fd[v] < fn[v] * od) {
-                fn[v] = on;
-                fd[v] = od;
-            }
+            tlo[v] = fmin(tlo[v], __shfl_xor(tlo[v], o, 64));
+            thi[v] = fmax(thi[v], __shfl_xor(thi[v], o, 64));
         }
     if (lane == 0) {
         double phi[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) phi[v] = fmax(fn[v] / fd[v], 0.0);
+        for (int v = 0; v < 4; ++v) phi[v] = venkat_phi(tlo[v], thi[v], dmax[v], dmin[v], eps2);
         qxl[p] = {phi[0] * gx[0], phi[1] * gx[1], phi[2] * gx[2], phi[3] * gx[3]};
         qyl[p] = {phi[0] * gy[0], phi[1] * gy[1], phi[2] * gy[2], phi[3] * gy[3]};
     }
 }
 
 // The same q-derivative pass with the neighbour gathers staged in LDS.  Tile
-// b is the kTile consecutive points [b kTile, (b+1) kTile); the host lists
+// b is the kQTile consecutive points [b kQTile, (b+1) kQTile); the host lists
 // the union of their neighbours (tile_idx[tile_off[b] ...], sorted) and gives
 // every CSR entry its neighbour's position in that list (lnbr).  The block
 // first copies position, q (and the current derivatives) of the listed
 // points into LDS -- runs of consecutive indices, so mostly coalesced --
 // then every neighbour read of the sums comes from LDS: a point's 24
 // neighbour records are shared with the tile's other points instead of being
-// gathered 24 times from the caches.  Four lanes per point; the arithmetic
-// and summation order are those of k_qgrad<INNER, LIMIT, 4>, so the results
-// are the same bit for bit.
+// gathered 24 times from the caches.  Four lanes per point, each summing
+// its neighbours in the order of k_qgrad<INNER, LIMIT, 4>; the compiler may
+// contract the products differently, so the two forms can differ in the
+// last bits.
 static_assert(kQTile * 4 == kBlock, "a q-derivative tile is one point per four lanes");
+constexpr int kLnPre = 8;  // list positions per lane held in registers (a whole stencil of <= 32)
 
 template <bool INNER, bool LIMIT>
 __global__ void __launch_bounds__(kBlock, 4) k_qgrad_tiled(
@@ -487,6 +507,31 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad_tiled(
     double* s_q = s_y + hmax;                  // 4 components
     double* s_g = s_q + 4 * hmax;              // 8 components (x then y derivatives)
     const int tile = xcd_block(blockIdx.x, gridDim.x);
+    // the point's own data and its first list positions are requested before
+    // the staging, so their latency overlaps it
+    const int64_t p = (int64_t)tile * kQTile + threadIdx.x / 4;
+    const int lane = threadIdx.x % 4;
+    const bool inb = p < n;
+    D2 r0{};
+    D4 q0{}, gx0{}, gy0{}, L{};
+    int32_t e0 = 0, e1 = 0;
+    if (inb) {
+        r0 = xy[p];
+        q0 = q[p];
+        e0 = off[p];
+        e1 = off[p + 1];
+        L = geom[p].lsq;
+        if (INNER) {
+            gx0 = qx_in[p];
+            gy0 = qy_in[p];
+        }
+    }
+    int lpre[kLnPre];
+#pragma unroll
+    for (int k = 0; k < kLnPre; ++k) {
+        const int32_t e = e0 + lane + 4 * k;
+        lpre[k] = e < e1 ? lnbr[e] : 0;
+    }
     const int32_t h0 = tile_off[tile], nh = tile_off[tile + 1] - h0;
     for (int32_t k = threadIdx.x; k < nh; k += kBlock) {
         const int32_t i = tile_idx[h0 + k];
@@ -511,22 +556,13 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad_tiled(
         }
     }
     __syncthreads();
-    const int64_t p = (int64_t)tile * kQTile + threadIdx.x / 4;
-    const int lane = threadIdx.x % 4;
-    if (p >= n || !live(comp, active, p)) return;  // uniform over the lanes of a point
-    const D2 r0 = xy[p];
-    const D4 q0 = q[p];
+    if (!inb || !live(comp, active, p)) return;  // uniform over the lanes of a point
     const double qv[4] = {q0.x, q0.y, q0.z, q0.w};
-    D4 gx0{}, gy0{};
-    if (INNER) {
-        gx0 = qx_in[p];
-        gy0 = qy_in[p];
-    }
     double bx[4] = {0, 0, 0, 0}, by[4] = {0, 0, 0, 0};
     double dmax[4] = {0, 0, 0, 0}, dmin[4] = {0, 0, 0, 0};
-    const int32_t e0 = off[p], e1 = off[p + 1];
-    for (int32_t e = e0 + lane; e < e1; e += 4) {
-        const int li = lnbr[e];
+    // a lane takes entries e0 + lane, e0 + lane + 4, ... in order: the first
+    // kLnPre from registers, any further ones from memory
+    auto first_walk = [&](int li) {
         const double dx = s_x[li] - r0.x, dy = s_y[li] - r0.y;
         const D4 qi = {s_q[li], s_q[hmax + li], s_q[2 * hmax + li], s_q[3 * hmax + li]};
         double dq[4] = {qi.x - qv[0], qi.y - qv[1], qi.z - qv[2], qi.w - qv[3]};
@@ -551,13 +587,16 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad_tiled(
             bx[v] += dx * dq[v];
             by[v] += dy * dq[v];
         }
-    }
+    };
+#pragma unroll
+    for (int k = 0; k < kLnPre; ++k)
+        if (e0 + lane + 4 * k < e1) first_walk(lpre[k]);
+    for (int32_t e = e0 + lane + 4 * kLnPre; e < e1; e += 4) first_walk(lnbr[e]);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         bx[v] = lane_sum<4>(bx[v]);
         by[v] = lane_sum<4>(by[v]);
     }
-    const D4 L = geom[p].lsq;
     double gx[4], gy[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -578,37 +617,31 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad_tiled(
         }
     const double kh = K * L.w;
     const double eps2 = kh * kh * kh;
-    double fn[4] = {1, 1, 1, 1}, fd[4] = {1, 1, 1, 1};  // running minimum fn/fd
-    for (int32_t e = e0 + lane; e < e1; e += 4) {
-        const int li = lnbr[e];
+    double tlo[4] = {0, 0, 0, 0}, thi[4] = {0, 0, 0, 0};  // extremes of dx qx + dy qy
+    auto second_walk = [&](int li) {
         const double dx = s_x[li] - r0.x, dy = s_y[li] - r0.y;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const double d2 = -0.5 * (dx * gx[v] + dy * gy[v]);
-            if (d2 == 0.0) continue;
-            const double d1 = d2 > 0.0 ? dmax[v] : dmin[v];
-            const double nu = d1 * d1 + eps2 + 2.0 * d1 * d2;
-            const double de = d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + eps2;
-            if (nu * fd[v] < fn[v] * de) {
-                fn[v] = nu;
-                fd[v] = de;
-            }
+            const double t = dx * gx[v] + dy * gy[v];
+            tlo[v] = fmin(tlo[v], t);
+            thi[v] = fmax(thi[v], t);
         }
-    }
+    };
+#pragma unroll
+    for (int k = 0; k < kLnPre; ++k)
+        if (e0 + lane + 4 * k < e1) second_walk(lpre[k]);
+    for (int32_t e = e0 + lane + 4 * kLnPre; e < e1; e += 4) second_walk(lnbr[e]);
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int o = 2; o > 0; o >>= 1) {
-            const double on = __shfl_xor(fn[v], o, 64), od = __shfl_xor(fd[v], o, 64);
-            if (on * fd[v] < fn[v] * od) {
-                fn[v] = on;
-                fd[v] = od;
-            }
+            tlo[v] = fmin(tlo[v], __shfl_xor(tlo[v], o, 64));
+            thi[v] = fmax(thi[v], __shfl_xor(thi[v], o, 64));
         }
     if (lane == 0) {
         double phi[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) phi[v] = fmax(fn[v] / fd[v], 0.0);
+        for (int v = 0; v < 4; ++v) phi[v] = venkat_phi(tlo[v], thi[v], dmax[v], dmin[v], eps2);
         qxl[p] = {phi[0] * gx[0], phi[1] * gx[1], phi[2] * gx[2], phi[3] * gx[3]};
         qyl[p] = {phi[0] * gy[0], phi[1] * gy[1], phi[2] * gy[2], phi[3] * gy[3]};
     }
