@@ -22,6 +22,7 @@
 // order.  The per-point 4x4 algebra is not a dense contraction, so no matrix
 // cores are used.
 #include "lskum_internal.h"
+#include "lskum_math.h"
 
 #include <cmath>
 
@@ -82,7 +83,7 @@ __device__ __forceinline__ Prim prim_from_q(const D4& q, double inv_gm1, bool g1
     w.u1 = q.y * i2b;
     w.u2 = q.z * i2b;
     const double usq = w.u1 * w.u1 + w.u2 * w.u2;
-    const double e = exp(q.x + beta * usq);
+    const double e = exp_fast(q.x + beta * usq);
     const double r2 = r * r;
     w.rho = g14 ? e * (r2 * r2 * r) : e * exp(-inv_gm1 * log(beta));
     w.p = w.rho * i2b;
@@ -100,8 +101,8 @@ __device__ __forceinline__ void split_flux(const Prim& w, double dx, double dy, 
     (void)inv_gm1;
     const double ud = DIR == 0 ? w.u1 : (DIR == 1 ? w.u2 : w.u1 * dx + w.u2 * dy);
     const double S = ud * w.sb;
-    const double A = 0.5 * (1.0 + sg * erf(S));
-    const double B = exp(-(S * S)) * (0.5 * kInvSqrtPi) * w.isb;
+    const double A = 0.5 * (1.0 + sg * erf_fast(S));
+    const double B = exp_fast(-(S * S)) * (0.5 * kInvSqrtPi) * w.isb;
     const double mass = w.rho * (ud * A + sg * B);
     const double pA = w.p * A;
     G[0] = mass;
@@ -846,7 +847,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(
             const double sb = sqrt(beta);
             const double sx = u1 * sb, sy = u2 * sb;
             const D4 j0 = {rho, u1, u2, pr};
-            const D4 j2 = {erf(sx), exp(-(sx * sx)), erf(sy), exp(-(sy * sy))};
+            const D4 j2 = {erf_fast(sx), exp_fast(-(sx * sx)), erf_fast(sy), exp_fast(-(sy * sy))};
             const double a = sqrt(gamma * pr / rho);
             const PointGeom& G = geom[p];
             const double dt = cfl[comp ? comp[p] : 0] * G.lsq.w / (sqrt(usq) + a);
@@ -1125,7 +1126,7 @@ __device__ __forceinline__ void jvp_fluxdiff(const Lin<double>& L, double er, do
     W.sb = sqrt(W.beta);
     const double S = (W.u1 * dx + W.u2 * dy) * W.sb;
     double Ga[4], Gb[4];
-    flux_lin(W, erf(S), exp(-(S * S)), dx, dy, sg, inv_gm1, Ga);
+    flux_lin(W, erf_fast(S), exp_fast(-(S * S)), dx, dy, sg, inv_gm1, Ga);
     flux_lin(L, er, g, dx, dy, sg, inv_gm1, Gb);
 #pragma unroll
     for (int v = 0; v < 4; ++v) J[v] = Ga[v] - Gb[v];
@@ -1238,11 +1239,11 @@ __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<
             const double sg = (cd & kSwNegA) ? 1.0 : -1.0;
             if constexpr (MODE == 1) {
                 const double S = (L.u1 * t.x + L.u2 * t.y) * L.sb;
-                jvp_fluxdiff(L, erf(S), exp(-(S * S)), U[i], t.x, t.y, sg, dv, gamma,
+                jvp_fluxdiff(L, erf_fast(S), exp_fast(-(S * S)), U[i], t.x, t.y, sg, dv, gamma,
                              1.0 / (gamma - 1.0), J);
             } else {
                 const T S = (L.u1 * T(t.x) + L.u2 * T(t.y)) * L.sb;
-                jvp_exact<T>(L, erf(S), exp(-(S * S)), T(t.x), T(t.y), T(sg), dv, gm1, inv_gm1, J);
+                jvp_exact<T>(L, erf_k(S), exp_k(-(S * S)), T(t.x), T(t.y), T(sg), dv, gm1, inv_gm1, J);
             }
             const T wa = T(w.x);
 #pragma unroll
@@ -1252,11 +1253,11 @@ __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<
             const double sg = (cd & kSwNegB) ? 1.0 : -1.0;
             if constexpr (MODE == 1) {
                 const double S = (-L.u1 * t.y + L.u2 * t.x) * L.sb;
-                jvp_fluxdiff(L, erf(S), exp(-(S * S)), U[i], -t.y, t.x, sg, dv, gamma,
+                jvp_fluxdiff(L, erf_fast(S), exp_fast(-(S * S)), U[i], -t.y, t.x, sg, dv, gamma,
                              1.0 / (gamma - 1.0), J);
             } else {
                 const T S = (-L.u1 * T(t.y) + L.u2 * T(t.x)) * L.sb;
-                jvp_exact<T>(L, erf(S), exp(-(S * S)), T(-t.y), T(t.x), T(sg), dv, gm1, inv_gm1, J);
+                jvp_exact<T>(L, erf_k(S), exp_k(-(S * S)), T(-t.y), T(t.x), T(sg), dv, gm1, inv_gm1, J);
             }
             const T wb = T(w.y);
 #pragma unroll
