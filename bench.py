@@ -22,7 +22,6 @@ sample of the timed workload (all host cores).
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -124,8 +123,9 @@ def kernel_rooflines(cloud, colours, phases: dict) -> dict:
 
 
 def device_source_hash() -> str:
-    src = os.path.join(ROOT, "paper_2406_07441_amd", "csrc", "lskum_device.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    """The library's build hash: its sources, headers and compiler flags."""
+    from paper_2406_07441_amd import build
+    return build.source_hash()
 
 
 TRAFFIC_FILE = {"fp64": "traffic_2621440_fp64.md", "mixed": "traffic_2621440_mixed.md"}
