@@ -1221,7 +1221,8 @@ __global__ void __launch_bounds__(kBlock) k_sweep_weights(int64_t n,
 // the normal split (n- at a wall, n+ at a far-field outer point) in the frame
 // t of point p.
 template <class T, int MODE>
-__device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<T>& w, int32_t i,
+__device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2* __restrict__ frame, int32_t p,
+                                              const W2<T>& w, int32_t i,
                                               const Vec4<T>* __restrict__ jv0,
                                               const Vec4<T>* __restrict__ jv2,
                                               const D4* __restrict__ U,
@@ -1235,6 +1236,7 @@ __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<
     T J[4];
     if (cd & kSwWall) {
         // wall-frame directions: erf/exp at the neighbour state are formed here
+        const D2 t = frame[p];
         if (cd & kSwA) {
             const double sg = (cd & kSwNegA) ? 1.0 : -1.0;
             if constexpr (MODE == 1) {
@@ -1296,7 +1298,7 @@ __device__ __forceinline__ void sweep_contrib(uint8_t cd, const D2& t, const W2<
 // colour-sorted positions [start, start + count) and their lists one
 // contiguous block.
 template <class T, bool FWD, int MODE, int LANES>
-__global__ void __launch_bounds__(kBlock) k_sweep(
+__global__ void __launch_bounds__(kBlock, 5) k_sweep(
     int32_t start, int32_t count, const int32_t* __restrict__ col_perm,
     const D2* __restrict__ frame, const int8_t* __restrict__ type,
     const int32_t* __restrict__ loff, const int32_t* __restrict__ lidx,
@@ -1328,19 +1330,6 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
         w = lw[e];
         i = lidx[e];
     }
-    const int8_t ty = type[p];
-    const D2 t = frame[p];
-    T dg = T(1);
-    Vec4<T> own = {T(0), T(0), T(0), T(0)};
-    if (lane == 0) {  // used after the list walk; the division waits until then
-        dg = Dg[p];
-        if (FWD) {
-            const D4 r = R[p];
-            own = {T(r.x), T(r.y), T(r.z), T(r.w)};
-        } else {
-            own = dU[p];
-        }
-    }
     T acc[4] = {T(0), T(0), T(0), T(0)};
     while (e < e1) {
         // the next entry is requested before this one's neighbour data is used;
@@ -1350,7 +1339,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
         const uint8_t cdn = lcode[ec];
         const W2<T> wn = lw[ec];
         const int32_t in = lidx[ec];
-        sweep_contrib<T, MODE>(cd, t, w, i, jv0, jv2, U, dU, gamma, acc);
+        sweep_contrib<T, MODE>(cd, frame, p, w, i, jv0, jv2, U, dU, gamma, acc);
         cd = cdn;
         w = wn;
         i = in;
@@ -1361,6 +1350,17 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] += __shfl_xor(acc[v], o, 64);
     if (lane != 0) return;
+    // the point's own data is read after the walk, by the one lane that uses
+    // it: held through the walk it cost every lane ten registers
+    const int8_t ty = type[p];
+    const T dg = Dg[p];
+    Vec4<T> own;
+    if (FWD) {
+        const D4 r = R[p];
+        own = {T(r.x), T(r.y), T(r.z), T(r.w)};
+    } else {
+        own = dU[p];
+    }
     if (ty == kOuter && !farfield) {
         if (FWD) dU[p] = {T(0), T(0), T(0), T(0)};
         return;
@@ -1379,6 +1379,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(
         out[3] = own.w - acc[3] * iD;
     }
     if (ty == kWall) {
+        const D2 t = frame[p];
         const T nx = T(-t.y), ny = T(t.x);
         const T mn = out[1] * nx + out[2] * ny;
         out[1] -= mn * nx;
