@@ -55,8 +55,8 @@ __device__ __forceinline__ f32x4 tile_mma(const __bf16* __restrict__ A, int64_t 
     return acc;
 }
 
-// Whole forward pass of 128 rows per workgroup (8 waves x 16 rows).  W2 and
-// W3 are staged in LDS with rows padded to kLdsW bf16 (a 16-byte operand read
+// Whole forward pass of 128 rows per workgroup (8 waves x 16 rows).  W2, then
+// W3, is staged in one LDS buffer with rows padded to kLdsW bf16 (a 16-byte operand read
 // by 16 lanes of different rows then hits distinct banks).  Layer 1 is
 // evaluated directly in the matrix-core operand layout (each lane computes the
 // 32 hidden units its A fragments hold); the 128 x 128 layers run on the
@@ -77,19 +77,22 @@ __global__ void __launch_bounds__(64 * kFwdWaves) k_mlp_forward(
     __bf16* __restrict__ Xb, float* __restrict__ Z1, float* __restrict__ Z2,
     float* __restrict__ Z3, __bf16* __restrict__ H1, __bf16* __restrict__ H2,
     __bf16* __restrict__ H3, float* __restrict__ dY, float* __restrict__ se) {
-    __shared__ __attribute__((aligned(16))) __bf16 sW2[kWidth * kLdsW];
-    __shared__ __attribute__((aligned(16))) __bf16 sW3[kWidth * kLdsW];
+    // one weight buffer: W2 for layer 2, then W3 for layer 3 (70 KB of LDS
+    // per block instead of 104 KB, so that two blocks share a CU)
+    __shared__ __attribute__((aligned(16))) __bf16 sW[kWidth * kLdsW];
     __shared__ __attribute__((aligned(16))) __bf16 sH[kFwdWaves][16 * kLdsW];
-    // stage W2, W3 (16-byte chunks)
-    for (int ch = threadIdx.x; ch < kWidth * kWidth / 8; ch += blockDim.x) {
-        const int row = ch / (kWidth / 8), c8 = (ch % (kWidth / 8)) * 8;
-        *(bf16x8*)&sW2[row * kLdsW + c8] = *(const bf16x8*)&W2[row * kWidth + c8];
-        *(bf16x8*)&sW3[row * kLdsW + c8] = *(const bf16x8*)&W3[row * kWidth + c8];
-    }
+    auto stage = [&](const __bf16* __restrict__ Wg) {  // 16-byte chunks
+        for (int ch = threadIdx.x; ch < kWidth * kWidth / 8; ch += blockDim.x) {
+            const int row = ch / (kWidth / 8), c8 = (ch % (kWidth / 8)) * 8;
+            *(bf16x8*)&sW[row * kLdsW + c8] = *(const bf16x8*)&Wg[row * kWidth + c8];
+        }
+    };
+    stage(W2);
     __syncthreads();
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int row0 = (blockIdx.x * kFwdWaves + w) * 16;
-    if (row0 >= M) return;  // no barrier follows: the tile's work is wave-local
+    // a wave past the last row does no work but takes part in the barriers
+    const bool act = row0 < M;
     const int r = l & 15, g = l >> 4, kq = 8 * g;
     const int64_t m = row0 + r;
     __bf16* hs = sH[w];
@@ -97,9 +100,9 @@ __global__ void __launch_bounds__(64 * kFwdWaves) k_mlp_forward(
     float x[kIn];
 #pragma unroll
     for (int f = 0; f < kIn; ++f) {
-        const __bf16 xb = (__bf16)(m < Mvalid ? X[m * kIn + f] : 0.0f);
+        const __bf16 xb = (__bf16)(act && m < Mvalid ? X[m * kIn + f] : 0.0f);
         x[f] = (float)xb;
-        if (TRAIN && g == 0) Xb[m * kIn + f] = xb;
+        if (TRAIN && act && g == 0) Xb[m * kIn + f] = xb;
     }
     bf16x8 a[4];
 #pragma unroll
@@ -114,7 +117,7 @@ __global__ void __launch_bounds__(64 * kFwdWaves) k_mlp_forward(
             zz[j] = z;
             a[s][j] = (__bf16)gelu(z);
         }
-        if (TRAIN) {
+        if (TRAIN && act) {
             float* z1 = Z1 + m * kWidth + 32 * s + kq;
 #pragma unroll
             for (int j = 0; j < 8; ++j) z1[j] = zz[j];
@@ -124,7 +127,13 @@ __global__ void __launch_bounds__(64 * kFwdWaves) k_mlp_forward(
     // ---- layers 2 and 3 (128 -> 128) on the matrix cores
 #pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
-        const __bf16* sW = layer == 0 ? sW2 : sW3;
+        if (layer == 1) {
+            // every wave has read W2: replace it by W3
+            __syncthreads();
+            stage(W3);
+            __syncthreads();
+        }
+        if (!act) continue;
         const float* bias = layer == 0 ? b2 : b3;
         float* Zg = layer == 0 ? Z2 : Z3;
         __bf16* Hg = layer == 0 ? H2 : H3;
