@@ -289,12 +289,13 @@ def test_warm_start_gain_held_out(lk):
         assert r_fs.status == 0 and r_ws.status == 0
         # the residual check accepted the prediction: its residual is below the free stream's
         assert fb[0] == 0 and res[0] < 0.5 * r_fs.res_fs
-        assert r_ws.iters <= 1.02 * r_fs.iters
+        # measured 0.90, 0.77, 0.82 (training and solves are deterministic)
+        assert r_ws.iters <= 0.95 * r_fs.iters
         assert abs(r_ws.cl - r_fs.cl) <= 1e-6 and abs(r_ws.cd - r_fs.cd) <= 1e-6
         its_fs.append(r_fs.iters)
         its_ws.append(r_ws.iters)
         fs.close()
         ws.close()
-    assert sum(its_ws) < 0.97 * sum(its_fs)
+    assert sum(its_ws) < 0.88 * sum(its_fs)  # measured 0.83
     net.close()
     torch.cuda.synchronize()
