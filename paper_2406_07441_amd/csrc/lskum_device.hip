@@ -1001,6 +1001,8 @@ __global__ void __launch_bounds__(kBlock) k_norm_partial(const double* __restric
     const int c = blockIdx.x;
     if (!active[chunk_comp[c]]) return;  // uniform over the block
     double s = 0.0;
+    // unrolled so that the loads are issued together; the additions keep their order
+#pragma unroll 4
     for (int64_t p = chunk_start[c] + threadIdx.x; p < chunk_start[c + 1]; p += blockDim.x)
         s += rr[p];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
@@ -1025,6 +1027,8 @@ __global__ void __launch_bounds__(64) k_norm_comp(const double* __restrict__ par
     const int k = blockIdx.x;  // one wavefront per component
     if (!active[k]) return;
     double t = 0.0;
+    // unrolled so that the loads are issued together; the additions keep their order
+#pragma unroll 8
     for (int c = comp_chunk_off[k] + threadIdx.x; c < comp_chunk_off[k + 1]; c += 64) t += partial[c];
     for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
     if (threadIdx.x != 0) return;
