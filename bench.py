@@ -357,6 +357,7 @@ PEAK_BF16_TFLOPS = 2500.0
 WARM_SCALES = {
     "default": (32, 4, 20_000, 60_000, (640, 256)),
     "large": (64, 8, 40_000, 80_000, (1280, 500)),
+    "xlarge": (128, 16, 40_000, 80_000, (1280, 500)),
 }
 
 
