@@ -16,6 +16,8 @@
 // the library's polynomials and literal-coefficient versions of these about
 // 10% slower in the residual kernel.
 #pragma once
+// Defines __constant__ tables: include it from one translation unit only
+// (the solver kernels' lskum_device.hip).
 
 #include <hip/hip_runtime.h>
 
