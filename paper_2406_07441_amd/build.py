@@ -66,9 +66,9 @@ def build(verbose: bool = False) -> str:
                 print(" ".join(cmd), flush=True)
             objs.append(obj)
             procs.append((cmd, subprocess.Popen(cmd)))
-        for cmd, pr in procs:
-            if pr.wait() != 0:
-                raise subprocess.CalledProcessError(pr.returncode, cmd)
+        failed = [(cmd, pr.returncode) for cmd, pr in procs if pr.wait() != 0]
+        if failed:  # every compile has ended before the objects' folder goes
+            raise subprocess.CalledProcessError(failed[0][1], failed[0][0])
         cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
         if verbose:
             print(" ".join(cmd), flush=True)
