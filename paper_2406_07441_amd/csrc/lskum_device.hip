@@ -1080,13 +1080,14 @@ __device__ __forceinline__ void jvp_exact(const Lin<T>& L, T er, T g, T dx, T dy
     const T bd = (rd - T(2) * L.beta * pd) * (T(0.5) * L.ip);
     const T ud = L.u1 * dx + L.u2 * dy;
     const T udd = u1d * dx + u2d * dy;
-    const T isb = L.sb / L.beta;  // 1/sqrt(beta)
+    const T ib = T(2) * L.p * L.irho;  // 1/beta = 2p/rho, without a division
+    const T isb = L.sb * ib;           // 1/sqrt(beta)
     const T S = ud * L.sb;
     const T Sd = udd * L.sb + T(0.5) * ud * bd * isb;
     const T A = T(0.5) * (T(1) + sg * er);
     const T Ad = sg * g * Sd * T(kInvSqrtPi);
     const T B = g * T(0.5 * kInvSqrtPi) * isb;
-    const T Bd = B * (T(-2) * S * Sd - T(0.5) * bd / L.beta);
+    const T Bd = B * (T(-2) * S * Sd - T(0.5) * bd * ib);
     const T F = ud * A + sg * B;
     const T Fd = udd * A + ud * Ad + sg * Bd;
     const T rhoE = L.p * inv_gm1 + T(0.5) * L.rho * usq;
