@@ -503,7 +503,7 @@ def mlp_profile_run(lk) -> dict:
     return out
 
 
-def cpu_baseline(cloud, mach, aoa, min_seconds: float = 10.0, max_iters: int = 4):
+def cpu_baseline(cloud, mach, aoa, min_seconds: float = 10.0, max_iters: int = 8):
     """The CPU oracle (serial arithmetic, per-point loops and the points of a
     colour over OpenMP threads, results independent of the thread count) on
     the timed workload: whole iterations from the free-stream start until
