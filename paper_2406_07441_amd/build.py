@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
            ("lskum_device.hip", "lskum_api.hip", "lskum_mlp.hip", "lskum_mlp_api.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f) for f in
-           ("lskum_internal.h", "lskum_math.h", "lskum_math_coef.h", "lskum_mlp.h")] + \
+           ("lskum_internal.h", "lskum_math.h", "lskum_math_coef.h", "lskum_mlp.h",
+            "lskum_tiles.h")] + \
           [os.path.join(os.path.dirname(HERE), "include", "lskum.h")]
 LIB = os.path.join(HERE, "liblskum.so")
 

@@ -10,6 +10,7 @@
 // it, reading back only a few bytes of bookkeeping between replays.
 #include "../../include/lskum.h"
 #include "lskum_internal.h"
+#include "lskum_tiles.h"
 
 #include <algorithm>
 #include <chrono>
@@ -63,7 +64,7 @@ void free_cloud(lskum::Cloud& c) {
                     c.lo_wf, c.up_wf,
                     c.comp_off, c.wall_off, c.comp_inv_active,
                     c.comp_orient, c.chunk_start, c.chunk_comp, c.comp_chunk_off,
-                    c.tile_off, c.tile_idx, c.lnbr};
+                    c.tile_pts, c.tile_off, c.tile_idx, c.lnbr};
     for (void* p : ptrs) (void)hipFree(p);
     c = lskum::Cloud{};
 }
@@ -210,55 +211,13 @@ int upload_cloud(lskum::Cloud& c) {
 
     // wall and outer points keep their frame; outer points use it with the
     // kinetic far field only, which needs a unit tangent at every one of them
-    // q-derivative tiles: the union of each tile's neighbours, sorted, and
-    // each CSR entry's neighbour as a position in it (linear time: a stamp per
-    // point marks the tile that listed it last)
-    std::vector<int32_t> tile_off, tile_idx;
-    std::vector<uint16_t> lnbr;
-    {
-        const int64_t nt = (n + lskum::kQTile - 1) / lskum::kQTile;
-        std::vector<int32_t> stamp(n, -1), pos(n, 0), list;
-        tile_off.reserve(nt + 1);
-        tile_off.push_back(0);
-        lnbr.resize(nnz);
-        bool ok = true;
-        int32_t hmax = 0;
-        for (int64_t b = 0; b < nt && ok; ++b) {
-            const int64_t p0 = b * lskum::kQTile, p1 = std::min<int64_t>(n, p0 + lskum::kQTile);
-            list.clear();
-            for (int32_t e = c.h_off[p0]; e < c.h_off[p1]; ++e) {
-                const int32_t i = c.h_idx[e];
-                if (stamp[i] != (int32_t)b) {
-                    stamp[i] = (int32_t)b;
-                    list.push_back(i);
-                }
-            }
-            if ((int64_t)list.size() > lskum::kQTileMax) {
-                ok = false;
-                break;
-            }
-            std::sort(list.begin(), list.end());
-            for (size_t k = 0; k < list.size(); ++k) pos[list[k]] = (int32_t)k;
-            for (int32_t e = c.h_off[p0]; e < c.h_off[p1]; ++e) lnbr[e] = (uint16_t)pos[c.h_idx[e]];
-            tile_idx.insert(tile_idx.end(), list.begin(), list.end());
-            tile_off.push_back((int32_t)tile_idx.size());
-            hmax = std::max(hmax, (int32_t)list.size());
-        }
-        // every entry's position must name its own neighbour
-        for (int64_t b = 0; b < nt && ok; ++b) {
-            const int64_t p0 = b * lskum::kQTile, p1 = std::min<int64_t>(n, p0 + lskum::kQTile);
-            for (int32_t e = c.h_off[p0]; e < c.h_off[p1] && ok; ++e)
-                ok = lnbr[e] < tile_off[b + 1] - tile_off[b] &&
-                     tile_idx[tile_off[b] + lnbr[e]] == c.h_idx[e];
-        }
-        c.ntile = ok ? (int32_t)nt : 0;
-        c.tile_hmax = ok ? hmax : 0;
-        if (!ok) {
-            tile_off.clear();
-            tile_idx.clear();
-            lnbr.clear();
-        }
-    }
+    // q-derivative tiles: runs of consecutive points or blocks of rows,
+    // whichever stages fewer points
+    lskum::TileSet tiles =
+        lskum::build_tiles(n, c.h_off.data(), c.h_idx.data(), c.h_comp_off, lskum::kQTile,
+                           lskum::kQTileJ, lskum::kQTileK, lskum::kQTileMax);
+    c.ntile = (int32_t)tiles.ntile;
+    c.tile_hmax = tiles.hmax;
 
     std::vector<lskum::D2> hxy(n), hfr(n);
     c.outer_frames = true;
@@ -289,9 +248,10 @@ int upload_cloud(lskum::Cloud& c) {
     chk(dalloc(&c.wall_list, wall.size()));
     chk(dalloc(&c.geom, n));
     if (c.ntile) {
-        chk(dalloc(&c.tile_off, tile_off.size()));
-        chk(dalloc(&c.tile_idx, std::max<size_t>(1, tile_idx.size())));
-        chk(dalloc(&c.lnbr, std::max<size_t>(1, lnbr.size())));
+        chk(dalloc(&c.tile_pts, tiles.pts.size()));
+        chk(dalloc(&c.tile_off, tiles.off.size()));
+        chk(dalloc(&c.tile_idx, std::max<size_t>(1, tiles.list.size())));
+        chk(dalloc(&c.lnbr, std::max<size_t>(1, tiles.lnbr.size())));
     }
     chk(dalloc(&c.lo_off, n + 1));
     chk(dalloc(&c.up_off, n + 1));
@@ -338,9 +298,10 @@ int upload_cloud(lskum::Cloud& c) {
         chk(upload(c.colour, c.h_colour.data(), n));
         chk(upload(c.col_perm, perm.data(), n));
         if (c.ntile) {
-            chk(upload(c.tile_off, tile_off.data(), tile_off.size()));
-            chk(upload(c.tile_idx, tile_idx.data(), tile_idx.size()));
-            chk(upload(c.lnbr, lnbr.data(), lnbr.size()));
+            chk(upload(c.tile_pts, tiles.pts.data(), tiles.pts.size()));
+            chk(upload(c.tile_off, tiles.off.data(), tiles.off.size()));
+            chk(upload(c.tile_idx, tiles.list.data(), tiles.list.size()));
+            chk(upload(c.lnbr, tiles.lnbr.data(), tiles.lnbr.size()));
         }
         chk(upload(c.lo_off, lo_off.data(), n + 1));
         chk(upload(c.up_off, up_off.data(), n + 1));

@@ -475,9 +475,11 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad(
 }
 
 // The same q-derivative pass with the neighbour gathers staged in LDS.  Tile
-// b is the kQTile consecutive points [b kQTile, (b+1) kQTile); the host lists
-// the union of their neighbours (tile_idx[tile_off[b] ...], sorted) and gives
-// every CSR entry its neighbour's position in that list (lnbr).  The block
+// b holds the points tile_pts[b kQTile ...] (-1 past its end: kQTile
+// consecutive points, or a block of kQTileJ points by kQTileK rows of a cloud
+// stored row by row); the host lists the union of their neighbours
+// (tile_idx[tile_off[b] ...], sorted) and gives every CSR entry its
+// neighbour's position in that list (lnbr).  The block
 // first copies position, q (and the current derivatives) of the listed
 // points into LDS -- runs of consecutive indices, so mostly coalesced --
 // then every neighbour read of the sums comes from LDS: a point's 24
@@ -491,8 +493,9 @@ constexpr int kLnPre = 8;  // list positions per lane held in registers (a whole
 
 template <bool INNER, bool LIMIT>
 __global__ void __launch_bounds__(kBlock, 4) k_qgrad_tiled(
-    int64_t n, double K, const D2* __restrict__ xy, const int32_t* __restrict__ off,
-    const uint16_t* __restrict__ lnbr, const int32_t* __restrict__ tile_off,
+    double K, const D2* __restrict__ xy, const int32_t* __restrict__ off,
+    const int32_t* __restrict__ tile_pts, const uint16_t* __restrict__ lnbr,
+    const int32_t* __restrict__ tile_off,
     const int32_t* __restrict__ tile_idx, int32_t hmax, const PointGeom* __restrict__ geom,
     const int32_t* __restrict__ comp, const int32_t* __restrict__ active,
     const D4* __restrict__ q, const D4* __restrict__ qx_in, const D4* __restrict__ qy_in,
@@ -510,9 +513,9 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad_tiled(
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     // the point's own data and its first list positions are requested before
     // the staging, so their latency overlaps it
-    const int64_t p = (int64_t)tile * kQTile + threadIdx.x / 4;
+    const int64_t p = tile_pts[(int64_t)tile * kQTile + threadIdx.x / 4];
     const int lane = threadIdx.x % 4;
-    const bool inb = p < n;
+    const bool inb = p >= 0;
     D2 r0{};
     D4 q0{}, gx0{}, gy0{}, L{};
     int32_t e0 = 0, e1 = 0;
@@ -1606,25 +1609,27 @@ static void qgrad_tiled(State& s) {
     const size_t lds0 = (size_t)c.tile_hmax * 6 * sizeof(double);
     const size_t lds1 = (size_t)c.tile_hmax * 14 * sizeof(double);
     if (m == 0 && lim)
-        hipLaunchKernelGGL((k_qgrad_tiled<false, true>), g, b, lds0, s.stream, c.n, K, c.xy, c.off,
-                           c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom, c.comp, s.active,
-                           s.q, nullptr, nullptr, s.qx[0], s.qy[0], s.qxl, s.qyl);
+        hipLaunchKernelGGL((k_qgrad_tiled<false, true>), g, b, lds0, s.stream, K, c.xy, c.off,
+                           c.tile_pts, c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom,
+                           c.comp, s.active, s.q, nullptr, nullptr, s.qx[0], s.qy[0], s.qxl,
+                           s.qyl);
     else
-        hipLaunchKernelGGL((k_qgrad_tiled<false, false>), g, b, lds0, s.stream, c.n, K, c.xy,
-                           c.off, c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom, c.comp,
-                           s.active, s.q, nullptr, nullptr, s.qx[0], s.qy[0], nullptr, nullptr);
+        hipLaunchKernelGGL((k_qgrad_tiled<false, false>), g, b, lds0, s.stream, K, c.xy, c.off,
+                           c.tile_pts, c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom,
+                           c.comp, s.active, s.q, nullptr, nullptr, s.qx[0], s.qy[0], nullptr,
+                           nullptr);
     int cur = 0;
     for (int it = 0; it < m; ++it) {
         if (it == m - 1 && lim)
-            hipLaunchKernelGGL((k_qgrad_tiled<true, true>), g, b, lds1, s.stream, c.n, K, c.xy,
-                               c.off, c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom, c.comp,
-                               s.active, s.q, s.qx[cur], s.qy[cur], s.qx[1 - cur], s.qy[1 - cur],
-                               s.qxl, s.qyl);
+            hipLaunchKernelGGL((k_qgrad_tiled<true, true>), g, b, lds1, s.stream, K, c.xy, c.off,
+                               c.tile_pts, c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom,
+                               c.comp, s.active, s.q, s.qx[cur], s.qy[cur], s.qx[1 - cur],
+                               s.qy[1 - cur], s.qxl, s.qyl);
         else
-            hipLaunchKernelGGL((k_qgrad_tiled<true, false>), g, b, lds1, s.stream, c.n, K, c.xy,
-                               c.off, c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom, c.comp,
-                               s.active, s.q, s.qx[cur], s.qy[cur], s.qx[1 - cur], s.qy[1 - cur],
-                               nullptr, nullptr);
+            hipLaunchKernelGGL((k_qgrad_tiled<true, false>), g, b, lds1, s.stream, K, c.xy, c.off,
+                               c.tile_pts, c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom,
+                               c.comp, s.active, s.q, s.qx[cur], s.qy[cur], s.qx[1 - cur],
+                               s.qy[1 - cur], nullptr, nullptr);
         cur = 1 - cur;
     }
     s.qsel = cur;

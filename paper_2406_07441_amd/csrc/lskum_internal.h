@@ -48,10 +48,14 @@ struct alignas(32) PointGeom {
 constexpr uint8_t kSwA = 1, kSwNegA = 2, kSwB = 4, kSwNegB = 8, kSwWall = 16;
 
 // q-derivative tiles: points per tile (one per four lanes of a 256-thread
-// block) and the longest neighbour list a tile may stage in LDS (the inner
-// pass holds 112 bytes per listed point: at most 56 KiB)
+// block), the block shape for clouds stored row by row (kQTileJ points by
+// kQTileK rows), and the longest neighbour list a tile may stage in LDS (the
+// inner pass holds 112 bytes per listed point: at most 56 KiB)
 constexpr int kQTile = 64;
+constexpr int kQTileJ = 16;
+constexpr int kQTileK = 4;
 constexpr int kQTileMax = 512;
+static_assert(kQTileJ * kQTileK <= kQTile, "a row block fits one tile");
 
 struct Cloud {
     int device = 0;
@@ -112,13 +116,16 @@ struct Cloud {
     std::vector<int8_t> h_type;
     std::vector<int32_t> h_off, h_idx;
     PointGeom* geom = nullptr;
-    // LDS tiles of the q-derivative passes: tile b is the kQTile points
-    // [b kQTile, (b+1) kQTile); tile_idx[tile_off[b] .. tile_off[b+1]) lists the
-    // union of their neighbours (sorted) and lnbr[e] gives CSR entry e's
-    // neighbour as a position in its point's tile list.  ntile = 0 when some
-    // tile's list is longer than kQTileMax (the passes then gather directly).
+    // LDS tiles of the q-derivative passes (lskum_tiles.h): tile b holds the
+    // points tile_pts[b kQTile ...] (-1 past its end), either kQTile
+    // consecutive points or a block of rows; tile_idx[tile_off[b] ..
+    // tile_off[b+1]) lists the union of their neighbours (sorted) and lnbr[e]
+    // gives CSR entry e's neighbour as a position in its point's tile list.
+    // ntile = 0 when some tile's list is longer than kQTileMax (the passes
+    // then gather directly).
     int32_t ntile = 0;
     int32_t tile_hmax = 0;              // longest tile list
+    int32_t* tile_pts = nullptr;        // device, ntile * kQTile
     int32_t* tile_off = nullptr;        // device, ntile + 1
     int32_t* tile_idx = nullptr;        // device
     uint16_t* lnbr = nullptr;           // device, nnz
