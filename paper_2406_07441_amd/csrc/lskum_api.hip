@@ -979,7 +979,7 @@ int lskum_q_derivatives(lskum_state* so, double* qx, double* qy, int on_device) 
     if (!so || !qx || !qy) return fail(LSKUM_ERR_ARG, "NULL argument");
     lskum::State& s = so->s;
     HIPCHK(lskum::launch_reset_components(s));
-    HIPCHK(lskum::launch_q_derivatives(s));
+    HIPCHK(lskum::launch_q_derivatives(s, true));
     if (int r = copy_field_out(s, s.qx[s.qsel], 0, s.cloud->n, qx, on_device)) return r;
     return copy_field_out(s, s.qy[s.qsel], 0, s.cloud->n, qy, on_device);
 }

@@ -291,7 +291,8 @@ __global__ void __launch_bounds__(kBlock) k_q_from_U(int64_t n, double gamma,
 // neighbours is the ratio at the largest positive and the most negative d2.
 // The walk therefore only keeps the extremes of dx qx + dy qy, and the ratio
 // is formed twice per component.  The limited derivatives phi * (qx, qy) go
-// to qxl, qyl.
+// to qxl, qyl; the unlimited ones of that pass to qx_out, qy_out only when
+// those are given (a query of the derivatives: the residual reads qxl, qyl).
 //
 // LANES consecutive lanes share one point and split its neighbours; the LS
 // right-hand sides, the neighbour extrema and the limiter minimum are
@@ -424,7 +425,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad(
         gx[v] = L.x * bx[v] + L.y * by[v];
         gy[v] = L.y * bx[v] + L.z * by[v];
     }
-    if (lane == 0) {
+    if (lane == 0 && (!LIMIT || qx_out)) {  // the limited pass writes them on request only
         qx_out[p] = {gx[0], gx[1], gx[2], gx[3]};
         qy_out[p] = {gy[0], gy[1], gy[2], gy[3]};
     }
@@ -607,7 +608,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_qgrad_tiled(
         gx[v] = L.x * bx[v] + L.y * by[v];
         gy[v] = L.y * bx[v] + L.z * by[v];
     }
-    if (lane == 0) {
+    if (lane == 0 && (!LIMIT || qx_out)) {  // the limited pass writes them on request only
         qx_out[p] = {gx[0], gx[1], gx[2], gx[3]};
         qy_out[p] = {gy[0], gy[1], gy[2], gy[3]};
     }
@@ -1568,7 +1569,7 @@ hipError_t launch_q_from_U(State& s) {
 }
 
 template <int LANES>
-static void qgrad_lanes(State& s) {
+static void qgrad_lanes(State& s, bool keep) {
     const Cloud& c = *s.cloud;
     const dim3 g(grid_for(c.n * LANES)), b(kBlock);
     const double K = s.prm.limiter_k;
@@ -1577,8 +1578,8 @@ static void qgrad_lanes(State& s) {
     // pass 0 (first order), then m inner passes; the limiter rides on the last
     if (m == 0 && lim)
         hipLaunchKernelGGL((k_qgrad<false, true, LANES>), g, b, 0, s.stream, c.n, K, c.xy, c.off,
-                           c.idx, c.geom, c.comp, s.active, s.q, nullptr, nullptr, s.qx[0],
-                           s.qy[0], s.qxl, s.qyl);
+                           c.idx, c.geom, c.comp, s.active, s.q, nullptr, nullptr,
+                           keep ? s.qx[0] : nullptr, keep ? s.qy[0] : nullptr, s.qxl, s.qyl);
     else
         hipLaunchKernelGGL((k_qgrad<false, false, LANES>), g, b, 0, s.stream, c.n, K, c.xy, c.off,
                            c.idx, c.geom, c.comp, s.active, s.q, nullptr, nullptr, s.qx[0],
@@ -1588,7 +1589,8 @@ static void qgrad_lanes(State& s) {
         if (it == m - 1 && lim)
             hipLaunchKernelGGL((k_qgrad<true, true, LANES>), g, b, 0, s.stream, c.n, K, c.xy,
                                c.off, c.idx, c.geom, c.comp, s.active, s.q, s.qx[cur], s.qy[cur],
-                               s.qx[1 - cur], s.qy[1 - cur], s.qxl, s.qyl);
+                               keep ? s.qx[1 - cur] : nullptr, keep ? s.qy[1 - cur] : nullptr,
+                               s.qxl, s.qyl);
         else
             hipLaunchKernelGGL((k_qgrad<true, false, LANES>), g, b, 0, s.stream, c.n, K, c.xy,
                                c.off, c.idx, c.geom, c.comp, s.active, s.q, s.qx[cur], s.qy[cur],
@@ -1600,7 +1602,7 @@ static void qgrad_lanes(State& s) {
 
 // Tiled passes (LDS-staged neighbours): block = tile, dynamic LDS sized by
 // the cloud's largest tile neighbour list.
-static void qgrad_tiled(State& s) {
+static void qgrad_tiled(State& s, bool keep) {
     const Cloud& c = *s.cloud;
     const dim3 g((unsigned)c.ntile), b(kBlock);
     const double K = s.prm.limiter_k;
@@ -1611,8 +1613,8 @@ static void qgrad_tiled(State& s) {
     if (m == 0 && lim)
         hipLaunchKernelGGL((k_qgrad_tiled<false, true>), g, b, lds0, s.stream, K, c.xy, c.off,
                            c.tile_pts, c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom,
-                           c.comp, s.active, s.q, nullptr, nullptr, s.qx[0], s.qy[0], s.qxl,
-                           s.qyl);
+                           c.comp, s.active, s.q, nullptr, nullptr, keep ? s.qx[0] : nullptr,
+                           keep ? s.qy[0] : nullptr, s.qxl, s.qyl);
     else
         hipLaunchKernelGGL((k_qgrad_tiled<false, false>), g, b, lds0, s.stream, K, c.xy, c.off,
                            c.tile_pts, c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom,
@@ -1623,8 +1625,9 @@ static void qgrad_tiled(State& s) {
         if (it == m - 1 && lim)
             hipLaunchKernelGGL((k_qgrad_tiled<true, true>), g, b, lds1, s.stream, K, c.xy, c.off,
                                c.tile_pts, c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom,
-                               c.comp, s.active, s.q, s.qx[cur], s.qy[cur], s.qx[1 - cur],
-                               s.qy[1 - cur], s.qxl, s.qyl);
+                               c.comp, s.active, s.q, s.qx[cur], s.qy[cur],
+                               keep ? s.qx[1 - cur] : nullptr, keep ? s.qy[1 - cur] : nullptr,
+                               s.qxl, s.qyl);
         else
             hipLaunchKernelGGL((k_qgrad_tiled<true, false>), g, b, lds1, s.stream, K, c.xy, c.off,
                                c.tile_pts, c.lnbr, c.tile_off, c.tile_idx, c.tile_hmax, c.geom,
@@ -1635,16 +1638,16 @@ static void qgrad_tiled(State& s) {
     s.qsel = cur;
 }
 
-hipError_t launch_q_derivatives(State& s) {
+hipError_t launch_q_derivatives(State& s, bool keep_unlimited) {
     if (s.qgrad_tiled && s.cloud->ntile > 0) {
-        qgrad_tiled(s);
+        qgrad_tiled(s, keep_unlimited);
         return hipGetLastError();
     }
     switch (s.qgrad_lanes) {
-        case 1: qgrad_lanes<1>(s); break;
-        case 2: qgrad_lanes<2>(s); break;
-        case 8: qgrad_lanes<8>(s); break;
-        default: qgrad_lanes<4>(s); break;
+        case 1: qgrad_lanes<1>(s, keep_unlimited); break;
+        case 2: qgrad_lanes<2>(s, keep_unlimited); break;
+        case 8: qgrad_lanes<8>(s, keep_unlimited); break;
+        default: qgrad_lanes<4>(s, keep_unlimited); break;
     }
     return hipGetLastError();
 }

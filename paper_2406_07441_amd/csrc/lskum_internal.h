@@ -227,7 +227,10 @@ hipError_t launch_precompute(Cloud& c, hipStream_t st);
 hipError_t launch_sweep_weights(Cloud& c, hipStream_t st);
 hipError_t launch_free_stream(State& s);
 hipError_t launch_q_from_U(State& s);
-hipError_t launch_q_derivatives(State& s);  // includes the limiter when on
+// q-derivative passes, with the limiter when on.  With the limiter the last
+// pass writes only the limited derivatives (all the residual reads) unless
+// keep_unlimited asks for the unlimited ones too (in qx/qy[qsel]).
+hipError_t launch_q_derivatives(State& s, bool keep_unlimited = false);
 // residual + time step/diagonal + sweep intermediates (per-point R_rho^2)
 // in_step: part of an implicit step (the kernel then also does the forward
 // sweep's first colour phase); false for a residual evaluation alone
