@@ -126,9 +126,12 @@ typedef struct {
                                points are then swept and updated like the
                                others and stay out of the residual norm */
     int32_t qgrad_lanes;    /* q-derivative kernels: 0 = library choice (each
-                               64-point tile stages its points' neighbours in
-                               LDS, four lanes per point, when every tile's
-                               neighbour list fits; direct gathers otherwise);
+                               64-point tile -- 16 points by 4 rows when the
+                               points are stored row by row, else 64
+                               consecutive points -- stages its points'
+                               neighbours in LDS, four lanes per point, when
+                               every tile's neighbour list fits; direct
+                               gathers otherwise);
                                1, 2, 4, 8 = direct gathers with that many
                                lanes per point (the same sums; the forms can
                                differ in the last bits). */
